@@ -1,0 +1,92 @@
+"""Seeded synthetic QUBO inputs shared by the tests, the smoke check and the benchmark.
+
+This module only draws random numbers and shapes them into instances; it holds
+none of the solver's arithmetic.  The paper benchmarks on "a uniformly random
+matrix" (Sec. V-C); these generators produce that workload:
+
+* ``uniform_int(n, lo, hi, seed)``: upper-triangular int32 Q including the
+  diagonal, entries i.i.d. uniform integers in [lo, hi], lower triangle zero.
+* ``normal_fp32(n, seed)``: upper-triangular float32 Q with N(0, 1) entries.
+* ``planted(n, lo, hi, seed)``: ``uniform_int`` whose diagonal is rewritten so a
+  seeded random x* is the unique ground state (each diagonal entry is
+  -(R_i + 1) where x*_i = 1 and +(R_i + 1) where x*_i = 0, with R_i the sum of
+  |Q_ij| + |Q_ji| over j != i; any single flip towards x* then lowers the
+  energy by at least 1 whatever the other bits are).
+* ``batch(count, n_lo, n_hi, seed, kind)``: many instances of uneven size.
+* ``poisson_requests(...)``: arrival times and instances for the serving mix.
+
+All draws use ``numpy.random.default_rng(seed)`` (PCG64).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def uniform_int(n: int, lo: int, hi: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    Q = rng.integers(lo, hi, size=(n, n), endpoint=True, dtype=np.int64)
+    return np.triu(Q).astype(np.int32)
+
+
+def normal_fp32(n: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    Q = rng.standard_normal(size=(n, n), dtype=np.float64).astype(np.float32)
+    return np.triu(Q)
+
+
+def planted(n: int, lo: int, hi: int, seed: int):
+    """Return (Q, xstar) with xstar the unique ground state of Q."""
+    rng = np.random.default_rng(seed)
+    Q = np.triu(rng.integers(lo, hi, size=(n, n), endpoint=True, dtype=np.int64))
+    xstar = rng.integers(0, 2, size=n, dtype=np.int64)
+    A = np.abs(Q)
+    np.fill_diagonal(A, 0)
+    R = A.sum(axis=1) + A.sum(axis=0)
+    diag = np.where(xstar == 1, -(R + 1), R + 1)
+    np.fill_diagonal(Q, diag)
+    if np.abs(Q).max() > 2**31 - 1:
+        raise ValueError("planted instance does not fit int32")
+    return Q.astype(np.int32), xstar
+
+
+def full_int(n: int, lo: int, hi: int, seed: int) -> np.ndarray:
+    """Dense int32 Q with BOTH triangles populated (exercises the fold)."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(lo, hi, size=(n, n), endpoint=True, dtype=np.int64).astype(np.int32)
+
+
+def batch(count: int, n_lo: int, n_hi: int, seed: int, kind: str = "int",
+          lo: int = -100, hi: int = 100):
+    """``count`` instances with n ~ U{n_lo..n_hi}; kind 'int' (U[lo,hi]) or 'fp32' (N(0,1))."""
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(n_lo, n_hi, size=count, endpoint=True)
+    seeds = rng.integers(0, 2**62, size=count)
+    out = []
+    for n, s in zip(ns, seeds):
+        if kind == "int":
+            out.append(uniform_int(int(n), lo, hi, int(s)))
+        elif kind == "fp32":
+            out.append(normal_fp32(int(n), int(s)))
+        else:
+            raise ValueError(kind)
+    return out
+
+
+def poisson_requests(count: int, rate_hz: float, n_lo: int, n_hi: int, seed: int,
+                     int_fraction: float = 0.8, lo: int = -100, hi: int = 100):
+    """Serving mix: (arrival_s, Q) pairs with Poisson arrivals at ``rate_hz``.
+
+    n ~ U{n_lo..n_hi}; an ``int_fraction`` share is int32 U[lo, hi], the rest
+    float32 N(0, 1).
+    """
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate_hz, size=count)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    ns = rng.integers(n_lo, n_hi, size=count, endpoint=True)
+    is_int = rng.random(size=count) < int_fraction
+    seeds = rng.integers(0, 2**62, size=count)
+    out = []
+    for t, n, ii, s in zip(arrivals, ns, is_int, seeds):
+        Q = uniform_int(int(n), lo, hi, int(s)) if ii else normal_fp32(int(n), int(s))
+        out.append((float(t), Q))
+    return out
