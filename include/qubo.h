@@ -1,0 +1,186 @@
+/*
+ * qubo.h -- C ABI of the MI355X exhaustive dense-QUBO solver.
+ *
+ * The solver minimises the QUBO objective E(x) = sum_{i,j} Q_ij x_i x_j over
+ * all 2^n binary states x (paper: Introduction; Sec. II-A, Eq. total_energy)
+ * by the prefix-suffix decomposition of Sec. II-A/II-C (Eqs.
+ * energy_decomposition and chunk_energy_final) and the Gray-code walk of
+ * Sec. III-B (Eq. incremental_update, Alg. 2), on int32 vector ALUs of a
+ * gfx950 GPU.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Q is a dense row-major n x n matrix, int32 (QUBO_INT32) or float32
+ *   (QUBO_FP32).  E sums over ALL i, j, so an upper-triangular Q (the paper's
+ *   Sec. II-A form) is the special case with a zero lower triangle; any lower
+ *   entries are folded onto the upper triangle.
+ * - A state is identified by its "index": its row in the lexicographic state
+ *   matrix U_N of Sec. II-B, whose column 0 is the most significant bit:
+ *       x_i = (index >> (n - 1 - i)) & 1.
+ * - The answer is the lexicographic minimum of (E, index): the minimum energy
+ *   and, among the states reaching it, the LOWEST index.  (Alg. 2 keeps the
+ *   first state visited in Gray order; this library resolves ties by index.)
+ * - 1 <= n <= 60.
+ * - int32 input: solved exactly.  The library folds T_ii = Q_ii,
+ *   T_ij = Q_ij + Q_ji (i < j) and requires sum_{i<=j} |T_ij| <= 2^30 - 1,
+ *   which proves every partial sum the walk forms fits int32 (the paper's
+ *   Sec. IV-B.5 overflow pre-check is heuristic; this bound is rigorous).
+ *   Larger inputs return QUBO_EOVERFLOW.
+ * - float32 input (the paper's Sec. VI-B future work): T is scaled by 2^p and
+ *   rounded half-to-even to int32 so that sum |T~| <= 2^29, solved exactly in
+ *   int32, and the returned state is rescored in float64 from the caller's Q.
+ *   With eps_q = nnz(T) * 2^(-p-1), |E(x) - 2^-p E~(x)| <= eps_q for every x,
+ *   so the returned energy is within tol = 2 eps_q of the true minimum.
+ *   NaN or Inf entries return QUBO_ENONFINITE.
+ * - Inputs are borrowed and read-only; they need to stay valid only for the
+ *   duration of the call (qubo_server_submit copies Q before returning).
+ * - Outputs are caller-allocated and written only when QUBO_OK is returned.
+ * - No C++ exception crosses this ABI.  On error the status is returned and a
+ *   thread-local message is available from qubo_last_error().
+ * - Every entry point is reentrant; a server handle is internally
+ *   synchronised.
+ */
+#ifndef QUBO_MI355X_H
+#define QUBO_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { QUBO_INT32 = 0, QUBO_FP32 = 1 } qubo_dtype_t;
+
+typedef enum {
+    QUBO_OK = 0,
+    QUBO_EINVAL = -1,      /* bad argument (n out of range, null pointer, bad option) */
+    QUBO_EOVERFLOW = -2,   /* int32 input whose |T| sum exceeds 2^30 - 1             */
+    QUBO_ENONFINITE = -3,  /* float32 input holding NaN or Inf                        */
+    QUBO_ENOMEM = -4,      /* host or device allocation failed                        */
+    QUBO_EDEVICE = -5,     /* HIP runtime error (message in qubo_last_error)          */
+    QUBO_EAGAIN = -6,      /* server: result not ready yet / admission deferred       */
+    QUBO_EINTERNAL = -7    /* a self-check failed (e.g. the argmin rescan)            */
+} qubo_status_t;
+
+/* One state with its energy.
+ * int32 input : energy_i is the exact energy, energy == (double)energy_i.
+ * float32 input: energy is E(x) in float64 from the caller's Q; energy_i is the
+ *                scaled integer energy E~(x) = round(2^p T) summed exactly. */
+typedef struct {
+    int64_t energy_i;
+    double energy;
+    uint64_t index;
+} qubo_state_t;
+
+typedef struct {
+    qubo_state_t best;
+    double tol;          /* 0 for int32; 2 eps_q for float32 (see above)           */
+    int p;               /* fixed-point exponent (0 for int32)                     */
+    int A, B;            /* prefix / suffix split used (A + B = n); B = 0: direct  */
+    int L;               /* log2 Gray steps per work item                          */
+    int tier;            /* 0 direct evaluation (n <= 14); 1 exact lane-min every
+                            Gray step; 2 block lower bound, exact min on demand   */
+    uint64_t states;     /* states evaluated = 2^n                                 */
+    double kernel_ms;    /* GPU time of the walk kernel (HIP events)               */
+    double total_ms;     /* host wall time of the whole call                       */
+} qubo_result_t;
+
+/* Plan overrides, mainly for tests and the autotuner.  Zero-initialise for the
+ * defaults.  B: suffix bits in [6, 10] (0 = default 10); L: log2 Gray steps per
+ * work item in [5, A] (0 = default); tier: 0 = default, 1 or 2 to force that
+ * walk tier; waves_per_cu: resident walk waves per compute unit (0 = default). */
+typedef struct {
+    int B;
+    int L;
+    int tier;
+    int waves_per_cu;
+    int reserved[4];
+} qubo_options_t;
+
+/* Solve one instance held in HOST memory.  k = 0 or 1: best state only
+ * (topk may be NULL).  k > 1: additionally the k lexicographically smallest
+ * (E, index) pairs into topk[0..k-1] (k <= 1024, k <= 2^n); topk[0] equals
+ * out->best.  Uses device 0 (or the current HIP device) and its own stream. */
+qubo_status_t qubo_solve(const void *Q, int n, qubo_dtype_t dtype, int k,
+                         qubo_result_t *out, qubo_state_t *topk);
+
+/* As qubo_solve, with plan overrides (opt may be NULL). */
+qubo_status_t qubo_solve_ex(const void *Q, int n, qubo_dtype_t dtype, int k,
+                            const qubo_options_t *opt, qubo_result_t *out,
+                            qubo_state_t *topk);
+
+/* Solve one instance whose Q is already in DEVICE memory of the current HIP
+ * device (e.g. a torch tensor's data_ptr), ordering all work on hip_stream
+ * (a hipStream_t; NULL = the null stream).  Returns after the result has been
+ * copied back (the stream is synchronised). */
+qubo_status_t qubo_solve_device(const void *dQ, int n, qubo_dtype_t dtype, int k,
+                                void *hip_stream, qubo_result_t *out,
+                                qubo_state_t *topk);
+
+/* Solve `count` independent instances (host memory) in one persistent walk
+ * launch.  Q[i] is n[i] x n[i] of dtype[i].  out[i] receives instance i's
+ * result (best state only).  The whole sequence is replayed from a HIP graph. */
+qubo_status_t qubo_solve_batch(int count, const void *const *Q, const int *n,
+                               const qubo_dtype_t *dtype, qubo_result_t *out);
+
+/* Batch handle: plan, allocate and capture once, replay many times. */
+typedef struct qubo_batch qubo_batch_t;
+qubo_status_t qubo_batch_create(int count, const void *const *Q, const int *n,
+                                const qubo_dtype_t *dtype, const qubo_options_t *opt,
+                                qubo_batch_t **batch);
+/* Replay the captured graph on hip_stream (NULL = the batch's own stream) and
+ * wait for it. */
+qubo_status_t qubo_batch_run(qubo_batch_t *batch, void *hip_stream);
+qubo_status_t qubo_batch_results(qubo_batch_t *batch, qubo_result_t *out);
+/* Total states of the batch and the walk-kernel time of the last replay. */
+qubo_status_t qubo_batch_stats(qubo_batch_t *batch, double *states, double *kernel_ms);
+void qubo_batch_destroy(qubo_batch_t *batch);
+
+/* Continuous-batching server (see the serving notes in the docs):
+ * requests are admitted into device slots as slots and the device-memory
+ * budget allow; each scheduler tick launches one walk over pending work items
+ * of every admitted request, so arrivals join work already on the GPU. */
+typedef struct qubo_server qubo_server_t;
+qubo_status_t qubo_server_create(size_t mem_budget_bytes, int max_slots,
+                                 qubo_server_t **srv);
+/* Copies Q; returns a ticket.  QUBO_EAGAIN never happens here: admission is
+ * deferred inside the server when slots or memory are short. */
+qubo_status_t qubo_server_submit(qubo_server_t *srv, const void *Q, int n,
+                                 qubo_dtype_t dtype, uint64_t *ticket);
+/* QUBO_OK with the result once finished, QUBO_EAGAIN while pending. */
+qubo_status_t qubo_server_poll(qubo_server_t *srv, uint64_t ticket, qubo_result_t *out);
+/* Blocks until the ticket finishes or timeout_ms passes (QUBO_EAGAIN). */
+qubo_status_t qubo_server_wait(qubo_server_t *srv, uint64_t ticket, double timeout_ms,
+                               qubo_result_t *out);
+/* Latency percentiles over finished requests (arrival -> result ready) and
+ * aggregate states/s since creation. */
+qubo_status_t qubo_server_stats(qubo_server_t *srv, double *p50_ms, double *p99_ms,
+                                double *states_per_s);
+void qubo_server_destroy(qubo_server_t *srv);
+
+/* Host-only planning, for tests: fold, overflow proof / fp32 scale, split.
+ * Never touches the GPU.  T_out (n*n int32, may be NULL) receives the folded
+ * (and for float32 scaled) upper-triangular matrix the kernels consume. */
+typedef struct {
+    int n, A, B, L, tier, direct;
+    int p;
+    double eps_q;
+    int64_t sum_abs_t;   /* sum |T~_ij| over i <= j */
+    uint64_t items;      /* walk work items */
+} qubo_plan_info_t;
+qubo_status_t qubo_plan_info(const void *Q, int n, qubo_dtype_t dtype,
+                             const qubo_options_t *opt, qubo_plan_info_t *info,
+                             int32_t *T_out);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *qubo_last_error(void);
+
+/* Library version string. */
+const char *qubo_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QUBO_MI355X_H */

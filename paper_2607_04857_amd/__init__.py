@@ -1,1 +1,326 @@
-"""MI355X exhaustive dense-QUBO solver (prefix-suffix decomposition + Gray-code walk)."""
+"""MI355X exhaustive dense-QUBO solver: thin Python binding of ``libqubo_mi355x.so``.
+
+Every step of a solve runs inside the HIP library (see ``include/qubo.h``);
+this module only marshals arguments.  There is no CPU fallback: if the
+library is missing, every call raises ``QuboLibraryMissing``.
+
+Conventions (paper Sec. I and II-B): E(x) = sum_{i,j} Q_ij x_i x_j; a state
+is its row ``index`` in the lexicographic matrix U_N (x_0 is the most
+significant bit); the answer is the minimum energy with the lowest index.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqubo_mi355x.so")
+
+QUBO_INT32, QUBO_FP32 = 0, 1
+STATUS = {0: "QUBO_OK", -1: "QUBO_EINVAL", -2: "QUBO_EOVERFLOW", -3: "QUBO_ENONFINITE",
+          -4: "QUBO_ENOMEM", -5: "QUBO_EDEVICE", -6: "QUBO_EAGAIN", -7: "QUBO_EINTERNAL"}
+
+
+class QuboLibraryMissing(RuntimeError):
+    pass
+
+
+class QuboError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class _State(ctypes.Structure):
+    _fields_ = [("energy_i", ctypes.c_int64), ("energy", ctypes.c_double),
+                ("index", ctypes.c_uint64)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("best", _State), ("tol", ctypes.c_double), ("p", ctypes.c_int),
+                ("A", ctypes.c_int), ("B", ctypes.c_int), ("L", ctypes.c_int),
+                ("tier", ctypes.c_int), ("states", ctypes.c_uint64),
+                ("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("B", ctypes.c_int), ("L", ctypes.c_int), ("tier", ctypes.c_int),
+                ("waves_per_cu", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
+
+
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("A", ctypes.c_int), ("B", ctypes.c_int),
+                ("L", ctypes.c_int), ("tier", ctypes.c_int), ("direct", ctypes.c_int),
+                ("p", ctypes.c_int), ("eps_q", ctypes.c_double), ("sum_abs_t", ctypes.c_int64),
+                ("items", ctypes.c_uint64)]
+
+
+# name -> (restype, argtypes); mirrors include/qubo.h
+_VP, _I, _U64P = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)
+_SIGS = {
+    "qubo_solve": (_I, [_VP, _I, _I, _I, ctypes.POINTER(_Result), ctypes.POINTER(_State)]),
+    "qubo_solve_ex": (_I, [_VP, _I, _I, _I, ctypes.POINTER(_Options), ctypes.POINTER(_Result),
+                           ctypes.POINTER(_State)]),
+    "qubo_solve_device": (_I, [_VP, _I, _I, _I, _VP, ctypes.POINTER(_Result),
+                               ctypes.POINTER(_State)]),
+    "qubo_solve_batch": (_I, [_I, ctypes.POINTER(_VP), ctypes.POINTER(_I), ctypes.POINTER(_I),
+                              ctypes.POINTER(_Result)]),
+    "qubo_batch_create": (_I, [_I, ctypes.POINTER(_VP), ctypes.POINTER(_I), ctypes.POINTER(_I),
+                               ctypes.POINTER(_Options), ctypes.POINTER(_VP)]),
+    "qubo_batch_run": (_I, [_VP, _VP]),
+    "qubo_batch_results": (_I, [_VP, ctypes.POINTER(_Result)]),
+    "qubo_batch_stats": (_I, [_VP, ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(ctypes.c_double)]),
+    "qubo_batch_destroy": (None, [_VP]),
+    "qubo_server_create": (_I, [ctypes.c_size_t, _I, ctypes.POINTER(_VP)]),
+    "qubo_server_submit": (_I, [_VP, _VP, _I, _I, _U64P]),
+    "qubo_server_poll": (_I, [_VP, ctypes.c_uint64, ctypes.POINTER(_Result)]),
+    "qubo_server_wait": (_I, [_VP, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(_Result)]),
+    "qubo_server_stats": (_I, [_VP, ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "qubo_server_destroy": (None, [_VP]),
+    "qubo_plan_info": (_I, [_VP, _I, _I, ctypes.POINTER(_Options), ctypes.POINTER(_PlanInfo),
+                            ctypes.POINTER(ctypes.c_int32)]),
+    "qubo_last_error": (ctypes.c_char_p, []),
+    "qubo_version": (ctypes.c_char_p, []),
+}
+EXPORTS = tuple(_SIGS)
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load the HIP library (raises QuboLibraryMissing when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise QuboLibraryMissing(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2607_04857_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != 0:
+        raise QuboError(status, lib().qubo_last_error().decode(errors="replace"))
+
+
+@dataclass
+class Result:
+    energy: float          # exact for int32; float64 rescore for fp32
+    energy_i: int          # exact integer energy (scaled by 2^p for fp32)
+    index: int             # U_N row of the argmin (lowest index among ties)
+    n: int
+    tol: float
+    p: int
+    A: int
+    B: int
+    L: int
+    tier: int
+    states: int
+    kernel_ms: float
+    total_ms: float
+
+    @property
+    def x(self) -> np.ndarray:
+        return np.array([(self.index >> (self.n - 1 - i)) & 1 for i in range(self.n)],
+                        dtype=np.int8)
+
+
+def _result(r: _Result, n: int) -> Result:
+    return Result(energy=r.best.energy, energy_i=r.best.energy_i, index=r.best.index, n=n,
+                  tol=r.tol, p=r.p, A=r.A, B=r.B, L=r.L, tier=r.tier, states=r.states,
+                  kernel_ms=r.kernel_ms, total_ms=r.total_ms)
+
+
+def _as_q(Q):
+    Q = np.asarray(Q)
+    if Q.ndim != 2 or Q.shape[0] != Q.shape[1]:
+        raise ValueError("Q must be a square matrix")
+    if Q.dtype == np.float32:
+        return np.ascontiguousarray(Q), QUBO_FP32
+    if Q.dtype.kind in "iu":
+        if Q.size and (Q.min() < -2**31 or Q.max() > 2**31 - 1):
+            raise ValueError("integer Q must fit int32")
+        return np.ascontiguousarray(Q, dtype=np.int32), QUBO_INT32
+    raise TypeError("Q must be int32 or float32")
+
+
+def _options(B=0, L=0, tier=0, waves_per_cu=0) -> _Options:
+    o = _Options()
+    o.B, o.L, o.tier, o.waves_per_cu = int(B), int(L), int(tier), int(waves_per_cu)
+    return o
+
+
+def solve(Q, k: int = 1, *, B: int = 0, L: int = 0, tier: int = 0, waves_per_cu: int = 0):
+    """Minimise E(x) for a host matrix.  k > 1 also returns the k smallest (E, index) pairs."""
+    Qc, dt = _as_q(Q)
+    n = Qc.shape[0]
+    out = _Result()
+    top = (_State * k)() if k > 1 else None
+    opt = _options(B, L, tier, waves_per_cu)
+    _check(lib().qubo_solve_ex(Qc.ctypes.data, n, dt, int(k), ctypes.byref(opt),
+                               ctypes.byref(out), top))
+    res = _result(out, n)
+    if k > 1:
+        pairs = [(t.energy if dt == QUBO_FP32 else t.energy_i, int(t.index)) for t in top]
+        return res, pairs
+    return res
+
+
+def solve_device(Qt, k: int = 1, stream=None):
+    """Solve a QUBO held in a torch CUDA tensor (int32 or float32), ordered on ``stream``."""
+    import torch
+    if not Qt.is_cuda or Qt.dim() != 2 or Qt.shape[0] != Qt.shape[1]:
+        raise ValueError("Qt must be a square CUDA tensor")
+    if Qt.dtype == torch.float32:
+        dt = QUBO_FP32
+    elif Qt.dtype == torch.int32:
+        dt = QUBO_INT32
+    else:
+        raise TypeError("Qt must be int32 or float32")
+    Qt = Qt.contiguous()
+    s = stream if stream is not None else torch.cuda.current_stream(Qt.device)
+    out = _Result()
+    top = (_State * k)() if k > 1 else None
+    with torch.cuda.device(Qt.device):
+        _check(lib().qubo_solve_device(ctypes.c_void_p(Qt.data_ptr()), Qt.shape[0], dt, int(k),
+                                       ctypes.c_void_p(s.cuda_stream), ctypes.byref(out), top))
+    res = _result(out, Qt.shape[0])
+    if k > 1:
+        pairs = [(t.energy if dt == QUBO_FP32 else t.energy_i, int(t.index)) for t in top]
+        return res, pairs
+    return res
+
+
+def _batch_args(Qs: Sequence):
+    mats = [_as_q(Q) for Q in Qs]
+    cnt = len(mats)
+    ptrs = (_VP * cnt)(*[m.ctypes.data for m, _ in mats])
+    ns = (_I * cnt)(*[m.shape[0] for m, _ in mats])
+    dts = (_I * cnt)(*[dt for _, dt in mats])
+    return mats, cnt, ptrs, ns, dts
+
+
+class Batch:
+    """Plan, allocate and graph-capture a batch once; ``run()`` replays it."""
+
+    def __init__(self, Qs: Sequence, *, B: int = 0, L: int = 0, tier: int = 0,
+                 waves_per_cu: int = 0):
+        self._mats, self.count, ptrs, ns, dts = _batch_args(Qs)
+        self._ns = [m.shape[0] for m, _ in self._mats]
+        self._h = _VP()
+        opt = _options(B, L, tier, waves_per_cu)
+        _check(lib().qubo_batch_create(self.count, ptrs, ns, dts, ctypes.byref(opt),
+                                       ctypes.byref(self._h)))
+
+    def run(self, stream=None):
+        s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+        _check(lib().qubo_batch_run(self._h, s))
+
+    def results(self) -> List[Result]:
+        out = (_Result * self.count)()
+        _check(lib().qubo_batch_results(self._h, out))
+        return [_result(out[i], self._ns[i]) for i in range(self.count)]
+
+    def stats(self):
+        st, ms = ctypes.c_double(), ctypes.c_double()
+        _check(lib().qubo_batch_stats(self._h, ctypes.byref(st), ctypes.byref(ms)))
+        return st.value, ms.value
+
+    def close(self):
+        if self._h:
+            lib().qubo_batch_destroy(self._h)
+            self._h = _VP()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batch(Qs: Sequence) -> List[Result]:
+    mats, cnt, ptrs, ns, dts = _batch_args(Qs)
+    out = (_Result * cnt)()
+    _check(lib().qubo_solve_batch(cnt, ptrs, ns, dts, out))
+    return [_result(out[i], mats[i][0].shape[0]) for i in range(cnt)]
+
+
+class Server:
+    """Continuous-batching server (see include/qubo.h)."""
+
+    def __init__(self, mem_budget_bytes: int = 1 << 30, max_slots: int = 256):
+        self._h = _VP()
+        _check(lib().qubo_server_create(int(mem_budget_bytes), int(max_slots),
+                                        ctypes.byref(self._h)))
+        self._n = {}
+
+    def submit(self, Q) -> int:
+        Qc, dt = _as_q(Q)
+        t = ctypes.c_uint64()
+        _check(lib().qubo_server_submit(self._h, Qc.ctypes.data, Qc.shape[0], dt, ctypes.byref(t)))
+        self._n[t.value] = Qc.shape[0]
+        return t.value
+
+    def poll(self, ticket: int) -> Optional[Result]:
+        out = _Result()
+        st = lib().qubo_server_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(out))
+        if st == -6:
+            return None
+        _check(st)
+        return _result(out, self._n[ticket])
+
+    def wait(self, ticket: int, timeout_ms: float = 60000.0) -> Optional[Result]:
+        out = _Result()
+        st = lib().qubo_server_wait(self._h, ctypes.c_uint64(ticket), float(timeout_ms),
+                                    ctypes.byref(out))
+        if st == -6:
+            return None
+        _check(st)
+        return _result(out, self._n[ticket])
+
+    def stats(self):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().qubo_server_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"p50_ms": a.value, "p99_ms": b.value, "states_per_s": c.value}
+
+    def close(self):
+        if self._h:
+            lib().qubo_server_destroy(self._h)
+            self._h = _VP()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan_info(Q, *, B: int = 0, L: int = 0, tier: int = 0):
+    """Host-only plan of a solve (no GPU): split, items, scale; plus the folded T."""
+    Qc, dt = _as_q(Q)
+    n = Qc.shape[0]
+    info = _PlanInfo()
+    T = np.zeros((n, n), dtype=np.int32)
+    opt = _options(B, L, tier)
+    _check(lib().qubo_plan_info(Qc.ctypes.data, n, dt, ctypes.byref(opt), ctypes.byref(info),
+                                T.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    d = {f: getattr(info, f) for f, _ in _PlanInfo._fields_}
+    d["T"] = T
+    return d
+
+
+def version() -> str:
+    return lib().qubo_version().decode()

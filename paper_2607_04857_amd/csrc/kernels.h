@@ -1,0 +1,74 @@
+// kernels.h -- device data layout and kernel launchers of the solver.
+//
+// Layout in HBM per instance (all int32 unless noted; built by table_kernel):
+//   T   [n][n]        folded upper-triangular matrix (input of the table build)
+//   M   [A][2^B]      interaction rows M_int[v][s] = sum over set suffix bits t
+//                     of T[v][A+t] (Sec. II-C: M_int = Q_ps U_B^T), column s
+//                     stored at s = j*64 + lane so lane `lane` owns columns
+//                     {j*64 + lane}, j < 2^B/64 (column-wise split, Sec. III-C.2)
+//   EB  [2^B]         suffix energies E_s(U_B) (Sec. III-A, preprocessing 2)
+//   S   [A][64]       S[w][l] = T[min(l,w)][max(l,w)] for l != w < A, else 0:
+//                     the prefix couplings, one lane per variable
+//   K   [3][16]       bound constants of the tier-2 walk (per-offset column
+//                     minima of the static low-level row combinations)
+//   Qf  [n][n] fp32   caller's float32 Q (fp32 instances only, for rescoring)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace qk {
+
+constexpr int kWave = 64;
+constexpr int kSuperLog = 5;          // unrolled super-block: 32 Gray steps
+constexpr int kLowLevels = 4;         // Gray levels with static patterns in a super-block
+constexpr int kPatterns = 1 << kLowLevels;
+constexpr int kVgprLevels = 12;       // M_int rows of levels 0..11 held in VGPRs
+constexpr int32_t kNoEnergy = 1 << 30;  // above every energy the walk can meet
+
+struct Inst {
+    const int32_t *T;
+    int32_t *M;
+    int32_t *EB;
+    int32_t *S;
+    int32_t *K;
+    const float *Qf;
+    int n, A, B, L;
+    int direct;        // 1: no walk, direct evaluation of all 2^n states
+    int pad;
+    uint64_t item_begin;   // global walk-item range [item_begin, item_end)
+    uint64_t item_end;
+};
+
+struct ItemRes {
+    int32_t E;         // best energy accepted inside the item (kNoEnergy: none)
+    int32_t found;
+    uint64_t row;      // prefix row (U_A row) of that chunk
+};
+
+struct FinalRes {
+    int64_t E;         // exact integer energy of the answer
+    uint64_t index;    // U_N row of the answer
+    double E64;        // float64 rescore from Qf (fp32 instances)
+    int32_t status;    // 0 ok, nonzero: self-check failure
+    int32_t pad;
+};
+
+// Builds M, EB, S, K for every instance and zeroes the item counter.
+hipError_t launch_tables(const Inst *d_insts, int n_inst, int max_A, unsigned long long *d_counter,
+                         hipStream_t stream);
+
+// Persistent Gray walk over all items; `waves` resident wavefronts.
+hipError_t launch_walk(int mcols, int tier, const Inst *d_insts, int n_inst, uint64_t total_items,
+                       unsigned long long *d_counter, ItemRes *d_res, int waves,
+                       hipStream_t stream);
+
+// Resident walk wavefronts per CU for a variant (occupancy query, >= 1).
+int walk_occupancy(int mcols, int tier);
+
+// Per-instance reduction of item results, argmin rescan (or direct
+// evaluation for tiny n) and float64 rescoring.
+hipError_t launch_finish(const Inst *d_insts, int n_inst, const ItemRes *d_res, FinalRes *d_out,
+                         hipStream_t stream);
+
+}  // namespace qk

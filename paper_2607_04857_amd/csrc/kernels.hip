@@ -1,0 +1,561 @@
+// kernels.hip -- gfx950 kernels of the exhaustive dense-QUBO solver.
+//
+// Method (paper Sec. II-III): split every state x = [x_p | x_s] into an
+// A-bit prefix and a B-bit suffix.  For a fixed prefix the energies of all
+// 2^B states of its chunk are (Sec. II-C, Eq. chunk_energy_final)
+//     E(C_xp) = E_p(x_p) 1 + x_p M_int + E_s(U_B),   M_int = Q_ps U_B^T.
+// Walking the prefixes in reflected Gray order (Sec. III-B) changes x_p by one
+// bit k per step, so the suffix-dependent vector E_sd = x_p M_int + E_s moves
+// by +-M_int[k] (Eq. incremental_update): one int32 add per state.
+//
+// MI355X mapping:
+//  * one wavefront owns all 2^B columns of its chunk: lane l holds columns
+//    s = j*64 + l (j < MC), i.e. E_sd lives in MC VGPRs per lane (column-wise
+//    split, Sec. III-C.2, at lane granularity);
+//  * the twelve most frequently flipped rows M_int[k] (Gray levels 0..11) sit
+//    in VGPRs; higher levels flip once per 4096 steps and are read from L2;
+//  * wavefronts take work items (2^L consecutive Gray steps of the prefix,
+//    the "straightforward" split of Sec. III-C.1 along the Gray index) from an
+//    atomic counter; the grid is persistent;
+//  * the scalar unit keeps the prefix self-energy E_p: the walk is unrolled
+//    over 32-step super-blocks in which the four lowest Gray levels follow a
+//    static pattern, so E_p of each of the 16 low patterns is tabulated in
+//    SGPRs and refreshed only when a higher prefix bit flips;
+//  * the per-state test "min over the chunk + E_p <= best" is a v_min3 tree
+//    per lane and one compare against an SGPR threshold; the rare hit is
+//    resolved with a DPP wave minimum.  Ties resolve to the lowest prefix row
+//    here and to the lowest suffix in the final rescan, giving the lowest
+//    U_N index overall.
+#include <type_traits>
+#include <utility>
+
+#include "kernels.h"
+
+namespace qk {
+
+// ---------------------------------------------------------------- helpers
+
+template <int Begin, int End, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (Begin < End) {
+        f(std::integral_constant<int, Begin>{});
+        static_for<Begin + 1, End>(static_cast<F &&>(f));
+    }
+}
+
+constexpr int cx_ctz(int v)
+{
+    int r = 0;
+    while (!(v & 1)) {
+        v >>= 1;
+        r++;
+    }
+    return r;
+}
+
+__device__ __forceinline__ int32_t sread(int32_t v)
+{
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ uint64_t sread64(uint64_t v)
+{
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int32_t(uint32_t(v))));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int32_t(uint32_t(v >> 32))));
+    return (uint64_t(hi) << 32) | lo;
+}
+
+// Minimum of E[0..N) with three-input minima (v_min3_i32) level by level:
+// ceil((N-1)/2) VALU ops.
+template <int N>
+__device__ __forceinline__ int32_t tree_min(const int32_t *e)
+{
+    if constexpr (N == 1) {
+        return e[0];
+    } else if constexpr (N == 2) {
+        return min(e[0], e[1]);
+    } else {
+        constexpr int G3 = N / 3, R = N % 3;
+        int32_t t[G3 + R];
+        static_for<0, G3>([&](auto gc) {
+            constexpr int g = decltype(gc)::value;
+            t[g] = min(min(e[3 * g], e[3 * g + 1]), e[3 * g + 2]);
+        });
+        static_for<0, R>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            t[G3 + r] = e[3 * G3 + r];
+        });
+        return tree_min<G3 + R>(t);
+    }
+}
+
+// Wave-wide minimum: DPP butterflies inside each row of 16 lanes, then the
+// four row results through the scalar unit.
+__device__ __forceinline__ int32_t wave_min(int32_t v)
+{
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xF, 0xF, false));  // row_ror:4
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xF, 0xF, false));  // row_ror:8
+    const int32_t a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+    const int32_t c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+    return min(min(a, b), min(c, d));
+}
+
+__device__ __forceinline__ int64_t wave_sum64(int64_t v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Energy of U_N row `idx` from the folded upper-triangular T (exact).
+__device__ int64_t energy_int(const int32_t *T, int n, uint64_t idx)
+{
+    int64_t E = 0;
+    for (int i = 0; i < n; i++) {
+        if (!((idx >> (n - 1 - i)) & 1)) continue;
+        int64_t rowsum = 0;
+        for (int j = i; j < n; j++)
+            if ((idx >> (n - 1 - j)) & 1) rowsum += T[i * n + j];
+        E += rowsum;
+    }
+    return E;
+}
+
+// E(x) = sum_{i,j} Q_ij x_i x_j in float64 from the caller's float32 Q,
+// summed i ascending then j ascending over the set bits.
+__device__ double energy_f64(const float *Q, int n, uint64_t idx)
+{
+    double E = 0.0;
+    for (int i = 0; i < n; i++) {
+        if (!((idx >> (n - 1 - i)) & 1)) continue;
+        for (int j = 0; j < n; j++)
+            if ((idx >> (n - 1 - j)) & 1) E += double(Q[i * n + j]);
+    }
+    return E;
+}
+
+__device__ __forceinline__ void lexmin(int64_t &bE, uint64_t &bI, int64_t e, uint64_t i)
+{
+    if (e < bE || (e == bE && i < bI)) {
+        bE = e;
+        bI = i;
+    }
+}
+
+// ---------------------------------------------------------------- tables
+
+__global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ insts,
+                                                     unsigned long long *__restrict__ counter)
+{
+    const Inst I = insts[blockIdx.y];
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *counter = 0ull;
+    if (I.direct) return;
+    const int n = I.n, A = I.A, B = I.B;
+    const uint32_t NS = 1u << B;
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const int32_t *T = I.T;
+    // M_int[v][s] = sum over the set suffix bits t of s of T[v][A + t]
+    // (Sec. II-C; bit t of the suffix row is (s >> (B-1-t)) & 1).
+    for (uint32_t e = tid; e < uint32_t(A) * NS; e += stride) {
+        const int v = int(e >> B);
+        const uint32_t s = e & (NS - 1);
+        int32_t acc = 0;
+        for (int t = 0; t < B; t++)
+            if ((s >> (B - 1 - t)) & 1u) acc += T[v * n + A + t];
+        I.M[e] = acc;
+    }
+    // E_s(U_B)[s] = sum_{t <= u, both set} T[A+t][A+u] (Sec. III-A, step 2)
+    for (uint32_t s = tid; s < NS; s += stride) {
+        int32_t acc = 0;
+        for (int t = 0; t < B; t++) {
+            if (!((s >> (B - 1 - t)) & 1u)) continue;
+            for (int u = t; u < B; u++)
+                if ((s >> (B - 1 - u)) & 1u) acc += T[(A + t) * n + A + u];
+        }
+        I.EB[s] = acc;
+    }
+    // prefix couplings, one lane per variable
+    for (uint32_t e = tid; e < uint32_t(A) * kWave; e += stride) {
+        const int w = int(e / kWave), l = int(e % kWave);
+        int32_t v = 0;
+        if (l < A && l != w) v = (l < w) ? T[l * n + w] : T[w * n + l];
+        I.S[e] = v;
+    }
+}
+
+// ---------------------------------------------------------------- walk
+
+template <int MC, int TIER>
+__global__ __launch_bounds__(kWave) void walk_kernel(const Inst *__restrict__ insts, int n_inst,
+                                                     uint64_t total_items,
+                                                     unsigned long long *__restrict__ counter,
+                                                     ItemRes *__restrict__ res)
+{
+    static_assert(TIER == 1, "tier");
+    constexpr int G = kVgprLevels;
+    const int lane = int(threadIdx.x);
+
+    int cur = -1;
+    const int32_t *M = nullptr, *EB = nullptr, *S = nullptr;
+    int A = 0, L = 0;
+    uint64_t item_begin = 0;
+    int32_t R[G][MC];        // M_int rows of Gray levels 0..G-1 (variable A-1-t)
+    int32_t S4 = 0;          // couplings of the level-4 variable, one lane each
+    int32_t diagl = 0;       // T[l][l] on lane l < A
+    int32_t CR[kPatterns];   // low-low coupling increments per pattern
+    int32_t best = kNoEnergy;
+    uint64_t bestRow = ~0ull;
+
+    for (;;) {
+        uint64_t g = 0;
+        if (lane == 0) g = atomicAdd(counter, 1ull);
+        g = sread64(g);
+        if (g >= total_items) break;
+
+        // instance owning item g: first k with item_end > g
+        int lo = 0, hi = n_inst - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (insts[mid].item_end > g) hi = mid;
+            else lo = mid + 1;
+        }
+        if (lo != cur) {
+            cur = lo;
+            const Inst &I = insts[lo];
+            M = I.M;
+            EB = I.EB;
+            S = I.S;
+            A = I.A;
+            L = I.L;
+            item_begin = I.item_begin;
+            static_for<0, G>([&](auto tc) {
+                constexpr int t = decltype(tc)::value;
+                const bool have = t < A;
+                const int v = have ? A - 1 - t : 0;
+#pragma unroll
+                for (int j = 0; j < MC; j++) R[t][j] = have ? M[(v * MC + j) * kWave + lane] : 0;
+            });
+            S4 = S[(A - 5) * kWave + lane];
+            diagl = lane < A ? I.T[lane * I.n + lane] : 0;
+            // Sll(t,u): coupling of the low variables A-1-t and A-1-u
+            int32_t Sll[kLowLevels][kLowLevels];
+            static_for<0, kLowLevels>([&](auto tc) {
+                constexpr int t = decltype(tc)::value;
+                static_for<0, kLowLevels>([&](auto uc) {
+                    constexpr int u = decltype(uc)::value;
+                    Sll[t][u] = (t == u) ? 0 : S[(A - 1 - u) * kWave + (A - 1 - t)];
+                });
+            });
+            CR[0] = 0;
+            static_for<1, kPatterns>([&](auto pc) {
+                constexpr int p = decltype(pc)::value;
+                constexpr int t = cx_ctz(p);
+                constexpr int pp = p & (p - 1);
+                int32_t acc = 0;
+                static_for<0, kLowLevels>([&](auto uc) {
+                    constexpr int u = decltype(uc)::value;
+                    if constexpr ((pp >> u) & 1) acc += Sll[t][u];
+                });
+                CR[p] = acc;
+            });
+            best = kNoEnergy;
+            bestRow = ~0ull;
+        }
+
+        // ---- item set-up: state g(i0) from scratch
+        const uint64_t i0 = (g - item_begin) << L;
+        const uint64_t sb0 = i0 >> kSuperLog;
+        const uint64_t sbEnd = sb0 + (1ull << (L - kSuperLog));
+        const uint64_t row0 = i0 ^ (i0 >> 1);
+
+        int32_t E[MC];
+#pragma unroll
+        for (int j = 0; j < MC; j++) E[j] = EB[j * kWave + lane];
+        for (int v = 0; v < A; v++) {
+            if ((row0 >> (A - 1 - v)) & 1) {
+#pragma unroll
+                for (int j = 0; j < MC; j++) E[j] += M[(v * MC + j) * kWave + lane];
+            }
+        }
+        // F: field of every prefix variable from the non-low ones (levels >= 4,
+        // variables 0..A-5), plus its diagonal; one lane per variable.
+        int32_t F = diagl;
+        for (int w = 0; w <= A - 5; w++)
+            if ((row0 >> (A - 1 - w)) & 1) F += S[w * kWave + lane];
+        // E_nl = energy of the non-low prefix bits = (sum_set F_w + T_ww) / 2
+        const bool lbit = lane <= A - 5 && ((row0 >> (A - 1 - lane)) & 1);
+        int32_t Enl = int32_t(wave_sum64(lbit ? int64_t(F) + diagl : 0) / 2);
+        Enl = sread(Enl);
+        int32_t H[kLowLevels];
+        static_for<0, kLowLevels>([&](auto tc) {
+            constexpr int t = decltype(tc)::value;
+            H[t] = __builtin_amdgcn_readlane(F, A - 1 - t);
+        });
+        // THR[p] = best - E_p(low pattern p): the chunk holds a candidate when
+        // its minimum E_sd is <= THR of the current pattern.
+        int32_t THR[kPatterns];
+        auto build_thr = [&]() {
+            THR[0] = best - Enl;
+            static_for<1, kPatterns>([&](auto pc) {
+                constexpr int p = decltype(pc)::value;
+                constexpr int t = cx_ctz(p);
+                constexpr int pp = p & (p - 1);
+                THR[p] = THR[pp] - H[t] - CR[p];
+            });
+        };
+        build_thr();
+
+        // A non-low prefix variable w flips (direction up: 0 -> 1).
+        auto nonlow_flip = [&](int w, bool up, int32_t Scol) {
+            const int32_t Fw = __builtin_amdgcn_readlane(F, w);
+            if (up) {
+                Enl += Fw;
+                F += Scol;
+            } else {
+                Enl -= Fw;
+                F -= Scol;
+            }
+            static_for<0, kLowLevels>([&](auto tc) {
+                constexpr int t = decltype(tc)::value;
+                H[t] = __builtin_amdgcn_readlane(F, A - 1 - t);
+            });
+            build_thr();
+        };
+
+        int32_t itemE = kNoEnergy;
+        uint64_t itemRow = 0;
+        int found = 0;
+
+        for (uint64_t sb = sb0; sb < sbEnd; sb++) {
+            static_for<0, 32>([&](auto oc) {
+                constexpr int o = decltype(oc)::value;
+                constexpr int pat = (o ^ (o >> 1)) & (kPatterns - 1);
+                // ---- evaluate the chunk of Gray step sb*32 + o
+                const int32_t lm = tree_min<MC>(E);
+                const int32_t thr = THR[pat];
+                if (__builtin_amdgcn_ballot_w64(lm <= thr)) {
+                    const int32_t wmin = wave_min(lm);
+                    const int32_t Ec = wmin + (best - thr);   // + E_p
+                    const uint64_t i = (sb << kSuperLog) | uint64_t(o);
+                    const uint64_t rc = i ^ (i >> 1);
+                    if (Ec < best || (Ec == best && rc < bestRow)) {
+                        const int32_t d = Ec - best;
+                        best = Ec;
+                        bestRow = rc;
+                        itemE = Ec;
+                        itemRow = rc;
+                        found = 1;
+                        static_for<0, kPatterns>([&](auto pc) {
+                            constexpr int p = decltype(pc)::value;
+                            THR[p] += d;
+                        });
+                    }
+                }
+                // ---- flip one prefix bit (Alg. 2: E_sd += delta M_int[k])
+                if constexpr (o < 31) {
+                    constexpr int t = cx_ctz(o + 1);
+                    if constexpr (t < kLowLevels) {
+                        constexpr bool up = ((((o + 1) ^ ((o + 1) >> 1)) >> t) & 1) != 0;
+#pragma unroll
+                        for (int j = 0; j < MC; j++) E[j] = up ? E[j] + R[t][j] : E[j] - R[t][j];
+                    } else {
+                        const bool up = (sb & 1) == 0;
+                        if (up) {
+#pragma unroll
+                            for (int j = 0; j < MC; j++) E[j] += R[4][j];
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < MC; j++) E[j] -= R[4][j];
+                        }
+                        nonlow_flip(A - 5, up, S4);
+                    }
+                } else {
+                    if (sb + 1 < sbEnd) {
+                        const uint64_t ip1 = (sb + 1) << kSuperLog;
+                        const int t = __builtin_ctzll(ip1);
+                        const bool up = ((ip1 >> (t + 1)) & 1) == 0;
+                        const int w = A - 1 - t;
+                        bool done = false;
+                        static_for<kSuperLog, G>([&](auto tc) {
+                            constexpr int tt = decltype(tc)::value;
+                            if (t == tt) {
+                                if (up) {
+#pragma unroll
+                                    for (int j = 0; j < MC; j++) E[j] += R[tt][j];
+                                } else {
+#pragma unroll
+                                    for (int j = 0; j < MC; j++) E[j] -= R[tt][j];
+                                }
+                                done = true;
+                            }
+                        });
+                        if (!done) {
+#pragma unroll
+                            for (int j = 0; j < MC; j++) {
+                                const int32_t r = M[(w * MC + j) * kWave + lane];
+                                E[j] = up ? E[j] + r : E[j] - r;
+                            }
+                        }
+                        nonlow_flip(w, up, S[w * kWave + lane]);
+                    }
+                }
+            });
+        }
+
+        if (lane == 0) {
+            ItemRes r;
+            r.E = found ? itemE : kNoEnergy;
+            r.found = found;
+            r.row = found ? itemRow : 0ull;
+            res[g] = r;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- finish
+
+__device__ void block_lexmin(int64_t &bE, uint64_t &bI, int64_t *sE, uint64_t *sI)
+{
+    const int t = threadIdx.x;
+    sE[t] = bE;
+    sI[t] = bI;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (t < off) {
+            int64_t e = sE[t + off];
+            uint64_t i = sI[t + off];
+            if (e < sE[t] || (e == sE[t] && i < sI[t])) {
+                sE[t] = e;
+                sI[t] = i;
+            }
+        }
+        __syncthreads();
+    }
+    bE = sE[0];
+    bI = sI[0];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void finish_kernel(const Inst *__restrict__ insts,
+                                                     const ItemRes *__restrict__ res,
+                                                     FinalRes *__restrict__ out)
+{
+    __shared__ int64_t sE[256];
+    __shared__ uint64_t sI[256];
+    const Inst I = insts[blockIdx.x];
+    const int n = I.n;
+    int64_t bE = INT64_MAX;
+    uint64_t bI = ~0ull;
+    int32_t status = 0;
+    if (I.direct) {
+        const uint64_t N = 1ull << n;
+        for (uint64_t r = threadIdx.x; r < N; r += blockDim.x) lexmin(bE, bI, energy_int(I.T, n, r), r);
+        block_lexmin(bE, bI, sE, sI);
+    } else {
+        for (uint64_t k = I.item_begin + threadIdx.x; k < I.item_end; k += blockDim.x) {
+            const ItemRes r = res[k];
+            if (r.found) lexmin(bE, bI, r.E, r.row);
+        }
+        block_lexmin(bE, bI, sE, sI);
+        const int64_t Estar = bE;
+        const uint64_t rowstar = bI;
+        if (Estar == INT64_MAX) {
+            status = 2;   // no item reported a candidate
+        } else {
+            // Argmin reconstruction (ConstructState of Alg. 2): lowest suffix
+            // of chunk rowstar whose energy equals E*.
+            bE = INT64_MAX;
+            bI = ~0ull;
+            const uint32_t NS = 1u << I.B;
+            for (uint32_t s = threadIdx.x; s < NS; s += blockDim.x) {
+                const uint64_t idx = (rowstar << I.B) | s;
+                const int64_t e = energy_int(I.T, n, idx);
+                if (e == Estar) lexmin(bE, bI, e, idx);
+            }
+            block_lexmin(bE, bI, sE, sI);
+            if (bE != Estar) status = 3;  // walk claimed an energy the chunk lacks
+        }
+    }
+    if (threadIdx.x == 0) {
+        FinalRes o;
+        o.E = bE;
+        o.index = bI;
+        o.E64 = (I.Qf && status == 0) ? energy_f64(I.Qf, n, bI) : double(bE);
+        o.status = status;
+        o.pad = 0;
+        out[blockIdx.x] = o;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_tables(const Inst *d_insts, int n_inst, int max_A, unsigned long long *d_counter,
+                         hipStream_t stream)
+{
+    int bx = (max_A * 1024 + 255) / 256;
+    if (bx < 1) bx = 1;
+    if (bx > 64) bx = 64;
+    hipLaunchKernelGGL(tables_kernel, dim3(bx, n_inst), dim3(256), 0, stream, d_insts, d_counter);
+    return hipGetLastError();
+}
+
+template <int MC>
+static hipError_t launch_walk_mc(int tier, const Inst *d_insts, int n_inst, uint64_t total_items,
+                                 unsigned long long *d_counter, ItemRes *d_res, int waves,
+                                 hipStream_t stream)
+{
+    if (tier != 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((walk_kernel<MC, 1>), dim3(waves), dim3(kWave), 0, stream, d_insts, n_inst,
+                       total_items, d_counter, d_res);
+    return hipGetLastError();
+}
+
+template <int MC>
+static int occupancy_mc(int tier)
+{
+    int blocks = 0;
+    if (tier != 1) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, 1>, kWave, 0) !=
+            hipSuccess ||
+        blocks < 1)
+        return 1;
+    return blocks;
+}
+
+int walk_occupancy(int mcols, int tier)
+{
+    switch (mcols) {
+    case 1: return occupancy_mc<1>(tier);
+    case 2: return occupancy_mc<2>(tier);
+    case 4: return occupancy_mc<4>(tier);
+    case 8: return occupancy_mc<8>(tier);
+    default: return occupancy_mc<16>(tier);
+    }
+}
+
+hipError_t launch_walk(int mcols, int tier, const Inst *d_insts, int n_inst, uint64_t total_items,
+                       unsigned long long *d_counter, ItemRes *d_res, int waves,
+                       hipStream_t stream)
+{
+    switch (mcols) {
+    case 1: return launch_walk_mc<1>(tier, d_insts, n_inst, total_items, d_counter, d_res, waves, stream);
+    case 2: return launch_walk_mc<2>(tier, d_insts, n_inst, total_items, d_counter, d_res, waves, stream);
+    case 4: return launch_walk_mc<4>(tier, d_insts, n_inst, total_items, d_counter, d_res, waves, stream);
+    case 8: return launch_walk_mc<8>(tier, d_insts, n_inst, total_items, d_counter, d_res, waves, stream);
+    case 16: return launch_walk_mc<16>(tier, d_insts, n_inst, total_items, d_counter, d_res, waves, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_finish(const Inst *d_insts, int n_inst, const ItemRes *d_res, FinalRes *d_out,
+                         hipStream_t stream)
+{
+    hipLaunchKernelGGL(finish_kernel, dim3(n_inst), dim3(256), 0, stream, d_insts, d_res, d_out);
+    return hipGetLastError();
+}
+
+}  // namespace qk

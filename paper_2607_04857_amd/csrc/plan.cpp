@@ -1,0 +1,155 @@
+// plan.cpp -- fold, exactness proof / fixed-point scale, split and work items.
+#include "plan.h"
+
+#include <cmath>
+#include <cstring>
+
+namespace qplan {
+
+namespace {
+
+// Default suffix width: 64 lanes x 16 columns (B = 10) keeps the lane's
+// columns and the twelve most frequently flipped M_int rows in VGPRs.
+constexpr int kDefaultB = 10;
+constexpr int kMinB = 6;           // one column per lane
+constexpr int kMaxB = 10;          // 16 columns per lane (VGPR budget)
+constexpr int kDefaultTier = 1;
+
+}  // namespace
+
+qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_options_t *opt,
+                        Plan *out, std::string *msg)
+{
+    if (!Q || !out) {
+        *msg = "null argument";
+        return QUBO_EINVAL;
+    }
+    if (n < 1 || n > kMaxN) {
+        *msg = "n must be in [1, 60]";
+        return QUBO_EINVAL;
+    }
+    if (dtype != QUBO_INT32 && dtype != QUBO_FP32) {
+        *msg = "unknown dtype";
+        return QUBO_EINVAL;
+    }
+    Plan P;
+    P.n = n;
+    P.dtype = dtype;
+    P.T.assign(size_t(n) * n, 0);
+    const size_t nn = size_t(n);
+
+    // Fold: E sums over all (i, j), so T_ii = Q_ii and T_ij = Q_ij + Q_ji for
+    // i < j describe the same objective with a zero lower triangle.
+    if (dtype == QUBO_INT32) {
+        const int32_t *q = static_cast<const int32_t *>(Q);
+        int64_t sum = 0;
+        for (size_t i = 0; i < nn; i++) {
+            for (size_t j = i; j < nn; j++) {
+                int64_t t = (i == j) ? int64_t(q[i * nn + i])
+                                     : int64_t(q[i * nn + j]) + int64_t(q[j * nn + i]);
+                sum += t < 0 ? -t : t;
+                if (sum > kIntSumLimit) {
+                    *msg = "sum of |T_ij| exceeds 2^30 - 1: int32 walk not provably exact";
+                    return QUBO_EOVERFLOW;
+                }
+                P.T[i * nn + j] = int32_t(t);
+            }
+        }
+        P.sum_abs = sum;
+    } else {
+        const float *q = static_cast<const float *>(Q);
+        std::vector<double> Td(nn * nn, 0.0);
+        double S = 0.0;
+        int nnz = 0;
+        for (size_t i = 0; i < nn; i++) {
+            for (size_t j = i; j < nn; j++) {
+                double a = q[i * nn + j], b = (i == j) ? 0.0 : double(q[j * nn + i]);
+                if (!std::isfinite(a) || !std::isfinite(b)) {
+                    *msg = "non-finite entry in Q";
+                    return QUBO_ENONFINITE;
+                }
+                double t = a + b;
+                Td[i * nn + j] = t;
+                S += std::fabs(t);
+                if (t != 0.0) nnz++;
+            }
+        }
+        // Largest p with S * 2^p <= 2^29; every partial sum of T~ then stays
+        // within 2^29 + nnz / 2 < 2^30 - 1.
+        int p = 0;
+        if (S > 0.0) {
+            p = int(std::floor(std::log2(kFpScaleTarget / S)));
+            while (std::ldexp(S, p) > kFpScaleTarget) p--;
+        }
+        int64_t sum = 0;
+        for (size_t i = 0; i < nn; i++)
+            for (size_t j = i; j < nn; j++) {
+                double v = std::nearbyint(std::ldexp(Td[i * nn + j], p));  // ties to even
+                int64_t t = int64_t(v);
+                P.T[i * nn + j] = int32_t(t);
+                sum += t < 0 ? -t : t;
+            }
+        if (sum > kIntSumLimit) {
+            *msg = "internal: scaled matrix exceeds the int32 bound";
+            return QUBO_EINTERNAL;
+        }
+        P.p = p;
+        P.sum_abs = sum;
+        // Each rounded entry is within 2^(-p-1) of T_ij * 2^p / 2^p, and a
+        // state's energy sums at most nnz entries.
+        P.eps_q = double(nnz) * std::ldexp(1.0, -p - 1);
+    }
+
+    int B = (opt && opt->B) ? opt->B : kDefaultB;
+    if (opt && opt->B && (opt->B < kMinB || opt->B > kMaxB)) {
+        *msg = "option B must be in [6, 10]";
+        return QUBO_EINVAL;
+    }
+    if (opt && (opt->tier < 0 || opt->tier > 2)) {
+        *msg = "option tier must be 0 (default), 1 or 2";
+        return QUBO_EINVAL;
+    }
+    const int tier = (opt && opt->tier) ? opt->tier : kDefaultTier;
+    P.direct = n <= kDirectMaxN;
+    if (!P.direct && n - B < kSuper) B = n - kSuper;  // the prefix must hold one super-block
+    if (P.direct) {
+        P.A = 0;
+        P.B = 0;
+        P.mcols = 0;
+        P.L = 0;
+        P.items = 0;
+        P.tier = 0;
+        *out = std::move(P);
+        return QUBO_OK;
+    }
+    if (B > kMaxB) B = kMaxB;
+    P.B = B;
+    P.A = n - B;
+    P.mcols = (1 << B) / kWave;
+    P.tier = tier;
+
+    // Work items: 2^L consecutive Gray steps each.  Default: about 2^14
+    // items (enough to keep ~2k resident waves busy with a small tail), but
+    // never fewer than 2^9 steps per item so the per-item set-up stays small,
+    // and never more than 2^20 items.
+    int L;
+    if (opt && opt->L) {
+        L = opt->L;
+        if (L < kSuper || L > P.A) {
+            *msg = "option L must be in [5, A]";
+            return QUBO_EINVAL;
+        }
+    } else {
+        L = P.A - 14;
+        if (L < 9) L = 9;
+        if (P.A - L > 20) L = P.A - 20;
+        if (L > P.A) L = P.A;
+        if (L < kSuper) L = kSuper;
+    }
+    P.L = L;
+    P.items = uint64_t(1) << (P.A - L);
+    *out = std::move(P);
+    return QUBO_OK;
+}
+
+}  // namespace qplan

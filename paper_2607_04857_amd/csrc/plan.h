@@ -1,0 +1,44 @@
+// plan.h -- host-side planning of one QUBO solve (no HIP dependency).
+//
+// Step "canonicalise and plan": fold Q into the upper-triangular T the
+// paper's decomposition assumes (Sec. II-A), prove int32 is exact or scale a
+// float32 Q to fixed point, and choose the prefix/suffix split
+// (A + B = N, Sec. II-A) and the work-item size of the Gray walk.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/qubo.h"
+
+namespace qplan {
+
+// Kernel geometry shared by planner and kernels.
+constexpr int kWave = 64;          // lanes per wavefront
+constexpr int kSuper = 5;          // log2 of the unrolled Gray super-block (32 steps)
+constexpr int kMaxN = 60;
+constexpr int kDirectMaxN = 14;    // n at or below this: direct evaluation, no walk
+constexpr int64_t kIntSumLimit = (int64_t(1) << 30) - 1;   // sum |T| bound, int32 input
+constexpr double kFpScaleTarget = double(int64_t(1) << 29); // sum |T~| target, fp32 input
+
+struct Plan {
+    int n = 0;
+    qubo_dtype_t dtype = QUBO_INT32;
+    bool direct = false;   // evaluate all 2^n states directly (tiny n)
+    int A = 0, B = 0;      // prefix / suffix bits
+    int mcols = 0;         // suffix columns per lane = 2^B / 64
+    int L = 0;             // log2 Gray steps per work item
+    int tier = 0;          // 0: exact lane-min each step; 1: block lower bound
+    int p = 0;             // fixed-point exponent (fp32)
+    double eps_q = 0.0;    // per-state quantisation bound (fp32)
+    int64_t sum_abs = 0;   // sum |T| over i <= j (of the int32 matrix solved)
+    uint64_t items = 0;    // 2^(A - L) walk items (0 when direct)
+    std::vector<int32_t> T;    // folded (and scaled) upper-triangular n x n
+};
+
+// Build a plan from a host Q.  Returns QUBO_OK or an error with msg set.
+qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_options_t *opt,
+                        Plan *out, std::string *msg);
+
+}  // namespace qplan

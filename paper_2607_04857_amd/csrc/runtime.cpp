@@ -1,0 +1,421 @@
+// runtime.cpp -- device jobs and the single-instance C ABI.
+#include "runtime.h"
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+namespace qrt {
+
+namespace {
+thread_local std::string g_last_error;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct JobOffsets {
+    size_t insts = 0, counter = 0, res = 0, out = 0;
+    std::vector<size_t> T, Qf, M, EB, S, K;
+};
+
+}  // namespace
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+const char *last_error_cstr() { return g_last_error.c_str(); }
+
+qubo_status_t device_error(const char *what, hipError_t e)
+{
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return QUBO_EDEVICE;
+}
+
+qubo_status_t device_info(DeviceInfo *info)
+{
+    int dev = 0;
+    QRT_HIP(hipGetDevice(&dev), "hipGetDevice");
+    static std::mutex mu;
+    static int cached_dev = -1, cached_cus = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (cached_dev != dev) {
+            hipDeviceProp_t prop;
+            QRT_HIP(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+            cached_dev = dev;
+            cached_cus = prop.multiProcessorCount;
+        }
+        info->device = dev;
+        info->cus = cached_cus;
+    }
+    return QUBO_OK;
+}
+
+}  // namespace qrt
+
+// Layout helpers kept in one translation unit with the job code.
+namespace qrt {
+
+static JobOffsets compute_offsets(const Job &job, size_t *stage_bytes, size_t *bytes)
+{
+    JobOffsets o;
+    const size_t ni = job.plans.size();
+    size_t off = 0;
+    o.insts = off;
+    off = align_up(off + ni * sizeof(qk::Inst), 256);
+    for (size_t i = 0; i < ni; i++) {
+        const size_t nn = size_t(job.plans[i].n) * job.plans[i].n;
+        o.T.push_back(off);
+        off = align_up(off + nn * sizeof(int32_t), 256);
+        if (job.qf[i]) {
+            o.Qf.push_back(off);
+            off = align_up(off + nn * sizeof(float), 256);
+        } else {
+            o.Qf.push_back(size_t(-1));
+        }
+    }
+    *stage_bytes = off;
+    o.counter = off;
+    off = align_up(off + sizeof(unsigned long long), 256);
+    for (size_t i = 0; i < ni; i++) {
+        const qplan::Plan &P = job.plans[i];
+        const size_t A = P.direct ? 0 : size_t(P.A), NS = P.direct ? 0 : (size_t(1) << P.B);
+        o.M.push_back(off);
+        off = align_up(off + A * NS * sizeof(int32_t), 256);
+        o.EB.push_back(off);
+        off = align_up(off + NS * sizeof(int32_t), 256);
+        o.S.push_back(off);
+        off = align_up(off + A * qk::kWave * sizeof(int32_t), 256);
+        o.K.push_back(off);
+        off = align_up(off + (P.direct ? 0 : 3 * qk::kPatterns * sizeof(int32_t)), 256);
+    }
+    o.res = off;
+    off = align_up(off + size_t(job.total_items) * sizeof(qk::ItemRes), 256);
+    o.out = off;
+    off = align_up(off + ni * sizeof(qk::FinalRes), 256);
+    *bytes = off;
+    return o;
+}
+
+qubo_status_t job_layout(Job *job, int waves_per_cu)
+{
+    job->max_A = 0;
+    job->total_items = 0;
+    job->states = 0.0;
+    job->mcols = 0;
+    job->tier = 0;
+    for (const qplan::Plan &P : job->plans) {
+        job->states += std::ldexp(1.0, P.n);
+        if (P.direct) continue;
+        if (job->mcols == 0) {
+            job->mcols = P.mcols;
+            job->tier = P.tier;
+        } else if (job->mcols != P.mcols || job->tier != P.tier) {
+            set_error("all walked instances of one job must share B and tier");
+            return QUBO_EINVAL;
+        }
+        if (P.A > job->max_A) job->max_A = P.A;
+        job->total_items += P.items;
+    }
+    DeviceInfo di;
+    qubo_status_t st = device_info(&di);
+    if (st != QUBO_OK) return st;
+    int wpc = waves_per_cu;
+    if (wpc <= 0) wpc = qk::walk_occupancy(job->mcols ? job->mcols : 16, job->tier ? job->tier : 1);
+    if (wpc <= 0) wpc = 1;
+    uint64_t waves = uint64_t(di.cus) * uint64_t(wpc);
+    if (job->total_items < waves) waves = job->total_items;
+    job->waves = int(waves);
+    size_t sb = 0, b = 0;
+    (void)compute_offsets(*job, &sb, &b);
+    job->stage_bytes = sb;
+    job->bytes = b;
+    return QUBO_OK;
+}
+
+// Fill the staging image and device pointers for allocation d_mem.
+qubo_status_t job_bind(Job *job, void *d_mem)
+{
+    size_t sb = 0, b = 0;
+    JobOffsets o = compute_offsets(*job, &sb, &b);
+    unsigned char *base = static_cast<unsigned char *>(d_mem);
+    job->d_mem = d_mem;
+    job->stage.assign(sb, 0);
+    job->d_insts = reinterpret_cast<qk::Inst *>(base + o.insts);
+    job->d_counter = reinterpret_cast<unsigned long long *>(base + o.counter);
+    job->d_res = reinterpret_cast<qk::ItemRes *>(base + o.res);
+    job->d_out = reinterpret_cast<qk::FinalRes *>(base + o.out);
+    std::vector<qk::Inst> insts(job->plans.size());
+    uint64_t item = 0;
+    for (size_t i = 0; i < job->plans.size(); i++) {
+        const qplan::Plan &P = job->plans[i];
+        qk::Inst &I = insts[i];
+        I.T = reinterpret_cast<const int32_t *>(base + o.T[i]);
+        I.M = reinterpret_cast<int32_t *>(base + o.M[i]);
+        I.EB = reinterpret_cast<int32_t *>(base + o.EB[i]);
+        I.S = reinterpret_cast<int32_t *>(base + o.S[i]);
+        I.K = reinterpret_cast<int32_t *>(base + o.K[i]);
+        I.Qf = job->qf[i] ? reinterpret_cast<const float *>(base + o.Qf[i]) : nullptr;
+        I.n = P.n;
+        I.A = P.A;
+        I.B = P.B;
+        I.L = P.L;
+        I.direct = P.direct ? 1 : 0;
+        I.pad = 0;
+        I.item_begin = item;
+        item += P.direct ? 0 : P.items;
+        I.item_end = item;
+        const size_t nn = size_t(P.n) * P.n;
+        std::memcpy(job->stage.data() + o.T[i], P.T.data(), nn * sizeof(int32_t));
+        if (job->qf[i]) std::memcpy(job->stage.data() + o.Qf[i], job->qf[i], nn * sizeof(float));
+    }
+    std::memcpy(job->stage.data() + o.insts, insts.data(), insts.size() * sizeof(qk::Inst));
+    return QUBO_OK;
+}
+
+qubo_status_t job_enqueue_kernels(const Job &job, hipStream_t stream, hipEvent_t walk_begin,
+                                  hipEvent_t walk_end)
+{
+    const int ni = int(job.plans.size());
+    QRT_HIP(qk::launch_tables(job.d_insts, ni, job.max_A, job.d_counter, stream), "tables kernel");
+    if (walk_begin) QRT_HIP(hipEventRecord(walk_begin, stream), "hipEventRecord");
+    if (job.total_items > 0)
+        QRT_HIP(qk::launch_walk(job.mcols, job.tier, job.d_insts, ni, job.total_items, job.d_counter,
+                                job.d_res, job.waves, stream),
+                "walk kernel");
+    if (walk_end) QRT_HIP(hipEventRecord(walk_end, stream), "hipEventRecord");
+    QRT_HIP(qk::launch_finish(job.d_insts, ni, job.d_res, job.d_out, stream), "finish kernel");
+    return QUBO_OK;
+}
+
+qubo_status_t job_result(const Job &job, int i, const qk::FinalRes &fr, qubo_result_t *out)
+{
+    const qplan::Plan &P = job.plans[size_t(i)];
+    if (fr.status != 0) {
+        set_error("internal self-check failed (status " + std::to_string(fr.status) + ")");
+        return QUBO_EINTERNAL;
+    }
+    std::memset(out, 0, sizeof(*out));
+    out->best.energy_i = fr.E;
+    out->best.index = fr.index;
+    out->best.energy = (P.dtype == QUBO_FP32) ? fr.E64 : double(fr.E);
+    out->tol = (P.dtype == QUBO_FP32) ? 2.0 * P.eps_q : 0.0;
+    out->p = P.p;
+    out->A = P.direct ? P.n : P.A;
+    out->B = P.B;
+    out->L = P.L;
+    out->tier = P.tier;
+    out->states = (P.n >= 64) ? ~0ull : (1ull << P.n);
+    return QUBO_OK;
+}
+
+}  // namespace qrt
+
+// ------------------------------------------------------------------ C ABI
+
+namespace {
+
+hipStream_t thread_stream(qubo_status_t *st)
+{
+    thread_local hipStream_t s = nullptr;
+    thread_local int dev = -1;
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) {
+        *st = qrt::device_error("hipGetDevice", hipErrorNoDevice);
+        return nullptr;
+    }
+    if (!s || dev != cur) {
+        hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            *st = qrt::device_error("hipStreamCreate", e);
+            s = nullptr;
+            return nullptr;
+        }
+        dev = cur;
+    }
+    *st = QUBO_OK;
+    return s;
+}
+
+qubo_status_t solve_planned(qrt::Job &job, hipStream_t stream, int waves_per_cu, qubo_result_t *out)
+{
+    using clock = std::chrono::steady_clock;
+    const auto t0 = clock::now();
+    qubo_status_t st = qrt::job_layout(&job, waves_per_cu);
+    if (st != QUBO_OK) return st;
+    void *d_mem = nullptr;
+    QRT_HIP(hipMallocAsync(&d_mem, job.bytes, stream), "hipMallocAsync");
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    qubo_status_t rs = QUBO_OK;
+    qk::FinalRes fr{};
+    do {
+        if ((rs = qrt::job_bind(&job, d_mem)) != QUBO_OK) break;
+        hipError_t e;
+        if ((e = hipEventCreate(&ev0)) != hipSuccess || (e = hipEventCreate(&ev1)) != hipSuccess) {
+            rs = qrt::device_error("hipEventCreate", e);
+            break;
+        }
+        if ((e = hipMemcpyAsync(d_mem, job.stage.data(), job.stage_bytes, hipMemcpyHostToDevice,
+                                stream)) != hipSuccess) {
+            rs = qrt::device_error("hipMemcpyAsync H2D", e);
+            break;
+        }
+        if ((rs = qrt::job_enqueue_kernels(job, stream, ev0, ev1)) != QUBO_OK) break;
+        if ((e = hipMemcpyAsync(&fr, job.d_out, sizeof(fr), hipMemcpyDeviceToHost, stream)) !=
+            hipSuccess) {
+            rs = qrt::device_error("hipMemcpyAsync D2H", e);
+            break;
+        }
+    } while (false);
+    hipError_t ef = hipFreeAsync(d_mem, stream);
+    hipError_t es = hipStreamSynchronize(stream);
+    float ms = 0.f;
+    if (rs == QUBO_OK && es == hipSuccess) (void)hipEventElapsedTime(&ms, ev0, ev1);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    if (rs != QUBO_OK) return rs;
+    if (es != hipSuccess) return qrt::device_error("hipStreamSynchronize", es);
+    if (ef != hipSuccess) return qrt::device_error("hipFreeAsync", ef);
+    st = qrt::job_result(job, 0, fr, out);
+    if (st != QUBO_OK) return st;
+    out->kernel_ms = ms;
+    out->total_ms = std::chrono::duration<double, std::milli>(clock::now() - t0).count();
+    return QUBO_OK;
+}
+
+qubo_status_t check_k(int k, int n, qubo_state_t *topk)
+{
+    if (k < 0 || k > 1024) {
+        qrt::set_error("k must be in [0, 1024]");
+        return QUBO_EINVAL;
+    }
+    if (k > 1) {
+        if (!topk) {
+            qrt::set_error("topk output required for k > 1");
+            return QUBO_EINVAL;
+        }
+        if (n < 11 && (1 << n) < k) {
+            qrt::set_error("k exceeds the number of states");
+            return QUBO_EINVAL;
+        }
+        qrt::set_error("k > 1 is not supported by this build");
+        return QUBO_EINVAL;
+    }
+    return QUBO_OK;
+}
+
+qubo_status_t solve_host(const void *Q, int n, qubo_dtype_t dtype, int k, const qubo_options_t *opt,
+                         hipStream_t stream, qubo_result_t *out, qubo_state_t *topk)
+{
+    if (!out) {
+        qrt::set_error("null output");
+        return QUBO_EINVAL;
+    }
+    qubo_status_t st = check_k(k, n, topk);
+    if (st != QUBO_OK) return st;
+    qrt::Job job;
+    job.plans.resize(1);
+    std::string msg;
+    st = qplan::make_plan(Q, n, dtype, opt, &job.plans[0], &msg);
+    if (st != QUBO_OK) {
+        qrt::set_error(msg);
+        return st;
+    }
+    job.qf.push_back(dtype == QUBO_FP32 ? static_cast<const float *>(Q) : nullptr);
+    st = solve_planned(job, stream, opt ? opt->waves_per_cu : 0, out);
+    if (st == QUBO_OK && k == 1 && topk) topk[0] = out->best;
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+qubo_status_t qubo_solve_ex(const void *Q, int n, qubo_dtype_t dtype, int k,
+                            const qubo_options_t *opt, qubo_result_t *out, qubo_state_t *topk)
+{
+    try {
+        qrt::set_error("");
+        qubo_status_t st;
+        hipStream_t s = thread_stream(&st);
+        if (st != QUBO_OK) return st;
+        return solve_host(Q, n, dtype, k, opt, s, out, topk);
+    } catch (const std::bad_alloc &) {
+        qrt::set_error("host allocation failed");
+        return QUBO_ENOMEM;
+    } catch (...) {
+        qrt::set_error("unexpected exception");
+        return QUBO_EINTERNAL;
+    }
+}
+
+qubo_status_t qubo_solve(const void *Q, int n, qubo_dtype_t dtype, int k, qubo_result_t *out,
+                         qubo_state_t *topk)
+{
+    return qubo_solve_ex(Q, n, dtype, k, nullptr, out, topk);
+}
+
+qubo_status_t qubo_solve_device(const void *dQ, int n, qubo_dtype_t dtype, int k, void *hip_stream,
+                                qubo_result_t *out, qubo_state_t *topk)
+{
+    try {
+        qrt::set_error("");
+        if (!dQ || n < 1 || n > qplan::kMaxN) {
+            qrt::set_error("bad device Q or n");
+            return QUBO_EINVAL;
+        }
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        // The planner's fold and exactness proof run on the host over the
+        // n x n input (at most 14.4 KB), so fetch it first.
+        std::vector<uint32_t> hq(size_t(n) * n);
+        QRT_HIP(hipMemcpyAsync(hq.data(), dQ, hq.size() * 4, hipMemcpyDeviceToHost, s),
+                "hipMemcpyAsync Q D2H");
+        QRT_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+        return solve_host(hq.data(), n, dtype, k, nullptr, s, out, topk);
+    } catch (const std::bad_alloc &) {
+        qrt::set_error("host allocation failed");
+        return QUBO_ENOMEM;
+    } catch (...) {
+        qrt::set_error("unexpected exception");
+        return QUBO_EINTERNAL;
+    }
+}
+
+qubo_status_t qubo_plan_info(const void *Q, int n, qubo_dtype_t dtype, const qubo_options_t *opt,
+                             qubo_plan_info_t *info, int32_t *T_out)
+{
+    try {
+        qrt::set_error("");
+        if (!info) {
+            qrt::set_error("null info");
+            return QUBO_EINVAL;
+        }
+        qplan::Plan P;
+        std::string msg;
+        qubo_status_t st = qplan::make_plan(Q, n, dtype, opt, &P, &msg);
+        if (st != QUBO_OK) {
+            qrt::set_error(msg);
+            return st;
+        }
+        info->n = P.n;
+        info->A = P.A;
+        info->B = P.B;
+        info->L = P.L;
+        info->tier = P.tier;
+        info->direct = P.direct ? 1 : 0;
+        info->p = P.p;
+        info->eps_q = P.eps_q;
+        info->sum_abs_t = P.sum_abs;
+        info->items = P.items;
+        if (T_out) std::memcpy(T_out, P.T.data(), P.T.size() * sizeof(int32_t));
+        return QUBO_OK;
+    } catch (...) {
+        qrt::set_error("unexpected exception");
+        return QUBO_EINTERNAL;
+    }
+}
+
+const char *qubo_last_error(void) { return qrt::last_error_cstr(); }
+
+const char *qubo_version(void) { return "qubo-mi355x 0.1"; }
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+"""GPU parity: the HIP solver against the CPU oracle, element by element.
+
+Every case runs through the C ABI (ctypes binding); int32 results must match
+the oracle's (E*, lowest index) exactly.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from conftest import GOLDEN
+from paper_2607_04857_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def q():
+    import paper_2607_04857_amd as q
+    q.lib()
+    return q
+
+
+def _check(q, orc, Q, **kw):
+    got = q.solve(Q, **kw)
+    exp = orc.solve(Q, k=1)[0]
+    print(f"n={Q.shape[0]} {kw} got=({got.energy_i},{got.index}) exp={exp} tier={got.tier}",
+          flush=True)
+    assert (got.energy_i, got.index) == exp
+    return got
+
+
+@pytest.mark.parametrize("n", list(range(1, 15)))
+def test_direct_path(q, orc, n):
+    got = _check(q, orc, inputs.uniform_int(n, -100, 100, 1000 + n))
+    assert got.tier == 0
+
+
+@pytest.mark.parametrize("n", [15, 16, 17, 19, 22])
+def test_walk_small(q, orc, n):
+    got = _check(q, orc, inputs.uniform_int(n, -1000, 1000, 2000 + n))
+    assert got.tier >= 1 and got.A + got.B == n
+
+
+@pytest.mark.parametrize("B", [6, 7, 8, 9, 10])
+@pytest.mark.parametrize("L", [5, 7, 0])
+def test_split_invariance(q, orc, B, L):
+    Q = inputs.uniform_int(21, -500, 500, 77)
+    _check(q, orc, Q, B=B, L=L)
+
+
+def test_ties_zero_matrix(q, orc):
+    for n in (15, 18):
+        _check(q, orc, np.zeros((n, n), dtype=np.int32))
+
+
+def test_ties_diagonal(q, orc):
+    rng = np.random.default_rng(5)
+    d = rng.integers(-3, 3, size=19, endpoint=True)
+    d[::4] = 0
+    _check(q, orc, np.diag(d).astype(np.int32))
+
+
+def test_fold_full_matrix(q, orc):
+    _check(q, orc, inputs.full_int(18, -300, 300, 9))
+
+
+def test_fp32(q, orc):
+    for n, seed in ((16, 1), (20, 2)):
+        Q = inputs.normal_fp32(n, seed)
+        got = q.solve(Q)
+        E, idx = orc.solve(Q, k=1)[0]
+        assert abs(got.energy - E) <= got.tol
+        assert got.tol <= 1e-5 * np.abs(Q.astype(np.float64)).sum()
+        assert got.index == idx or got.energy <= E + got.tol
+
+
+def _golden():
+    with open(os.path.join(GOLDEN, "oracle_results.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", ["n24_int_u100_s1", "n30_int_u1000_s10", "n36_int_u1000_s2",
+                                  "n36_planted_u1000_s3"])
+def test_stored_oracle_results(q, name):
+    g = _golden()
+    if name not in g:
+        pytest.skip("stored value not generated")
+    e = g[name]
+    Q = getattr(inputs, e["generator"])(**e["kwargs"])
+    if e["generator"] == "planted":
+        Q = Q[0]
+    got = q.solve(Q)
+    print(name, got.energy_i, got.index, e["best"], f"{got.kernel_ms:.2f} ms", flush=True)
+    assert [got.energy_i, got.index] == e["best"]
+
+
+def test_planted_n44(q, orc):
+    Q, xstar = inputs.planted(44, -10000, 10000, 8)
+    got = q.solve(Q)
+    istar = orc.index_of(xstar)
+    print("planted44", got.energy_i, got.index, istar, f"{got.kernel_ms:.1f} ms", flush=True)
+    assert got.index == istar
+    assert got.energy_i == orc.energy(Q, istar)
