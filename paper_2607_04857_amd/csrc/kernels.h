@@ -9,8 +9,12 @@
 //   EB  [2^B]         suffix energies E_s(U_B) (Sec. III-A, preprocessing 2)
 //   S   [A][64]       S[w][l] = T[min(l,w)][max(l,w)] for l != w < A, else 0:
 //                     the prefix couplings, one lane per variable
-//   K   [3][16]       bound constants of the tier-2 walk (per-offset column
-//                     minima of the static low-level row combinations)
+//   K   [6][16]       (all instances' K tables are contiguous) tier-2 bound constants per super-block offset o and
+//                     table (0: o < 16; 1: o >= 16, level-4 bit rising;
+//                     2: o >= 16, falling): rows 0..2 hold C2 = ELOW + D,
+//                     rows 3..5 hold D, where D is the minimum over all 2^B
+//                     columns of E_sd(o) - E_sd(super-block start) and ELOW the
+//                     low-low coupling energy of the low pattern at o
 //   Qf  [n][n] fp32   caller's float32 Q (fp32 instances only, for rescoring)
 #pragma once
 
@@ -23,6 +27,7 @@ constexpr int kWave = 64;
 constexpr int kSuperLog = 5;          // unrolled super-block: 32 Gray steps
 constexpr int kLowLevels = 4;         // Gray levels with static patterns in a super-block
 constexpr int kPatterns = 1 << kLowLevels;
+constexpr int kKTable = 6 * kPatterns;  // ints in the per-instance K table
 constexpr int kVgprLevels = 12;       // M_int rows of levels 0..11 held in VGPRs
 constexpr int32_t kNoEnergy = 1 << 30;  // above every energy the walk can meet
 
@@ -58,10 +63,11 @@ struct FinalRes {
 hipError_t launch_tables(const Inst *d_insts, int n_inst, int max_A, unsigned long long *d_counter,
                          hipStream_t stream);
 
-// Persistent Gray walk over all items; `waves` resident wavefronts.
+// Persistent Gray walk over all items; `waves` resident wavefronts.  d_k is
+// the contiguous array of every instance's K table (instance i at i*kKTable).
 hipError_t launch_walk(int mcols, int tier, const Inst *d_insts, int n_inst, uint64_t total_items,
-                       unsigned long long *d_counter, ItemRes *d_res, int waves,
-                       hipStream_t stream);
+                       unsigned long long *d_counter, ItemRes *d_res, const int32_t *d_k,
+                       int waves, hipStream_t stream);
 
 // Resident walk wavefronts per CU for a variant (occupancy query, >= 1).
 int walk_occupancy(int mcols, int tier);

@@ -185,22 +185,93 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
         if (l < A && l != w) v = (l < w) ? T[l * n + w] : T[w * n + l];
         I.S[e] = v;
     }
+    if (blockIdx.x != 0) return;
+    // Tier-2 bound constants.  Inside a 32-step super-block the four lowest
+    // Gray levels follow the static pattern p(o) = g(o) & 15 from 0, and the
+    // level-4 bit moves once (by +-1) at o = 16, so
+    //   E_sd(o) - E_sd(0) = sum_{t<4} p_t(o) M[A-1-t] + [o >= 16] c4 M[A-5].
+    // D = its minimum over all 2^B columns, a lower bound of how far the
+    // chunk minimum can fall from its value at the super-block start.
+    __shared__ int32_t red[256];
+    int32_t mcol[4][5];   // M rows of levels 0..4 at this thread's columns
+    for (int k = 0; k < 4; k++) {
+        const uint32_t col = threadIdx.x + 256u * uint32_t(k);
+        for (int t = 0; t < 5; t++) {
+            int32_t m = 0;
+            if (col < NS)
+                for (int b = 0; b < B; b++)
+                    if ((col >> (B - 1 - b)) & 1u) m += T[(A - 1 - t) * n + A + b];
+            mcol[k][t] = m;
+        }
+    }
+    for (int tab = 0; tab < 3; tab++) {
+        const int c4 = tab == 0 ? 0 : (tab == 1 ? 1 : -1);
+        for (int o16 = 0; o16 < kPatterns; o16++) {
+            const int o = tab == 0 ? o16 : kPatterns + o16;
+            const int pat = (o ^ (o >> 1)) & (kPatterns - 1);
+            int32_t mn = INT32_MAX;
+            for (int k = 0; k < 4; k++) {
+                if (threadIdx.x + 256u * uint32_t(k) >= NS) continue;
+                int32_t v = c4 * mcol[k][4];
+                for (int t = 0; t < 4; t++)
+                    if ((pat >> t) & 1) v += mcol[k][t];
+                mn = min(mn, v);
+            }
+            red[threadIdx.x] = mn;
+            __syncthreads();
+            for (int off = 128; off > 0; off >>= 1) {
+                if (int(threadIdx.x) < off) red[threadIdx.x] = min(red[threadIdx.x], red[threadIdx.x + off]);
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) {
+                int32_t elow = 0;   // couplings among the set low variables
+                for (int t = 0; t < 4; t++)
+                    for (int u = t + 1; u < 4; u++)
+                        if (((pat >> t) & 1) && ((pat >> u) & 1)) elow += T[(A - 1 - u) * n + (A - 1 - t)];
+                I.K[(3 + tab) * kPatterns + o16] = red[0];
+                I.K[tab * kPatterns + o16] = elow + red[0];
+            }
+            __syncthreads();
+        }
+    }
 }
 
 // ---------------------------------------------------------------- walk
 
+// Wave-wide minimum for the tier-2 super-block base: DPP inside each row of
+// 16 lanes, then row broadcasts, result in lane 63.
+__device__ __forceinline__ int32_t wave_min_bcast(int32_t v)
+{
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xF, 0xF, false));  // row_ror:4
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xF, 0xF, false));  // row_ror:8
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// TIER 1: the chunk minimum (v_min3 tree) is compared with the threshold at
+//         every Gray step.
+// TIER 2: an exact wave minimum W0 is taken once per 32-step super-block;
+//         at offset o the chunk minimum is at least W0 + D(o) (table K), so
+//         the step needs only the scalar test W0 <= THR - D(o); the exact
+//         minimum is formed only when that test passes.
 template <int MC, int TIER>
 __global__ __launch_bounds__(kWave) void walk_kernel(const Inst *__restrict__ insts, int n_inst,
                                                      uint64_t total_items,
                                                      unsigned long long *__restrict__ counter,
-                                                     ItemRes *__restrict__ res)
+                                                     ItemRes *__restrict__ res,
+                                                     const int32_t *__restrict__ kall)
 {
-    static_assert(TIER == 1, "tier");
+    static_assert(TIER == 1 || TIER == 2, "tier");
     constexpr int G = kVgprLevels;
+    constexpr int H16 = kPatterns;   // steps per half super-block
     const int lane = int(threadIdx.x);
 
     int cur = -1;
     const int32_t *M = nullptr, *EB = nullptr, *S = nullptr;
+    int kbase = 0;                // this instance's K table: kall[kbase ...] (scalar loads)
     int A = 0, L = 0;
     uint64_t item_begin = 0;
     int32_t R[G][MC];        // M_int rows of Gray levels 0..G-1 (variable A-1-t)
@@ -229,6 +300,7 @@ __global__ __launch_bounds__(kWave) void walk_kernel(const Inst *__restrict__ in
             M = I.M;
             EB = I.EB;
             S = I.S;
+            kbase = lo * kKTable;
             A = I.A;
             L = I.L;
             item_begin = I.item_begin;
@@ -247,7 +319,9 @@ __global__ __launch_bounds__(kWave) void walk_kernel(const Inst *__restrict__ in
                 constexpr int t = decltype(tc)::value;
                 static_for<0, kLowLevels>([&](auto uc) {
                     constexpr int u = decltype(uc)::value;
-                    Sll[t][u] = (t == u) ? 0 : S[(A - 1 - u) * kWave + (A - 1 - t)];
+                    // loads through the descriptor's generic pointers count as
+                    // divergent; readfirstlane keeps these constants in SGPRs
+                    Sll[t][u] = (t == u) ? 0 : sread(S[(A - 1 - u) * kWave + (A - 1 - t)]);
                 });
             });
             CR[0] = 0;
@@ -295,8 +369,9 @@ __global__ __launch_bounds__(kWave) void walk_kernel(const Inst *__restrict__ in
             constexpr int t = decltype(tc)::value;
             H[t] = __builtin_amdgcn_readlane(F, A - 1 - t);
         });
-        // THR[p] = best - E_p(low pattern p): the chunk holds a candidate when
-        // its minimum E_sd is <= THR of the current pattern.
+
+        // TIER 1: THR[p] = best - E_p(low pattern p): the chunk holds a
+        // candidate when its minimum E_sd is <= THR of the current pattern.
         int32_t THR[kPatterns];
         auto build_thr = [&]() {
             THR[0] = best - Enl;
@@ -307,7 +382,29 @@ __global__ __launch_bounds__(kWave) void walk_kernel(const Inst *__restrict__ in
                 THR[p] = THR[pp] - H[t] - CR[p];
             });
         };
-        build_thr();
+        // TIER 2: TP[o'] = best - E_p(pattern at offset o) - D(o) for the 16
+        // offsets of the current half super-block (table tab of K).
+        int32_t TP[H16];
+        auto build_tp = [&](int half, int tab) {
+            const int32_t base = best - Enl;
+            int32_t hs = half ? H[kLowLevels - 1] : 0;   // pattern 8 opens the second half
+            static_for<0, H16>([&](auto oc) {
+                constexpr int o2 = decltype(oc)::value;
+                if constexpr (o2 > 0) {
+                    // pattern changes by one bit between consecutive offsets
+                    constexpr int pa0 = (o2 - 1) ^ ((o2 - 1) >> 1), pa1 = o2 ^ (o2 >> 1);
+                    constexpr int t = cx_ctz(pa0 ^ pa1);
+                    // first half walks the patterns g(o2); the second half walks
+                    // g(o2) ^ 8: the same bit sequence with bit 3 inverted
+                    constexpr bool rise0 = ((pa1 >> t) & 1) != 0;
+                    const bool rise = (half && t == kLowLevels - 1) ? !rise0 : rise0;
+                    hs = rise ? hs + H[t] : hs - H[t];
+                }
+                TP[o2] = base - hs - kall[kbase + tab * kPatterns + o2];
+            });
+        };
+        if constexpr (TIER == 1) build_thr();
+        else build_tp(0, 0);
 
         // A non-low prefix variable w flips (direction up: 0 -> 1).
         auto nonlow_flip = [&](int w, bool up, int32_t Scol) {
@@ -323,36 +420,50 @@ __global__ __launch_bounds__(kWave) void walk_kernel(const Inst *__restrict__ in
                 constexpr int t = decltype(tc)::value;
                 H[t] = __builtin_amdgcn_readlane(F, A - 1 - t);
             });
-            build_thr();
         };
 
         int32_t itemE = kNoEnergy;
         uint64_t itemRow = 0;
         int found = 0;
+        int32_t W0 = 0;    // TIER 2: exact wave minimum at the super-block start
+        int tab2 = 0;      // TIER 2: K table of the current half
+
+        // Candidate test at Gray step i with chunk minimum lm and threshold thr.
+        auto candidate = [&](int32_t lm, int32_t thr, uint64_t i) {
+            if (__builtin_amdgcn_ballot_w64(lm <= thr)) {
+                const int32_t wmin = wave_min(lm);
+                const int32_t Ec = wmin + (best - thr);   // + E_p
+                const uint64_t rc = i ^ (i >> 1);
+                if (Ec < best || (Ec == best && rc < bestRow)) {
+                    const int32_t d = Ec - best;
+                    best = Ec;
+                    bestRow = rc;
+                    itemE = Ec;
+                    itemRow = rc;
+                    found = 1;
+                    static_for<0, kPatterns>([&](auto pc) {
+                        constexpr int p = decltype(pc)::value;
+                        if constexpr (TIER == 1) THR[p] += d;
+                        else TP[p] += d;
+                    });
+                }
+            }
+        };
 
         for (uint64_t sb = sb0; sb < sbEnd; sb++) {
             static_for<0, 32>([&](auto oc) {
                 constexpr int o = decltype(oc)::value;
                 constexpr int pat = (o ^ (o >> 1)) & (kPatterns - 1);
-                // ---- evaluate the chunk of Gray step sb*32 + o
-                const int32_t lm = tree_min<MC>(E);
-                const int32_t thr = THR[pat];
-                if (__builtin_amdgcn_ballot_w64(lm <= thr)) {
-                    const int32_t wmin = wave_min(lm);
-                    const int32_t Ec = wmin + (best - thr);   // + E_p
-                    const uint64_t i = (sb << kSuperLog) | uint64_t(o);
-                    const uint64_t rc = i ^ (i >> 1);
-                    if (Ec < best || (Ec == best && rc < bestRow)) {
-                        const int32_t d = Ec - best;
-                        best = Ec;
-                        bestRow = rc;
-                        itemE = Ec;
-                        itemRow = rc;
-                        found = 1;
-                        static_for<0, kPatterns>([&](auto pc) {
-                            constexpr int p = decltype(pc)::value;
-                            THR[p] += d;
-                        });
+                const uint64_t i = (sb << kSuperLog) | uint64_t(o);
+                // ---- evaluate the chunk of Gray step i
+                if constexpr (TIER == 1) {
+                    candidate(tree_min<MC>(E), THR[pat], i);
+                } else {
+                    if constexpr (o == 0) W0 = wave_min_bcast(tree_min<MC>(E));
+                    if (W0 <= TP[o % H16]) {
+                        const int32_t thr =
+                            TP[o % H16] + kall[kbase + (3 + tab2) * kPatterns + (o % H16)];
+                        candidate(tree_min<MC>(E), thr, i);
                     }
                 }
                 // ---- flip one prefix bit (Alg. 2: E_sd += delta M_int[k])
@@ -372,6 +483,12 @@ __global__ __launch_bounds__(kWave) void walk_kernel(const Inst *__restrict__ in
                             for (int j = 0; j < MC; j++) E[j] -= R[4][j];
                         }
                         nonlow_flip(A - 5, up, S4);
+                        if constexpr (TIER == 1) {
+                            build_thr();
+                        } else {
+                            tab2 = up ? 1 : 2;
+                            build_tp(1, tab2);
+                        }
                     }
                 } else {
                     if (sb + 1 < sbEnd) {
@@ -401,6 +518,12 @@ __global__ __launch_bounds__(kWave) void walk_kernel(const Inst *__restrict__ in
                             }
                         }
                         nonlow_flip(w, up, S[w * kWave + lane]);
+                        if constexpr (TIER == 1) {
+                            build_thr();
+                        } else {
+                            tab2 = 0;
+                            build_tp(0, 0);
+                        }
                     }
                 }
             });
@@ -505,12 +628,17 @@ hipError_t launch_tables(const Inst *d_insts, int n_inst, int max_A, unsigned lo
 
 template <int MC>
 static hipError_t launch_walk_mc(int tier, const Inst *d_insts, int n_inst, uint64_t total_items,
-                                 unsigned long long *d_counter, ItemRes *d_res, int waves,
-                                 hipStream_t stream)
+                                 unsigned long long *d_counter, ItemRes *d_res,
+                                 const int32_t *d_k, int waves, hipStream_t stream)
 {
-    if (tier != 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((walk_kernel<MC, 1>), dim3(waves), dim3(kWave), 0, stream, d_insts, n_inst,
-                       total_items, d_counter, d_res);
+    if (tier == 1)
+        hipLaunchKernelGGL((walk_kernel<MC, 1>), dim3(waves), dim3(kWave), 0, stream, d_insts,
+                           n_inst, total_items, d_counter, d_res, d_k);
+    else if (tier == 2)
+        hipLaunchKernelGGL((walk_kernel<MC, 2>), dim3(waves), dim3(kWave), 0, stream, d_insts,
+                           n_inst, total_items, d_counter, d_res, d_k);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -518,11 +646,10 @@ template <int MC>
 static int occupancy_mc(int tier)
 {
     int blocks = 0;
-    if (tier != 1) return 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, 1>, kWave, 0) !=
-            hipSuccess ||
-        blocks < 1)
-        return 1;
+    hipError_t e = tier == 2
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, 2>, kWave, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, 1>, kWave, 0);
+    if (e != hipSuccess || blocks < 1) return 1;
     return blocks;
 }
 
@@ -538,15 +665,15 @@ int walk_occupancy(int mcols, int tier)
 }
 
 hipError_t launch_walk(int mcols, int tier, const Inst *d_insts, int n_inst, uint64_t total_items,
-                       unsigned long long *d_counter, ItemRes *d_res, int waves,
-                       hipStream_t stream)
+                       unsigned long long *d_counter, ItemRes *d_res, const int32_t *d_k,
+                       int waves, hipStream_t stream)
 {
     switch (mcols) {
-    case 1: return launch_walk_mc<1>(tier, d_insts, n_inst, total_items, d_counter, d_res, waves, stream);
-    case 2: return launch_walk_mc<2>(tier, d_insts, n_inst, total_items, d_counter, d_res, waves, stream);
-    case 4: return launch_walk_mc<4>(tier, d_insts, n_inst, total_items, d_counter, d_res, waves, stream);
-    case 8: return launch_walk_mc<8>(tier, d_insts, n_inst, total_items, d_counter, d_res, waves, stream);
-    case 16: return launch_walk_mc<16>(tier, d_insts, n_inst, total_items, d_counter, d_res, waves, stream);
+    case 1: return launch_walk_mc<1>(tier, d_insts, n_inst, total_items, d_counter, d_res, d_k, waves, stream);
+    case 2: return launch_walk_mc<2>(tier, d_insts, n_inst, total_items, d_counter, d_res, d_k, waves, stream);
+    case 4: return launch_walk_mc<4>(tier, d_insts, n_inst, total_items, d_counter, d_res, d_k, waves, stream);
+    case 8: return launch_walk_mc<8>(tier, d_insts, n_inst, total_items, d_counter, d_res, d_k, waves, stream);
+    case 16: return launch_walk_mc<16>(tier, d_insts, n_inst, total_items, d_counter, d_res, d_k, waves, stream);
     default: return hipErrorInvalidValue;
     }
 }

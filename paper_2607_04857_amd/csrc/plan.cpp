@@ -13,7 +13,7 @@ namespace {
 constexpr int kDefaultB = 10;
 constexpr int kMinB = 6;           // one column per lane
 constexpr int kMaxB = 10;          // 16 columns per lane (VGPR budget)
-constexpr int kDefaultTier = 1;
+constexpr int kDefaultTier = 2;
 
 }  // namespace
 

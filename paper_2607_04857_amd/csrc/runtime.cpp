@@ -14,8 +14,8 @@ thread_local std::string g_last_error;
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct JobOffsets {
-    size_t insts = 0, counter = 0, res = 0, out = 0;
-    std::vector<size_t> T, Qf, M, EB, S, K;
+    size_t insts = 0, counter = 0, res = 0, out = 0, K = 0;
+    std::vector<size_t> T, Qf, M, EB, S;
 };
 
 }  // namespace
@@ -85,9 +85,9 @@ static JobOffsets compute_offsets(const Job &job, size_t *stage_bytes, size_t *b
         off = align_up(off + NS * sizeof(int32_t), 256);
         o.S.push_back(off);
         off = align_up(off + A * qk::kWave * sizeof(int32_t), 256);
-        o.K.push_back(off);
-        off = align_up(off + (P.direct ? 0 : 3 * qk::kPatterns * sizeof(int32_t)), 256);
     }
+    o.K = off;
+    off = align_up(off + ni * qk::kKTable * sizeof(int32_t), 256);
     o.res = off;
     off = align_up(off + size_t(job.total_items) * sizeof(qk::ItemRes), 256);
     o.out = off;
@@ -144,6 +144,7 @@ qubo_status_t job_bind(Job *job, void *d_mem)
     job->d_counter = reinterpret_cast<unsigned long long *>(base + o.counter);
     job->d_res = reinterpret_cast<qk::ItemRes *>(base + o.res);
     job->d_out = reinterpret_cast<qk::FinalRes *>(base + o.out);
+    job->d_k = reinterpret_cast<int32_t *>(base + o.K);
     std::vector<qk::Inst> insts(job->plans.size());
     uint64_t item = 0;
     for (size_t i = 0; i < job->plans.size(); i++) {
@@ -153,7 +154,7 @@ qubo_status_t job_bind(Job *job, void *d_mem)
         I.M = reinterpret_cast<int32_t *>(base + o.M[i]);
         I.EB = reinterpret_cast<int32_t *>(base + o.EB[i]);
         I.S = reinterpret_cast<int32_t *>(base + o.S[i]);
-        I.K = reinterpret_cast<int32_t *>(base + o.K[i]);
+        I.K = reinterpret_cast<int32_t *>(base + o.K) + i * qk::kKTable;
         I.Qf = job->qf[i] ? reinterpret_cast<const float *>(base + o.Qf[i]) : nullptr;
         I.n = P.n;
         I.A = P.A;
@@ -180,7 +181,7 @@ qubo_status_t job_enqueue_kernels(const Job &job, hipStream_t stream, hipEvent_t
     if (walk_begin) QRT_HIP(hipEventRecord(walk_begin, stream), "hipEventRecord");
     if (job.total_items > 0)
         QRT_HIP(qk::launch_walk(job.mcols, job.tier, job.d_insts, ni, job.total_items, job.d_counter,
-                                job.d_res, job.waves, stream),
+                                job.d_res, job.d_k, job.waves, stream),
                 "walk kernel");
     if (walk_end) QRT_HIP(hipEventRecord(walk_end, stream), "hipEventRecord");
     QRT_HIP(qk::launch_finish(job.d_insts, ni, job.d_res, job.d_out, stream), "finish kernel");

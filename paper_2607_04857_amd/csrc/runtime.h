@@ -49,6 +49,7 @@ struct Job {
     unsigned long long *d_counter = nullptr;
     qk::ItemRes *d_res = nullptr;
     qk::FinalRes *d_out = nullptr;
+    int32_t *d_k = nullptr;              // all K tables, instance i at i * kKTable
 };
 
 // Lay out plans (already made) into a Job; `waves_per_cu` 0 = occupancy.

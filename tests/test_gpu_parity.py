@@ -37,39 +37,53 @@ def test_direct_path(q, orc, n):
     assert got.tier == 0
 
 
+TIERS = [1, 2]
+
+
+@pytest.mark.parametrize("tier", TIERS)
 @pytest.mark.parametrize("n", [15, 16, 17, 19, 22])
-def test_walk_small(q, orc, n):
-    got = _check(q, orc, inputs.uniform_int(n, -1000, 1000, 2000 + n))
-    assert got.tier >= 1 and got.A + got.B == n
+def test_walk_small(q, orc, n, tier):
+    got = _check(q, orc, inputs.uniform_int(n, -1000, 1000, 2000 + n), tier=tier)
+    assert got.tier == tier and got.A + got.B == n
 
 
+@pytest.mark.parametrize("tier", TIERS)
 @pytest.mark.parametrize("B", [6, 7, 8, 9, 10])
 @pytest.mark.parametrize("L", [5, 7, 0])
-def test_split_invariance(q, orc, B, L):
+def test_split_invariance(q, orc, B, L, tier):
     Q = inputs.uniform_int(21, -500, 500, 77)
-    _check(q, orc, Q, B=B, L=L)
+    _check(q, orc, Q, B=B, L=L, tier=tier)
 
 
-def test_ties_zero_matrix(q, orc):
+@pytest.mark.parametrize("tier", TIERS)
+def test_ties_zero_matrix(q, orc, tier):
     for n in (15, 18):
-        _check(q, orc, np.zeros((n, n), dtype=np.int32))
+        _check(q, orc, np.zeros((n, n), dtype=np.int32), tier=tier)
 
 
-def test_ties_diagonal(q, orc):
+@pytest.mark.parametrize("tier", TIERS)
+def test_ties_diagonal(q, orc, tier):
     rng = np.random.default_rng(5)
     d = rng.integers(-3, 3, size=19, endpoint=True)
     d[::4] = 0
-    _check(q, orc, np.diag(d).astype(np.int32))
+    _check(q, orc, np.diag(d).astype(np.int32), tier=tier)
 
 
-def test_fold_full_matrix(q, orc):
-    _check(q, orc, inputs.full_int(18, -300, 300, 9))
+@pytest.mark.parametrize("tier", TIERS)
+def test_all_negative(q, orc, tier):
+    _check(q, orc, np.full((17, 17), -1, dtype=np.int32), tier=tier)
 
 
-def test_fp32(q, orc):
+@pytest.mark.parametrize("tier", TIERS)
+def test_fold_full_matrix(q, orc, tier):
+    _check(q, orc, inputs.full_int(18, -300, 300, 9), tier=tier)
+
+
+@pytest.mark.parametrize("tier", TIERS)
+def test_fp32(q, orc, tier):
     for n, seed in ((16, 1), (20, 2)):
         Q = inputs.normal_fp32(n, seed)
-        got = q.solve(Q)
+        got = q.solve(Q, tier=tier)
         E, idx = orc.solve(Q, k=1)[0]
         assert abs(got.energy - E) <= got.tol
         assert got.tol <= 1e-5 * np.abs(Q.astype(np.float64)).sum()
@@ -81,9 +95,11 @@ def _golden():
         return json.load(f)
 
 
-@pytest.mark.parametrize("name", ["n24_int_u100_s1", "n30_int_u1000_s10", "n36_int_u1000_s2",
-                                  "n36_planted_u1000_s3"])
-def test_stored_oracle_results(q, name):
+@pytest.mark.parametrize("name", ["n24_int_u100_s1", "n30_int_u1000_s10", "n31_int_u10000_s11",
+                                  "n33_int_u100_s12", "n36_int_u1000_s2", "n36_planted_u1000_s3",
+                                  "n28_fp32_s6", "n32_fp32_s13"])
+@pytest.mark.parametrize("tier", TIERS)
+def test_stored_oracle_results(q, name, tier):
     g = _golden()
     if name not in g:
         pytest.skip("stored value not generated")
@@ -91,14 +107,22 @@ def test_stored_oracle_results(q, name):
     Q = getattr(inputs, e["generator"])(**e["kwargs"])
     if e["generator"] == "planted":
         Q = Q[0]
-    got = q.solve(Q)
-    print(name, got.energy_i, got.index, e["best"], f"{got.kernel_ms:.2f} ms", flush=True)
-    assert [got.energy_i, got.index] == e["best"]
+    got = q.solve(Q, tier=tier)
+    print(name, got.energy_i, got.energy, got.index, e["best"], f"{got.kernel_ms:.2f} ms",
+          flush=True)
+    if e["dtype"] == "int32":
+        assert [got.energy_i, got.index] == e["best"]
+    else:
+        E, idx = e["best"]
+        assert abs(got.energy - E) <= got.tol
+        assert got.tol <= 1e-5 * np.abs(Q.astype(np.float64)).sum()
+        assert got.index == idx or got.energy <= E + got.tol
 
 
-def test_planted_n44(q, orc):
+@pytest.mark.parametrize("tier", TIERS)
+def test_planted_n44(q, orc, tier):
     Q, xstar = inputs.planted(44, -10000, 10000, 8)
-    got = q.solve(Q)
+    got = q.solve(Q, tier=tier)
     istar = orc.index_of(xstar)
     print("planted44", got.energy_i, got.index, istar, f"{got.kernel_ms:.1f} ms", flush=True)
     assert got.index == istar
