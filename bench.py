@@ -1,0 +1,172 @@
+"""Benchmark: exhaustive dense-QUBO minimisation on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch]
+
+One step = one complete solve (plan, table build, Gray walk, finish, result
+copy) of the headline workload: a dense n=44 int32 QUBO, entries i.i.d.
+uniform in [-10000, 10000], seed 4, held in device memory (a torch tensor)
+before the timed region starts.  Prints ONE JSON line.
+
+value            = 2^44 * K / (timed seconds)  [states/s, whole job]
+roofline         = the walk kernel (dominant kernel) against the int32 VALU
+                   issue peak of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+                   = 39.32 T int32 lane-ops/s; algorithmic work = 1 int32 add
+                   per state (the Gray update of Sec. III-B); duration = HIP
+                   events around the walk kernel on its own stream.
+cpu_baseline     = the CPU oracle (direct evaluation) timed on this host over a
+                   bounded contiguous index range of the same instance.
+batched          = 4096 instances, n ~ U{20..34}, int32 U[-100,100] (seed 5):
+                   aggregate states/s of one graph replay.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9        # int32 lane-ops/s
+METRIC = ("states/sec on 1 MI355X (single n=44; batched mixed-n) vs VALU peak; "
+          "p50/p99 solve latency")
+HEADLINE = dict(n=44, lo=-10000, hi=10000, seed=4)
+PMC_FILE = os.path.join(ROOT, "profiles", "walk_n44_pmc.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2607_04857_amd", "csrc", "kernels.hip")
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profile():
+    """HBM bytes per walk launch from the committed PMC summary, if still valid."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    txt = open(PMC_FILE).read()
+    m_h = re.search(r"kernels\.hip sha256\[:16\]:\s*`?([0-9a-f]{16})", txt)
+    m_b = re.search(r"HBM bytes per walk launch:\s*([0-9.eE+]+)", txt)
+    if not m_h or not m_b or m_h.group(1) != kernel_hash():
+        return None
+    return float(m_b.group(1))
+
+
+def cpu_baseline(Q, budget_s=12.0):
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    n = Q.shape[0]
+    first = 0x5A5A5A5 << 17          # a fixed contiguous slice of the 2^44 index space
+    probe = 1 << 22
+    t0 = time.perf_counter()
+    oracle.solve_range(Q, first, probe, k=1, threads=threads)
+    rate0 = probe / max(time.perf_counter() - t0, 1e-6)
+    count = int(min(max(rate0 * budget_s, probe), 1 << 34))
+    t0 = time.perf_counter()
+    oracle.solve_range(Q, first, count, k=1, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": count / dt, "unit": "states/s", "cores": threads, "kind": "oracle",
+            "sample": f"direct evaluation of {count} consecutive states (indices "
+                      f"[{first}, {first + count})) of the n={n} instance, {dt:.1f} s"}
+
+
+def batched(q, steps=2):
+    from paper_2607_04857_amd import inputs
+    Qs = inputs.batch(4096, 20, 34, seed=5, kind="int", lo=-100, hi=100)
+    b = q.Batch(Qs)
+    b.run()                                   # warm-up replay
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.run()
+    dt = (time.perf_counter() - t0) / steps
+    states, kms = b.stats()
+    b.close()
+    return {"workload": "4096 dense QUBOs, n~U{20..34}, int32 U[-100,100], seed 5",
+            "states_per_s": states / dt, "ms_per_replay": dt * 1e3,
+            "states": states, "graph_ms": kms}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run one plain device copy of BYTES (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        src = torch.ones(args.copy_probe // 4, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
+        return
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for {args.gpus}); the solve "
+              "shards by Gray-index range across GPUs with one 8-byte MIN reduction, which is "
+              "not built here.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2607_04857_amd as q
+    from paper_2607_04857_amd import inputs
+
+    torch.cuda.set_device(0)
+    Q = inputs.uniform_int(HEADLINE["n"], HEADLINE["lo"], HEADLINE["hi"], HEADLINE["seed"])
+    dQ = torch.from_numpy(Q).to("cuda:0")
+    stream = torch.cuda.current_stream()
+    n = Q.shape[0]
+
+    for _ in range(args.warmup):
+        q.solve_device(dQ, stream=stream)
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = q.solve_device(dQ, stream=stream)
+        kms.append(r.kernel_ms)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    states = float(2 ** n) * args.steps
+    value = states / dt
+    walk_ms = sum(kms) / len(kms)
+    achieved = (2.0 ** n) / (walk_ms / 1e3)          # int32 adds per second in the walk
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "states/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i32",
+        "data": "synthetic",
+        "config": {"workload": "single dense QUBO n=44, int32 Q upper-triangular, entries "
+                               "U[-10000,10000], seed 4", "n": n, "states_per_step": 2 ** n,
+                   "tier": r.tier, "A": r.A, "B": r.B, "L": r.L},
+        "result": {"energy": r.energy_i, "index": r.index},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS,
+                     "traffic": traffic_from_profile(),
+                     "kernel": "walk_kernel<16,%d>" % r.tier, "walk_ms": walk_ms},
+        "paper_context": {"states_per_s": 7.42e12, "hardware": "NVIDIA H100 80GB",
+                          "precision": "int16", "n": 44},
+    }
+    if not args.no_batch:
+        line["batched"] = batched(q)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(Q)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -54,7 +54,7 @@ qubo_status_t batch_build(qubo_batch *b, int count, const void *const *Q, const 
             qrt::set_error("null Q in batch at " + std::to_string(i));
             return QUBO_EINVAL;
         }
-        qubo_status_t st = qplan::make_plan(Q[i], n[i], dtype[i], opt, &plans[size_t(i)], &msg);
+        qubo_status_t st = qplan::make_plan(Q[i], n[i], dtype[i], opt, &plans[size_t(i)], &msg, true);
         if (st != QUBO_OK) {
             qrt::set_error("instance " + std::to_string(i) + ": " + msg);
             return st;

@@ -18,7 +18,7 @@ constexpr int kDefaultTier = 2;
 }  // namespace
 
 qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_options_t *opt,
-                        Plan *out, std::string *msg)
+                        Plan *out, std::string *msg, bool many)
 {
     if (!Q || !out) {
         *msg = "null argument";
@@ -128,10 +128,11 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
     P.mcols = (1 << B) / kWave;
     P.tier = tier;
 
-    // Work items: 2^L consecutive Gray steps each.  Default: about 2^14
-    // items (enough to keep ~2k resident waves busy with a small tail), but
-    // never fewer than 2^9 steps per item so the per-item set-up stays small,
-    // and never more than 2^20 items.
+    // Work items: 2^L consecutive Gray steps each.  Default 2^14 steps (the
+    // per-item set-up, about A*MC adds plus the prefix fields, stays below
+    // 0.3% of the item), the whole prefix range when it is smaller, and never
+    // more than 2^20 items per instance.  A lone instance instead keeps at
+    // least 2^11 items (one per resident wavefront) down to 2^9-step items.
     int L;
     if (opt && opt->L) {
         L = opt->L;
@@ -140,11 +141,10 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
             return QUBO_EINVAL;
         }
     } else {
-        L = P.A - 14;
-        if (L < 9) L = 9;
-        if (P.A - L > 20) L = P.A - 20;
+        L = P.A < 14 ? P.A : 14;
+        if (!many && P.A - L < 11) L = P.A - 11 < 9 ? 9 : P.A - 11;
         if (L > P.A) L = P.A;
-        if (L < kSuper) L = kSuper;
+        if (P.A - L > 20) L = P.A - 20;
     }
     P.L = L;
     P.items = uint64_t(1) << (P.A - L);

@@ -38,7 +38,9 @@ struct Plan {
 };
 
 // Build a plan from a host Q.  Returns QUBO_OK or an error with msg set.
+// `many`: the instance shares its walk launch with others (batch, server),
+// so it needs no item-level parallelism of its own.
 qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_options_t *opt,
-                        Plan *out, std::string *msg);
+                        Plan *out, std::string *msg, bool many = false);
 
 }  // namespace qplan

@@ -1,0 +1,137 @@
+"""C ABI and host-side planning, without a GPU.
+
+Checks that the library loads, exports every entry point include/qubo.h
+declares, and that the planner (fold, int32 exactness bound, fp32 fixed-point
+scale, split and work items) behaves as documented.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2607_04857_amd as q
+from paper_2607_04857_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "qubo.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(qubo_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = q.lib()
+    syms = header_symbols()
+    assert len(syms) >= 18
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert sorted(q.EXPORTS) == syms
+
+
+def test_version_and_last_error():
+    assert q.version().startswith("qubo-mi355x")
+    assert isinstance(q.lib().qubo_last_error(), bytes)
+
+
+def test_plan_fold_identity_on_upper_triangular():
+    Q = inputs.uniform_int(20, -100, 100, 1)
+    info = q.plan_info(Q)
+    assert np.array_equal(info["T"], Q)
+    assert info["sum_abs_t"] == int(np.abs(Q.astype(np.int64)).sum())
+    assert info["A"] + info["B"] == 20 and info["B"] == 10
+    assert info["items"] == 2 ** (info["A"] - info["L"])
+
+
+def test_plan_fold_moves_lower_triangle_up():
+    Q = inputs.full_int(17, -50, 50, 2)
+    T = q.plan_info(Q)["T"].astype(np.int64)
+    Q64 = Q.astype(np.int64)
+    assert np.array_equal(np.tril(T, -1), np.zeros_like(T))
+    assert np.array_equal(np.diag(T), np.diag(Q64))
+    iu = np.triu_indices(17, 1)
+    assert np.array_equal(T[iu], (Q64 + Q64.T)[iu])
+
+
+def test_int32_exactness_bound():
+    n = 16
+    lim = 2 ** 30 - 1
+    Q = np.zeros((n, n), dtype=np.int32)
+    Q[0, 0] = lim                               # sum |T| == 2^30 - 1: accepted
+    assert q.plan_info(Q)["sum_abs_t"] == lim
+    Q[1, 1] = 1                                 # one more: rejected
+    with pytest.raises(q.QuboError) as e:
+        q.plan_info(Q)
+    assert e.value.status == -2
+    # the fold can overflow int32 even when every entry fits: rejected, not wrapped
+    Q = np.zeros((n, n), dtype=np.int32)
+    Q[0, 1] = Q[1, 0] = 2 ** 31 - 1
+    with pytest.raises(q.QuboError):
+        q.plan_info(Q)
+
+
+def test_fp32_fixed_point_scale():
+    Q = inputs.normal_fp32(30, 3)
+    info = q.plan_info(Q)
+    p, T = info["p"], info["T"].astype(np.float64)
+    Td = np.triu(Q.astype(np.float64)) + np.tril(Q.astype(np.float64), -1).T
+    S = np.abs(Td).sum()
+    assert S * 2.0 ** p <= 2 ** 29 < S * 2.0 ** (p + 1)
+    assert np.all(np.abs(T - Td * 2.0 ** p) <= 0.5)
+    nnz = int(np.count_nonzero(Td))
+    assert info["eps_q"] == pytest.approx(nnz * 2.0 ** (-p - 1))
+    assert info["sum_abs_t"] <= 2 ** 29 + nnz / 2
+    assert info["eps_q"] * 2 <= 1e-5 * np.abs(Q.astype(np.float64)).sum()
+
+
+def test_fp32_zero_and_nonfinite():
+    assert q.plan_info(np.zeros((16, 16), dtype=np.float32))["p"] == 0
+    Q = inputs.normal_fp32(16, 4)
+    Q[3, 5] = np.nan
+    with pytest.raises(q.QuboError) as e:
+        q.plan_info(Q)
+    assert e.value.status == -3
+    Q[3, 5] = np.inf
+    with pytest.raises(q.QuboError):
+        q.plan_info(Q)
+
+
+@pytest.mark.parametrize("n", [1, 7, 14])
+def test_tiny_instances_take_the_direct_path(n):
+    info = q.plan_info(inputs.uniform_int(n, -9, 9, n))
+    assert info["direct"] == 1 and info["items"] == 0
+
+
+def test_split_options_and_validation():
+    Q = inputs.uniform_int(24, -100, 100, 5)
+    for B in (6, 8, 10):
+        info = q.plan_info(Q, B=B, L=7)
+        assert (info["B"], info["A"], info["L"]) == (B, 24 - B, 7)
+        assert info["items"] == 2 ** (24 - B - 7)
+    for bad in (dict(B=5), dict(B=11), dict(L=4), dict(L=30), dict(tier=3)):
+        with pytest.raises(q.QuboError) as e:
+            q.plan_info(Q, **bad)
+        assert e.value.status == -1
+
+
+def test_bad_n():
+    for n in (0, 61):
+        with pytest.raises((q.QuboError, ValueError)):
+            q.plan_info(np.zeros((max(n, 1), max(n, 1)), dtype=np.int32)[:n, :n])
+
+
+def test_headline_plan_is_provably_exact():
+    info = q.plan_info(inputs.uniform_int(44, -10000, 10000, 4))
+    assert info["sum_abs_t"] <= 990 * 10000 < 2 ** 30 - 1
+    assert (info["A"], info["B"]) == (34, 10)
+
+
+@pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and
+                    __import__("torch").cuda.is_available(), reason="GPU present")
+def test_solve_without_gpu_fails_loudly():
+    with pytest.raises(q.QuboError) as e:
+        q.solve(inputs.uniform_int(16, -5, 5, 1))
+    assert e.value.status == -5
