@@ -157,6 +157,11 @@ qubo_status_t qubo_server_wait(qubo_server_t *srv, uint64_t ticket, double timeo
  * aggregate states/s since creation. */
 qubo_status_t qubo_server_stats(qubo_server_t *srv, double *p50_ms, double *p99_ms,
                                 double *states_per_s);
+/* Scheduler counters: device memory held by admitted requests now and at
+ * its peak, the peak number of admitted requests, and walk ticks launched. */
+qubo_status_t qubo_server_info(qubo_server_t *srv, size_t *mem_in_use, size_t *mem_peak,
+                               int *active_peak, uint64_t *ticks);
+/* Stops accepting work, finishes every submitted request, frees the server. */
 void qubo_server_destroy(qubo_server_t *srv);
 
 /* Host-only planning, for tests: fold, overflow proof / fp32 scale, split.

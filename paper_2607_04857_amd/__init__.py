@@ -83,6 +83,8 @@ _SIGS = {
     "qubo_server_wait": (_I, [_VP, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(_Result)]),
     "qubo_server_stats": (_I, [_VP, ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "qubo_server_info": (_I, [_VP, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                              ctypes.POINTER(_I), _U64P]),
     "qubo_server_destroy": (None, [_VP]),
     "qubo_plan_info": (_I, [_VP, _I, _I, ctypes.POINTER(_Options), ctypes.POINTER(_PlanInfo),
                             ctypes.POINTER(ctypes.c_int32)]),
@@ -295,6 +297,13 @@ class Server:
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         _check(lib().qubo_server_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return {"p50_ms": a.value, "p99_ms": b.value, "states_per_s": c.value}
+
+    def info(self):
+        a, b, c, d = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int(), ctypes.c_uint64()
+        _check(lib().qubo_server_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                      ctypes.byref(d)))
+        return {"mem_in_use": a.value, "mem_peak": b.value, "active_peak": c.value,
+                "ticks": d.value}
 
     def close(self):
         if self._h:

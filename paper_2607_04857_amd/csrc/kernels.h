@@ -31,18 +31,23 @@ constexpr int kKTable = 6 * kPatterns;  // ints in the per-instance K table
 constexpr int kVgprLevels = 12;       // M_int rows of levels 0..11 held in VGPRs
 constexpr int32_t kNoEnergy = 1 << 30;  // above every energy the walk can meet
 
+struct ItemRes;
+
 struct Inst {
     const int32_t *T;
     int32_t *M;
     int32_t *EB;
     int32_t *S;
-    int32_t *K;
+    int32_t *K;            // this instance's K table (kslot-th table of the K array)
     const float *Qf;
+    ItemRes *res;          // per-item results of this instance, by local item index
     int n, A, B, L;
-    int direct;        // 1: no walk, direct evaluation of all 2^n states
-    int pad;
-    uint64_t item_begin;   // global walk-item range [item_begin, item_end)
+    int direct;            // 1: no walk, direct evaluation of all 2^n states
+    int kslot;             // index of the K table in the launch's K array
+    uint64_t item_begin;   // this launch's walk-item range [item_begin, item_end)
     uint64_t item_end;
+    uint64_t item_local0;  // local index of the instance's item number item_begin
+    uint64_t n_items;      // the instance's total items, 2^(A-L)
 };
 
 struct ItemRes {
@@ -59,22 +64,23 @@ struct FinalRes {
     int32_t pad;
 };
 
-// Builds M, EB, S, K for every instance and zeroes the item counter.
+// Builds M, EB, S, K for every instance and zeroes the item counter
+// (d_counter may be null).
 hipError_t launch_tables(const Inst *d_insts, int n_inst, int max_A, unsigned long long *d_counter,
                          hipStream_t stream);
 
 // Persistent Gray walk over all items; `waves` resident wavefronts.  d_k is
-// the contiguous array of every instance's K table (instance i at i*kKTable).
+// the contiguous array of K tables (instance i's at insts[i].kslot*kKTable).
 hipError_t launch_walk(int mcols, int tier, const Inst *d_insts, int n_inst, uint64_t total_items,
-                       unsigned long long *d_counter, ItemRes *d_res, const int32_t *d_k,
-                       int waves, hipStream_t stream);
+                       unsigned long long *d_counter, const int32_t *d_k, int waves,
+                       hipStream_t stream);
 
 // Resident walk wavefronts per CU for a variant (occupancy query, >= 1).
 int walk_occupancy(int mcols, int tier);
 
-// Per-instance reduction of item results, argmin rescan (or direct
-// evaluation for tiny n) and float64 rescoring.
-hipError_t launch_finish(const Inst *d_insts, int n_inst, const ItemRes *d_res, FinalRes *d_out,
-                         hipStream_t stream);
+// Per-instance reduction of item results (insts[i].res[0..n_items)), argmin
+// rescan (or direct evaluation for tiny n) and float64 rescoring; one
+// FinalRes per descriptor.
+hipError_t launch_finish(const Inst *d_insts, int n_inst, FinalRes *d_out, hipStream_t stream);
 
 }  // namespace qk

@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
                                                      unsigned long long *__restrict__ counter)
 {
     const Inst I = insts[blockIdx.y];
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *counter = 0ull;
+    if (counter && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *counter = 0ull;
     if (I.direct) return;
     const int n = I.n, A = I.A, B = I.B;
     const uint32_t NS = 1u << B;
@@ -261,7 +261,6 @@ template <int MC, int TIER>
 __global__ __launch_bounds__(kWave) void walk_kernel(const Inst *__restrict__ insts, int n_inst,
                                                      uint64_t total_items,
                                                      unsigned long long *__restrict__ counter,
-                                                     ItemRes *__restrict__ res,
                                                      const int32_t *__restrict__ kall)
 {
     static_assert(TIER == 1 || TIER == 2, "tier");
@@ -271,9 +270,10 @@ __global__ __launch_bounds__(kWave) void walk_kernel(const Inst *__restrict__ in
 
     int cur = -1;
     const int32_t *M = nullptr, *EB = nullptr, *S = nullptr;
+    ItemRes *ires = nullptr;
     int kbase = 0;                // this instance's K table: kall[kbase ...] (scalar loads)
     int A = 0, L = 0;
-    uint64_t item_begin = 0;
+    uint64_t item_begin = 0, item_local0 = 0;
     int32_t R[G][MC];        // M_int rows of Gray levels 0..G-1 (variable A-1-t)
     int32_t S4 = 0;          // couplings of the level-4 variable, one lane each
     int32_t diagl = 0;       // T[l][l] on lane l < A
@@ -300,10 +300,12 @@ __global__ __launch_bounds__(kWave) void walk_kernel(const Inst *__restrict__ in
             M = I.M;
             EB = I.EB;
             S = I.S;
-            kbase = lo * kKTable;
+            kbase = I.kslot * kKTable;
             A = I.A;
             L = I.L;
             item_begin = I.item_begin;
+            item_local0 = I.item_local0;
+            ires = I.res;
             static_for<0, G>([&](auto tc) {
                 constexpr int t = decltype(tc)::value;
                 const bool have = t < A;
@@ -341,7 +343,8 @@ __global__ __launch_bounds__(kWave) void walk_kernel(const Inst *__restrict__ in
         }
 
         // ---- item set-up: state g(i0) from scratch
-        const uint64_t i0 = (g - item_begin) << L;
+        const uint64_t qloc = g - item_begin + item_local0;   // the instance's item number
+        const uint64_t i0 = qloc << L;
         const uint64_t sb0 = i0 >> kSuperLog;
         const uint64_t sbEnd = sb0 + (1ull << (L - kSuperLog));
         const uint64_t row0 = i0 ^ (i0 >> 1);
@@ -534,7 +537,7 @@ __global__ __launch_bounds__(kWave) void walk_kernel(const Inst *__restrict__ in
             r.E = found ? itemE : kNoEnergy;
             r.found = found;
             r.row = found ? itemRow : 0ull;
-            res[g] = r;
+            ires[qloc] = r;
         }
     }
 }
@@ -564,7 +567,6 @@ __device__ void block_lexmin(int64_t &bE, uint64_t &bI, int64_t *sE, uint64_t *s
 }
 
 __global__ __launch_bounds__(256) void finish_kernel(const Inst *__restrict__ insts,
-                                                     const ItemRes *__restrict__ res,
                                                      FinalRes *__restrict__ out)
 {
     __shared__ int64_t sE[256];
@@ -579,8 +581,8 @@ __global__ __launch_bounds__(256) void finish_kernel(const Inst *__restrict__ in
         for (uint64_t r = threadIdx.x; r < N; r += blockDim.x) lexmin(bE, bI, energy_int(I.T, n, r), r);
         block_lexmin(bE, bI, sE, sI);
     } else {
-        for (uint64_t k = I.item_begin + threadIdx.x; k < I.item_end; k += blockDim.x) {
-            const ItemRes r = res[k];
+        for (uint64_t k = threadIdx.x; k < I.n_items; k += blockDim.x) {
+            const ItemRes r = I.res[k];
             if (r.found) lexmin(bE, bI, r.E, r.row);
         }
         block_lexmin(bE, bI, sE, sI);
@@ -628,15 +630,15 @@ hipError_t launch_tables(const Inst *d_insts, int n_inst, int max_A, unsigned lo
 
 template <int MC>
 static hipError_t launch_walk_mc(int tier, const Inst *d_insts, int n_inst, uint64_t total_items,
-                                 unsigned long long *d_counter, ItemRes *d_res,
-                                 const int32_t *d_k, int waves, hipStream_t stream)
+                                 unsigned long long *d_counter, const int32_t *d_k, int waves,
+                                 hipStream_t stream)
 {
     if (tier == 1)
         hipLaunchKernelGGL((walk_kernel<MC, 1>), dim3(waves), dim3(kWave), 0, stream, d_insts,
-                           n_inst, total_items, d_counter, d_res, d_k);
+                           n_inst, total_items, d_counter, d_k);
     else if (tier == 2)
         hipLaunchKernelGGL((walk_kernel<MC, 2>), dim3(waves), dim3(kWave), 0, stream, d_insts,
-                           n_inst, total_items, d_counter, d_res, d_k);
+                           n_inst, total_items, d_counter, d_k);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -665,23 +667,22 @@ int walk_occupancy(int mcols, int tier)
 }
 
 hipError_t launch_walk(int mcols, int tier, const Inst *d_insts, int n_inst, uint64_t total_items,
-                       unsigned long long *d_counter, ItemRes *d_res, const int32_t *d_k,
-                       int waves, hipStream_t stream)
+                       unsigned long long *d_counter, const int32_t *d_k, int waves,
+                       hipStream_t stream)
 {
     switch (mcols) {
-    case 1: return launch_walk_mc<1>(tier, d_insts, n_inst, total_items, d_counter, d_res, d_k, waves, stream);
-    case 2: return launch_walk_mc<2>(tier, d_insts, n_inst, total_items, d_counter, d_res, d_k, waves, stream);
-    case 4: return launch_walk_mc<4>(tier, d_insts, n_inst, total_items, d_counter, d_res, d_k, waves, stream);
-    case 8: return launch_walk_mc<8>(tier, d_insts, n_inst, total_items, d_counter, d_res, d_k, waves, stream);
-    case 16: return launch_walk_mc<16>(tier, d_insts, n_inst, total_items, d_counter, d_res, d_k, waves, stream);
+    case 1: return launch_walk_mc<1>(tier, d_insts, n_inst, total_items, d_counter, d_k, waves, stream);
+    case 2: return launch_walk_mc<2>(tier, d_insts, n_inst, total_items, d_counter, d_k, waves, stream);
+    case 4: return launch_walk_mc<4>(tier, d_insts, n_inst, total_items, d_counter, d_k, waves, stream);
+    case 8: return launch_walk_mc<8>(tier, d_insts, n_inst, total_items, d_counter, d_k, waves, stream);
+    case 16: return launch_walk_mc<16>(tier, d_insts, n_inst, total_items, d_counter, d_k, waves, stream);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_finish(const Inst *d_insts, int n_inst, const ItemRes *d_res, FinalRes *d_out,
-                         hipStream_t stream)
+hipError_t launch_finish(const Inst *d_insts, int n_inst, FinalRes *d_out, hipStream_t stream)
 {
-    hipLaunchKernelGGL(finish_kernel, dim3(n_inst), dim3(256), 0, stream, d_insts, d_res, d_out);
+    hipLaunchKernelGGL(finish_kernel, dim3(n_inst), dim3(256), 0, stream, d_insts, d_out);
     return hipGetLastError();
 }
 

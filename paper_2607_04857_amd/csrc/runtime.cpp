@@ -156,15 +156,18 @@ qubo_status_t job_bind(Job *job, void *d_mem)
         I.S = reinterpret_cast<int32_t *>(base + o.S[i]);
         I.K = reinterpret_cast<int32_t *>(base + o.K) + i * qk::kKTable;
         I.Qf = job->qf[i] ? reinterpret_cast<const float *>(base + o.Qf[i]) : nullptr;
+        I.res = job->d_res + item;
         I.n = P.n;
         I.A = P.A;
         I.B = P.B;
         I.L = P.L;
         I.direct = P.direct ? 1 : 0;
-        I.pad = 0;
+        I.kslot = int(i);
         I.item_begin = item;
         item += P.direct ? 0 : P.items;
         I.item_end = item;
+        I.item_local0 = 0;
+        I.n_items = P.direct ? 0 : P.items;
         const size_t nn = size_t(P.n) * P.n;
         std::memcpy(job->stage.data() + o.T[i], P.T.data(), nn * sizeof(int32_t));
         if (job->qf[i]) std::memcpy(job->stage.data() + o.Qf[i], job->qf[i], nn * sizeof(float));
@@ -181,10 +184,10 @@ qubo_status_t job_enqueue_kernels(const Job &job, hipStream_t stream, hipEvent_t
     if (walk_begin) QRT_HIP(hipEventRecord(walk_begin, stream), "hipEventRecord");
     if (job.total_items > 0)
         QRT_HIP(qk::launch_walk(job.mcols, job.tier, job.d_insts, ni, job.total_items, job.d_counter,
-                                job.d_res, job.d_k, job.waves, stream),
+                                job.d_k, job.waves, stream),
                 "walk kernel");
     if (walk_end) QRT_HIP(hipEventRecord(walk_end, stream), "hipEventRecord");
-    QRT_HIP(qk::launch_finish(job.d_insts, ni, job.d_res, job.d_out, stream), "finish kernel");
+    QRT_HIP(qk::launch_finish(job.d_insts, ni, job.d_out, stream), "finish kernel");
     return QUBO_OK;
 }
 

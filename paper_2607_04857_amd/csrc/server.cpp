@@ -1,9 +1,577 @@
+// server.cpp -- continuous-batching solve server.
+//
+// Requests are planned on the submitting thread and queued.  One scheduler
+// thread owns the device stream and runs ticks:
+//   1. admission: queued requests enter device slots, first come first
+//      served, while a slot is free and the device-memory budget allows;
+//      each admitted request gets one allocation (its tables, per-item
+//      results) and a table-build launch; the tables stay resident until it
+//      finishes;
+//   2. one persistent walk launch over a slice of work items from EVERY
+//      admitted request (water-filling: requests with few items left get all
+//      of them, the rest share the remaining per-tick item budget), so a
+//      request arriving while others are on the GPU joins the next tick;
+//   3. a finish launch for requests whose last items ran in this tick, and
+//      one small result download.
+// Ticks alternate between two buffer sets: tick k+1 is enqueued before the
+// host waits for tick k, so the GPU does not idle between ticks.  A request
+// is solved by the same kernels and the same integer arithmetic whether it
+// runs alone or mixed with others, so its result does not depend on the mix.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
 #include "runtime.h"
-extern "C" {
-qubo_status_t qubo_server_create(size_t, int, qubo_server_t **) { qrt::set_error("server pending"); return QUBO_EINTERNAL; }
-qubo_status_t qubo_server_submit(qubo_server_t *, const void *, int, qubo_dtype_t, uint64_t *) { return QUBO_EINTERNAL; }
-qubo_status_t qubo_server_poll(qubo_server_t *, uint64_t, qubo_result_t *) { return QUBO_EINTERNAL; }
-qubo_status_t qubo_server_wait(qubo_server_t *, uint64_t, double, qubo_result_t *) { return QUBO_EINTERNAL; }
-qubo_status_t qubo_server_stats(qubo_server_t *, double *, double *, double *) { return QUBO_EINTERNAL; }
-void qubo_server_destroy(qubo_server_t *) {}
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+enum class RState { Queued, Active, Done, Failed };
+
+struct Request {
+    uint64_t ticket = 0;
+    qrt::Job job;                 // single-instance job
+    std::vector<float> qf;        // owned float32 input
+    Clock::time_point arrival;
+    RState state = RState::Queued;
+    void *d_mem = nullptr;
+    int kslot = -1;
+    qk::Inst base{};              // device descriptor of the whole instance
+    uint64_t next_item = 0;       // next work item to issue
+    qubo_result_t result{};
+    qubo_status_t status = QUBO_OK;
+    std::string error;
+};
+
+struct TickBuf {
+    hipEvent_t done = nullptr;
+    qk::Inst *h_walk = nullptr, *d_walk = nullptr;   // walk descriptors (max_slots)
+    qk::Inst *h_fin = nullptr, *d_fin = nullptr;     // finish descriptors (max_slots)
+    qk::FinalRes *h_out = nullptr, *d_out = nullptr; // finish results (max_slots)
+    std::vector<Request *> finishing;
+    bool inflight = false;
+};
+
+}  // namespace
+
+struct qubo_server {
+    int dev = 0;
+    size_t budget = 0;
+    int max_slots = 0;
+    int waves_cap = 0;            // resident walk waves of the device
+    uint64_t tick_items = 0;      // work items per tick (two per resident wave)
+    hipStream_t stream = nullptr;
+    int32_t *d_karena = nullptr;  // max_slots K tables
+    unsigned long long *d_counter = nullptr;
+    std::vector<int> free_kslots;
+    TickBuf ticks[2];
+    int cur = 0;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request *> queue;
+    std::vector<Request *> active;
+    std::unordered_map<uint64_t, Request *> reqs;
+    uint64_t next_ticket = 1;
+    size_t mem_used = 0, mem_peak = 0;
+    int active_peak = 0;
+    uint64_t n_ticks = 0;
+    bool stop = false;
+    std::string fatal;
+    std::vector<double> lat_ms;
+    double states_done = 0.0;
+    bool have_t0 = false;
+    Clock::time_point t0;
+    std::thread th;
+};
+
+namespace {
+
+double ms_since(Clock::time_point a) { return std::chrono::duration<double, std::milli>(Clock::now() - a).count(); }
+
+void fail_all(qubo_server *s, const std::string &msg)
+{
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->fatal = msg;
+    for (auto &kv : s->reqs) {
+        Request *r = kv.second;
+        if (r->state == RState::Queued || r->state == RState::Active) {
+            r->state = RState::Failed;
+            r->status = QUBO_EDEVICE;
+            r->error = msg;
+        }
+    }
+    s->queue.clear();
+    s->active.clear();
+    s->cv_done.notify_all();
 }
+
+// Called with the tick's event complete: publish results, release memory.
+void complete_tick(qubo_server *s, TickBuf &t)
+{
+    std::vector<Request *> done = std::move(t.finishing);
+    t.finishing.clear();
+    t.inflight = false;
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (size_t i = 0; i < done.size(); i++) {
+        Request *r = done[i];
+        qubo_status_t st = qrt::job_result(r->job, 0, t.h_out[i], &r->result);
+        const double lat = ms_since(r->arrival);
+        if (st != QUBO_OK) {
+            r->status = st;
+            r->error = qrt::last_error_cstr();
+            r->state = RState::Failed;
+        } else {
+            r->result.total_ms = lat;
+            r->result.kernel_ms = 0.0;
+            r->state = RState::Done;
+        }
+        s->lat_ms.push_back(lat);
+        s->states_done += std::ldexp(1.0, r->job.plans[0].n);
+        (void)hipFreeAsync(r->d_mem, s->stream);
+        r->d_mem = nullptr;
+        s->mem_used -= r->job.bytes;
+        s->free_kslots.push_back(r->kslot);
+        s->active.erase(std::find(s->active.begin(), s->active.end(), r));
+    }
+    s->cv_done.notify_all();
+}
+
+// Admit queued requests; returns the newly admitted ones (device set-up pending).
+std::vector<Request *> take_admissions(qubo_server *s)
+{
+    std::vector<Request *> adm;
+    while (!s->queue.empty() && int(s->active.size()) < s->max_slots && !s->free_kslots.empty()) {
+        Request *r = s->queue.front();
+        if (s->mem_used + r->job.bytes > s->budget) break;   // wait for memory to free up
+        s->queue.pop_front();
+        s->mem_used += r->job.bytes;
+        s->mem_peak = std::max(s->mem_peak, s->mem_used);
+        r->kslot = s->free_kslots.back();
+        s->free_kslots.pop_back();
+        r->state = RState::Active;
+        s->active.push_back(r);
+        s->active_peak = std::max(s->active_peak, int(s->active.size()));
+        adm.push_back(r);
+    }
+    return adm;
+}
+
+qubo_status_t setup_request(qubo_server *s, Request *r)
+{
+    QRT_HIP(hipMallocAsync(&r->d_mem, r->job.bytes, s->stream), "hipMallocAsync");
+    qubo_status_t st = qrt::job_bind(&r->job, r->d_mem);
+    if (st != QUBO_OK) return st;
+    // The K table lives in the server's arena so one walk launch sees every
+    // request's table in a single array.
+    qk::Inst I;
+    std::memcpy(&I, r->job.stage.data(), sizeof(I));
+    I.K = s->d_karena + size_t(r->kslot) * qk::kKTable;
+    I.kslot = r->kslot;
+    std::memcpy(r->job.stage.data(), &I, sizeof(I));
+    r->base = I;
+    QRT_HIP(hipMemcpyAsync(r->d_mem, r->job.stage.data(), r->job.stage_bytes, hipMemcpyHostToDevice,
+                           s->stream),
+            "hipMemcpyAsync H2D");
+    QRT_HIP(qk::launch_tables(r->job.d_insts, 1, r->job.max_A, nullptr, s->stream), "tables kernel");
+    return QUBO_OK;
+}
+
+// Enqueue one tick into buffer t; *launched stays false when there was nothing to do.
+qubo_status_t enqueue_tick(qubo_server *s, TickBuf &t, bool *launched)
+{
+    *launched = false;
+    std::vector<Request *> act;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        act = s->active;
+    }
+    // requests still owning unissued items or an unrun finish
+    std::vector<Request *> walkers, finishers;
+    for (Request *r : act) {
+        const qplan::Plan &P = r->job.plans[0];
+        if (P.direct) {
+            if (r->next_item == 0) {   // not yet finished: finish-only request
+                r->next_item = 1;
+                finishers.push_back(r);
+            }
+        } else if (r->next_item < P.items) {
+            walkers.push_back(r);
+        }
+    }
+    // water-filling over the per-tick item budget, fewest remaining first
+    std::sort(walkers.begin(), walkers.end(), [](Request *a, Request *b) {
+        return a->job.plans[0].items - a->next_item < b->job.plans[0].items - b->next_item;
+    });
+    uint64_t budget = s->tick_items, g = 0;
+    int nw = 0;
+    for (size_t k = 0; k < walkers.size(); k++) {
+        Request *r = walkers[k];
+        const uint64_t left = r->job.plans[0].items - r->next_item;
+        const uint64_t share = std::max<uint64_t>(1, budget / (walkers.size() - k));
+        const uint64_t c = std::min(left, share);
+        qk::Inst I = r->base;
+        I.item_begin = g;
+        I.item_end = g + c;
+        I.item_local0 = r->next_item;
+        t.h_walk[nw++] = I;
+        g += c;
+        budget = budget > c ? budget - c : 0;
+        r->next_item += c;
+        if (r->next_item == r->job.plans[0].items) finishers.push_back(r);
+    }
+    if (g == 0 && finishers.empty()) return QUBO_OK;
+    if (g > 0) {
+        QRT_HIP(hipMemcpyAsync(t.d_walk, t.h_walk, size_t(nw) * sizeof(qk::Inst), hipMemcpyHostToDevice,
+                               s->stream),
+                "hipMemcpyAsync tick");
+        QRT_HIP(hipMemsetAsync(s->d_counter, 0, sizeof(unsigned long long), s->stream), "hipMemsetAsync");
+        const int waves = int(std::min<uint64_t>(g, uint64_t(s->waves_cap)));
+        const qrt::Job &j0 = walkers[0]->job;
+        QRT_HIP(qk::launch_walk(j0.mcols, j0.tier, t.d_walk, nw, g, s->d_counter, s->d_karena, waves,
+                                s->stream),
+                "walk kernel");
+    }
+    if (!finishers.empty()) {
+        for (size_t i = 0; i < finishers.size(); i++) t.h_fin[i] = finishers[i]->base;
+        QRT_HIP(hipMemcpyAsync(t.d_fin, t.h_fin, finishers.size() * sizeof(qk::Inst),
+                               hipMemcpyHostToDevice, s->stream),
+                "hipMemcpyAsync finish");
+        QRT_HIP(qk::launch_finish(t.d_fin, int(finishers.size()), t.d_out, s->stream), "finish kernel");
+        QRT_HIP(hipMemcpyAsync(t.h_out, t.d_out, finishers.size() * sizeof(qk::FinalRes),
+                               hipMemcpyDeviceToHost, s->stream),
+                "hipMemcpyAsync results");
+    }
+    t.finishing = std::move(finishers);
+    QRT_HIP(hipEventRecord(t.done, s->stream), "hipEventRecord");
+    t.inflight = true;
+    *launched = true;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->n_ticks++;
+    }
+    return QUBO_OK;
+}
+
+void scheduler(qubo_server *s)
+{
+    if (hipSetDevice(s->dev) != hipSuccess) {
+        fail_all(s, "hipSetDevice failed in the scheduler");
+        return;
+    }
+    for (;;) {
+        std::vector<Request *> adm;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            adm = take_admissions(s);
+            const bool idle = adm.empty() && s->active.empty() && !s->ticks[0].inflight &&
+                              !s->ticks[1].inflight;
+            if (idle) {
+                if (s->stop && s->queue.empty()) break;
+                s->cv_work.wait_for(lk, std::chrono::milliseconds(20));
+                continue;
+            }
+        }
+        for (Request *r : adm) {
+            qubo_status_t st = setup_request(s, r);
+            if (st != QUBO_OK) {
+                fail_all(s, qrt::last_error_cstr());
+                return;
+            }
+        }
+        TickBuf &t = s->ticks[s->cur];
+        if (t.inflight) {
+            // the buffer's previous tick was enqueued two ticks ago
+            if (hipEventSynchronize(t.done) != hipSuccess) {
+                fail_all(s, "tick failed on the device");
+                return;
+            }
+            complete_tick(s, t);
+        }
+        bool launched = false;
+        if (enqueue_tick(s, t, &launched) != QUBO_OK) {
+            fail_all(s, qrt::last_error_cstr());
+            return;
+        }
+        if (launched) {
+            s->cur ^= 1;
+        } else {
+            // nothing new to run: retire the other buffer's tick, if any
+            TickBuf &o = s->ticks[s->cur ^ 1];
+            if (o.inflight) {
+                if (hipEventSynchronize(o.done) != hipSuccess) {
+                    fail_all(s, "tick failed on the device");
+                    return;
+                }
+                complete_tick(s, o);
+            } else {
+                std::unique_lock<std::mutex> lk(s->mu);
+                if (s->queue.empty() || int(s->active.size()) >= s->max_slots)
+                    s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+            }
+        }
+    }
+}
+
+void server_free(qubo_server *s)
+{
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    for (TickBuf &t : s->ticks) {
+        if (t.done) (void)hipEventDestroy(t.done);
+        if (t.h_walk) (void)hipHostFree(t.h_walk);
+        if (t.h_fin) (void)hipHostFree(t.h_fin);
+        if (t.h_out) (void)hipHostFree(t.h_out);
+        if (t.d_walk) (void)hipFree(t.d_walk);
+        if (t.d_fin) (void)hipFree(t.d_fin);
+        if (t.d_out) (void)hipFree(t.d_out);
+    }
+    for (auto &kv : s->reqs) {
+        if (kv.second->d_mem) (void)hipFree(kv.second->d_mem);
+        delete kv.second;
+    }
+    if (s->d_karena) (void)hipFree(s->d_karena);
+    if (s->d_counter) (void)hipFree(s->d_counter);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+qubo_status_t server_init(qubo_server *s, size_t budget, int max_slots)
+{
+    QRT_HIP(hipGetDevice(&s->dev), "hipGetDevice");
+    s->budget = budget;
+    s->max_slots = max_slots;
+    qrt::DeviceInfo di;
+    qubo_status_t st = qrt::device_info(&di);
+    if (st != QUBO_OK) return st;
+    s->waves_cap = di.cus * qk::walk_occupancy(16, 2);
+    s->tick_items = uint64_t(s->waves_cap) * 2;
+    QRT_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "hipStreamCreate");
+    QRT_HIP(hipMalloc(&s->d_karena, size_t(max_slots) * qk::kKTable * sizeof(int32_t)), "hipMalloc");
+    QRT_HIP(hipMalloc(&s->d_counter, sizeof(unsigned long long)), "hipMalloc");
+    for (int k = max_slots - 1; k >= 0; k--) s->free_kslots.push_back(k);
+    for (TickBuf &t : s->ticks) {
+        QRT_HIP(hipEventCreateWithFlags(&t.done, hipEventDisableTiming), "hipEventCreate");
+        const size_t ib = size_t(max_slots) * sizeof(qk::Inst), ob = size_t(max_slots) * sizeof(qk::FinalRes);
+        QRT_HIP(hipHostMalloc(reinterpret_cast<void **>(&t.h_walk), ib, 0), "hipHostMalloc");
+        QRT_HIP(hipHostMalloc(reinterpret_cast<void **>(&t.h_fin), ib, 0), "hipHostMalloc");
+        QRT_HIP(hipHostMalloc(reinterpret_cast<void **>(&t.h_out), ob, 0), "hipHostMalloc");
+        QRT_HIP(hipMalloc(&t.d_walk, ib), "hipMalloc");
+        QRT_HIP(hipMalloc(&t.d_fin, ib), "hipMalloc");
+        QRT_HIP(hipMalloc(&t.d_out, ob), "hipMalloc");
+    }
+    return QUBO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qubo_status_t qubo_server_create(size_t mem_budget_bytes, int max_slots, qubo_server_t **srv)
+{
+    try {
+        qrt::set_error("");
+        if (!srv || max_slots < 1 || max_slots > 65536 || mem_budget_bytes == 0) {
+            qrt::set_error("bad server arguments");
+            return QUBO_EINVAL;
+        }
+        qubo_server *s = new qubo_server();
+        qubo_status_t st = server_init(s, mem_budget_bytes, max_slots);
+        if (st != QUBO_OK) {
+            const std::string keep = qrt::last_error_cstr();
+            server_free(s);
+            qrt::set_error(keep);
+            return st;
+        }
+        s->th = std::thread(scheduler, s);
+        *srv = s;
+        return QUBO_OK;
+    } catch (const std::bad_alloc &) {
+        qrt::set_error("host allocation failed");
+        return QUBO_ENOMEM;
+    } catch (...) {
+        qrt::set_error("unexpected exception");
+        return QUBO_EINTERNAL;
+    }
+}
+
+qubo_status_t qubo_server_submit(qubo_server_t *s, const void *Q, int n, qubo_dtype_t dtype,
+                                 uint64_t *ticket)
+{
+    try {
+        qrt::set_error("");
+        if (!s || !ticket) {
+            qrt::set_error("null argument");
+            return QUBO_EINVAL;
+        }
+        Request *r = new Request();
+        r->job.plans.resize(1);
+        std::string msg;
+        qubo_status_t st = qplan::make_plan(Q, n, dtype, nullptr, &r->job.plans[0], &msg, true);
+        if (st != QUBO_OK) {
+            delete r;
+            qrt::set_error(msg);
+            return st;
+        }
+        if (dtype == QUBO_FP32) {
+            const float *q = static_cast<const float *>(Q);
+            r->qf.assign(q, q + size_t(n) * n);
+            r->job.qf.push_back(r->qf.data());
+        } else {
+            r->job.qf.push_back(nullptr);
+        }
+        st = qrt::job_layout(&r->job, 0);
+        if (st != QUBO_OK) {
+            delete r;
+            return st;
+        }
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (!s->fatal.empty()) {
+            delete r;
+            qrt::set_error(s->fatal);
+            return QUBO_EDEVICE;
+        }
+        if (r->job.bytes > s->budget) {
+            delete r;
+            qrt::set_error("request needs more device memory than the server budget");
+            return QUBO_ENOMEM;
+        }
+        r->ticket = s->next_ticket++;
+        r->arrival = Clock::now();
+        if (!s->have_t0) {
+            s->have_t0 = true;
+            s->t0 = r->arrival;
+        }
+        s->reqs[r->ticket] = r;
+        s->queue.push_back(r);
+        *ticket = r->ticket;
+        s->cv_work.notify_one();
+        return QUBO_OK;
+    } catch (const std::bad_alloc &) {
+        qrt::set_error("host allocation failed");
+        return QUBO_ENOMEM;
+    } catch (...) {
+        qrt::set_error("unexpected exception");
+        return QUBO_EINTERNAL;
+    }
+}
+
+static qubo_status_t take_result(qubo_server *s, uint64_t ticket, qubo_result_t *out, bool *ready)
+{
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) {
+        qrt::set_error("unknown ticket");
+        *ready = true;
+        return QUBO_EINVAL;
+    }
+    Request *r = it->second;
+    if (r->state == RState::Queued || r->state == RState::Active) {
+        *ready = false;
+        return QUBO_EAGAIN;
+    }
+    *ready = true;
+    qubo_status_t st = r->status;
+    if (r->state == RState::Done) {
+        if (out) *out = r->result;
+    } else {
+        qrt::set_error(r->error);
+    }
+    s->reqs.erase(it);
+    delete r;
+    return st;
+}
+
+qubo_status_t qubo_server_poll(qubo_server_t *s, uint64_t ticket, qubo_result_t *out)
+{
+    if (!s) {
+        qrt::set_error("null server");
+        return QUBO_EINVAL;
+    }
+    qrt::set_error("");
+    std::lock_guard<std::mutex> lk(s->mu);
+    bool ready = false;
+    return take_result(s, ticket, out, &ready);
+}
+
+qubo_status_t qubo_server_wait(qubo_server_t *s, uint64_t ticket, double timeout_ms,
+                               qubo_result_t *out)
+{
+    if (!s) {
+        qrt::set_error("null server");
+        return QUBO_EINVAL;
+    }
+    qrt::set_error("");
+    const auto deadline = Clock::now() + std::chrono::microseconds(int64_t(timeout_ms * 1000.0));
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        bool ready = false;
+        qubo_status_t st = take_result(s, ticket, out, &ready);
+        if (ready) return st;
+        if (s->cv_done.wait_until(lk, deadline) == std::cv_status::timeout) {
+            st = take_result(s, ticket, out, &ready);
+            return st;
+        }
+    }
+}
+
+qubo_status_t qubo_server_stats(qubo_server_t *s, double *p50_ms, double *p99_ms,
+                                double *states_per_s)
+{
+    if (!s) {
+        qrt::set_error("null server");
+        return QUBO_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::vector<double> v = s->lat_ms;
+    std::sort(v.begin(), v.end());
+    auto pct = [&](double p) {
+        if (v.empty()) return 0.0;
+        // nearest-rank percentile
+        size_t k = size_t(std::ceil(p / 100.0 * double(v.size())));
+        if (k < 1) k = 1;
+        return v[k - 1];
+    };
+    if (p50_ms) *p50_ms = pct(50.0);
+    if (p99_ms) *p99_ms = pct(99.0);
+    if (states_per_s) {
+        const double sec = s->have_t0 ? ms_since(s->t0) / 1e3 : 0.0;
+        *states_per_s = sec > 0 ? s->states_done / sec : 0.0;
+    }
+    return QUBO_OK;
+}
+
+qubo_status_t qubo_server_info(qubo_server_t *s, size_t *mem_in_use, size_t *mem_peak,
+                               int *active_peak, uint64_t *ticks)
+{
+    if (!s) {
+        qrt::set_error("null server");
+        return QUBO_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (mem_in_use) *mem_in_use = s->mem_used;
+    if (mem_peak) *mem_peak = s->mem_peak;
+    if (active_peak) *active_peak = s->active_peak;
+    if (ticks) *ticks = s->n_ticks;
+    return QUBO_OK;
+}
+
+void qubo_server_destroy(qubo_server_t *s)
+{
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->th.joinable()) s->th.join();
+    server_free(s);
+}
+
+}  // extern "C"
