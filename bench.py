@@ -1,6 +1,6 @@
 """Benchmark: exhaustive dense-QUBO minimisation on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--no-serve]
 
 One step = one complete solve (plan, table build, Gray walk, finish, result
 copy) of the headline workload: a dense n=44 int32 QUBO, entries i.i.d.
@@ -9,14 +9,22 @@ before the timed region starts.  Prints ONE JSON line.
 
 value            = 2^44 * K / (timed seconds)  [states/s, whole job]
 roofline         = the walk kernel (dominant kernel) against the int32 VALU
-                   issue peak of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
-                   = 39.32 T int32 lane-ops/s; algorithmic work = 1 int32 add
-                   per state (the Gray update of Sec. III-B); duration = HIP
-                   events around the walk kernel on its own stream.
+                   peak of MI355X: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz
+                   = 78.64 T int32 lane-ops/s (the published 157.3 TFLOP/s fp32
+                   vector rate counts an FMA lane-op as 2 flops; v_add_u32
+                   issues a wave64 in 2 cycles, as the VALU probe confirms);
+                   algorithmic work = 1 int32 add per state (the Gray update of
+                   Sec. III-B); duration = HIP events around the walk kernel on
+                   its own stream.
 cpu_baseline     = the CPU oracle (direct evaluation) timed on this host over a
                    bounded contiguous index range of the same instance.
 batched          = 4096 instances, n ~ U{20..34}, int32 U[-100,100] (seed 5):
                    aggregate states/s of one graph replay.
+serving          = Poisson arrivals at a fixed rate (seed 7), n ~ U{16..40},
+                   80% int32 U[-100,100] / 20% float32 N(0,1): p50/p99 latency
+                   (arrival -> result) and aggregate states/s through the
+                   continuous-batching server; plus the same requests submitted
+                   at once (saturation throughput).
 """
 import argparse
 import hashlib
@@ -29,7 +37,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9        # int32 lane-ops/s
+VALU_PEAK_OPS = 256 * 4 * 32 * 2.4e9        # int32 lane-ops/s
 METRIC = ("states/sec on 1 MI355X (single n=44; batched mixed-n) vs VALU peak; "
           "p50/p99 solve latency")
 HEADLINE = dict(n=44, lo=-10000, hi=10000, seed=4)
@@ -88,6 +96,47 @@ def batched(q, steps=2):
             "states": states, "graph_ms": kms}
 
 
+def serving(q, count=600, rate_hz=150.0):
+    import threading
+    from paper_2607_04857_amd import inputs
+    reqs = inputs.poisson_requests(count, rate_hz, 16, 40, seed=7, int_fraction=0.8)
+    states = sum(2.0 ** Q.shape[0] for _, Q in reqs)
+
+    def run(paced):
+        srv = q.Server(mem_budget_bytes=8 << 30, max_slots=512)
+        tickets = [None] * len(reqs)
+
+        def submitter():
+            t0 = time.perf_counter()
+            for k, (arrival, Q) in enumerate(reqs):
+                if paced:
+                    while time.perf_counter() - t0 < arrival:
+                        time.sleep(0.0001)
+                tickets[k] = srv.submit(Q)
+
+        t0 = time.perf_counter()
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+        for t in tickets:
+            assert srv.wait(t, timeout_ms=600000) is not None
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        info = srv.info()
+        srv.close()
+        return st, info, wall
+
+    st, info, wall = run(True)
+    sat, _, sat_wall = run(False)
+    return {"workload": f"{count} requests, Poisson {rate_hz:g}/s, n~U{{16..40}}, 80% int32 "
+                        "U[-100,100] / 20% fp32 N(0,1), seed 7",
+            "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "states_per_s": states / wall,
+            "offered_states_per_s": states / reqs[-1][0], "ticks": info["ticks"],
+            "mem_peak_bytes": info["mem_peak"],
+            "saturation_states_per_s": states / sat_wall,
+            "saturation_p50_ms": sat["p50_ms"], "saturation_p99_ms": sat["p99_ms"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
@@ -95,6 +144,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
@@ -152,17 +202,20 @@ def main():
         "data": "synthetic",
         "config": {"workload": "single dense QUBO n=44, int32 Q upper-triangular, entries "
                                "U[-10000,10000], seed 4", "n": n, "states_per_step": 2 ** n,
-                   "tier": r.tier, "A": r.A, "B": r.B, "L": r.L},
+                   "tier": r.tier, "A": r.A, "B": r.B, "L": r.L, "vgpr_levels": r.vgpr_levels},
         "result": {"energy": r.energy_i, "index": r.index},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                      "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS,
                      "traffic": traffic_from_profile(),
-                     "kernel": "walk_kernel<16,%d>" % r.tier, "walk_ms": walk_ms},
+                     "kernel": "walk_kernel<%d,%d,%d>" % (2 ** (r.B - 6), r.vgpr_levels, r.tier),
+                     "walk_ms": walk_ms},
         "paper_context": {"states_per_s": 7.42e12, "hardware": "NVIDIA H100 80GB",
                           "precision": "int16", "n": 44},
     }
     if not args.no_batch:
         line["batched"] = batched(q)
+    if not args.no_serve:
+        line["serving"] = serving(q)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(Q)
     print(json.dumps(line), flush=True)

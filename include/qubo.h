@@ -81,6 +81,7 @@ typedef struct {
     int L;               /* log2 Gray steps per work item                          */
     int tier;            /* 0 direct evaluation (n <= 14); 1 exact lane-min every
                             Gray step; 2 block lower bound, exact min on demand   */
+    int vgpr_levels;     /* Gray levels with VGPR-resident rows (0 when direct)    */
     uint64_t states;     /* states evaluated = 2^n                                 */
     double kernel_ms;    /* GPU time of the walk kernel (HIP events)               */
     double total_ms;     /* host wall time of the whole call                       */
@@ -89,13 +90,19 @@ typedef struct {
 /* Plan overrides, mainly for tests and the autotuner.  Zero-initialise for the
  * defaults.  B: suffix bits in [6, 10] (0 = default 10); L: log2 Gray steps per
  * work item in [5, A] (0 = default); tier: 0 = default, 1 or 2 to force that
- * walk tier; waves_per_cu: resident walk waves per compute unit (0 = default). */
+ * walk tier; waves_per_cu: resident walk waves per compute unit (0 = the
+ * occupancy limit); vgpr_levels: see below. */
 typedef struct {
     int B;
     int L;
     int tier;
     int waves_per_cu;
-    int reserved[4];
+    int vgpr_levels;     /* Gray levels whose M_int rows stay in VGPRs: 0 = default
+                            (6 for B = 10, else 12), 12, 8 (B = 9 or 10) or 6
+                            (B = 10); fewer levels free VGPRs for a third/fourth
+                            wave per SIMD, the higher rows being read from L2
+                            when they flip                                    */
+    int reserved[3];
 } qubo_options_t;
 
 /* Solve one instance held in HOST memory.  k = 0 or 1: best state only
@@ -164,11 +171,18 @@ qubo_status_t qubo_server_info(qubo_server_t *srv, size_t *mem_in_use, size_t *m
 /* Stops accepting work, finishes every submitted request, frees the server. */
 void qubo_server_destroy(qubo_server_t *srv);
 
+/* Measurement: int32 VALU throughput of this device.  Runs wave64 streams of
+ * independent `op` instructions (0: v_add_u32, 1: v_min3_i32) with
+ * waves_per_simd resident waves on every SIMD and reports lane-operations per
+ * second and the kernel time. */
+qubo_status_t qubo_probe_valu(int op, int waves_per_simd, int iters, double *lane_ops_per_s,
+                              double *ms);
+
 /* Host-only planning, for tests: fold, overflow proof / fp32 scale, split.
  * Never touches the GPU.  T_out (n*n int32, may be NULL) receives the folded
  * (and for float32 scaled) upper-triangular matrix the kernels consume. */
 typedef struct {
-    int n, A, B, L, tier, direct;
+    int n, A, B, L, tier, direct, vgpr_levels;
     int p;
     double eps_q;
     int64_t sum_abs_t;   /* sum |T~_ij| over i <= j */

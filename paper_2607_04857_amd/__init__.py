@@ -44,19 +44,20 @@ class _State(ctypes.Structure):
 class _Result(ctypes.Structure):
     _fields_ = [("best", _State), ("tol", ctypes.c_double), ("p", ctypes.c_int),
                 ("A", ctypes.c_int), ("B", ctypes.c_int), ("L", ctypes.c_int),
-                ("tier", ctypes.c_int), ("states", ctypes.c_uint64),
+                ("tier", ctypes.c_int), ("vgpr_levels", ctypes.c_int), ("states", ctypes.c_uint64),
                 ("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
 
 
 class _Options(ctypes.Structure):
     _fields_ = [("B", ctypes.c_int), ("L", ctypes.c_int), ("tier", ctypes.c_int),
-                ("waves_per_cu", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
+                ("waves_per_cu", ctypes.c_int), ("vgpr_levels", ctypes.c_int),
+                ("reserved", ctypes.c_int * 3)]
 
 
 class _PlanInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("A", ctypes.c_int), ("B", ctypes.c_int),
                 ("L", ctypes.c_int), ("tier", ctypes.c_int), ("direct", ctypes.c_int),
-                ("p", ctypes.c_int), ("eps_q", ctypes.c_double), ("sum_abs_t", ctypes.c_int64),
+                ("vgpr_levels", ctypes.c_int), ("p", ctypes.c_int), ("eps_q", ctypes.c_double), ("sum_abs_t", ctypes.c_int64),
                 ("items", ctypes.c_uint64)]
 
 
@@ -88,6 +89,8 @@ _SIGS = {
     "qubo_server_destroy": (None, [_VP]),
     "qubo_plan_info": (_I, [_VP, _I, _I, ctypes.POINTER(_Options), ctypes.POINTER(_PlanInfo),
                             ctypes.POINTER(ctypes.c_int32)]),
+    "qubo_probe_valu": (_I, [_I, _I, _I, ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(ctypes.c_double)]),
     "qubo_last_error": (ctypes.c_char_p, []),
     "qubo_version": (ctypes.c_char_p, []),
 }
@@ -130,6 +133,7 @@ class Result:
     B: int
     L: int
     tier: int
+    vgpr_levels: int
     states: int
     kernel_ms: float
     total_ms: float
@@ -142,7 +146,8 @@ class Result:
 
 def _result(r: _Result, n: int) -> Result:
     return Result(energy=r.best.energy, energy_i=r.best.energy_i, index=r.best.index, n=n,
-                  tol=r.tol, p=r.p, A=r.A, B=r.B, L=r.L, tier=r.tier, states=r.states,
+                  tol=r.tol, p=r.p, A=r.A, B=r.B, L=r.L, tier=r.tier, vgpr_levels=r.vgpr_levels,
+                  states=r.states,
                   kernel_ms=r.kernel_ms, total_ms=r.total_ms)
 
 
@@ -159,19 +164,21 @@ def _as_q(Q):
     raise TypeError("Q must be int32 or float32")
 
 
-def _options(B=0, L=0, tier=0, waves_per_cu=0) -> _Options:
+def _options(B=0, L=0, tier=0, waves_per_cu=0, vgpr_levels=0) -> _Options:
     o = _Options()
     o.B, o.L, o.tier, o.waves_per_cu = int(B), int(L), int(tier), int(waves_per_cu)
+    o.vgpr_levels = int(vgpr_levels)
     return o
 
 
-def solve(Q, k: int = 1, *, B: int = 0, L: int = 0, tier: int = 0, waves_per_cu: int = 0):
+def solve(Q, k: int = 1, *, B: int = 0, L: int = 0, tier: int = 0, waves_per_cu: int = 0,
+          vgpr_levels: int = 0):
     """Minimise E(x) for a host matrix.  k > 1 also returns the k smallest (E, index) pairs."""
     Qc, dt = _as_q(Q)
     n = Qc.shape[0]
     out = _Result()
     top = (_State * k)() if k > 1 else None
-    opt = _options(B, L, tier, waves_per_cu)
+    opt = _options(B, L, tier, waves_per_cu, vgpr_levels)
     _check(lib().qubo_solve_ex(Qc.ctypes.data, n, dt, int(k), ctypes.byref(opt),
                                ctypes.byref(out), top))
     res = _result(out, n)
@@ -219,11 +226,11 @@ class Batch:
     """Plan, allocate and graph-capture a batch once; ``run()`` replays it."""
 
     def __init__(self, Qs: Sequence, *, B: int = 0, L: int = 0, tier: int = 0,
-                 waves_per_cu: int = 0):
+                 waves_per_cu: int = 0, vgpr_levels: int = 0):
         self._mats, self.count, ptrs, ns, dts = _batch_args(Qs)
         self._ns = [m.shape[0] for m, _ in self._mats]
         self._h = _VP()
-        opt = _options(B, L, tier, waves_per_cu)
+        opt = _options(B, L, tier, waves_per_cu, vgpr_levels)
         _check(lib().qubo_batch_create(self.count, ptrs, ns, dts, ctypes.byref(opt),
                                        ctypes.byref(self._h)))
 
@@ -317,18 +324,26 @@ class Server:
             pass
 
 
-def plan_info(Q, *, B: int = 0, L: int = 0, tier: int = 0):
+def plan_info(Q, *, B: int = 0, L: int = 0, tier: int = 0, vgpr_levels: int = 0):
     """Host-only plan of a solve (no GPU): split, items, scale; plus the folded T."""
     Qc, dt = _as_q(Q)
     n = Qc.shape[0]
     info = _PlanInfo()
     T = np.zeros((n, n), dtype=np.int32)
-    opt = _options(B, L, tier)
+    opt = _options(B, L, tier, vgpr_levels=vgpr_levels)
     _check(lib().qubo_plan_info(Qc.ctypes.data, n, dt, ctypes.byref(opt), ctypes.byref(info),
                                 T.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
     d = {f: getattr(info, f) for f, _ in _PlanInfo._fields_}
     d["T"] = T
     return d
+
+
+def probe_valu(op: str = "add", waves_per_simd: int = 4, iters: int = 4096):
+    """Measured int32 VALU lane-operations per second (op 'add' or 'min3')."""
+    rate, ms = ctypes.c_double(), ctypes.c_double()
+    _check(lib().qubo_probe_valu({"add": 0, "min3": 1}[op], int(waves_per_simd), int(iters),
+                                 ctypes.byref(rate), ctypes.byref(ms)))
+    return rate.value, ms.value
 
 
 def version() -> str:

@@ -14,7 +14,10 @@
 //                     2: o >= 16, falling): rows 0..2 hold C2 = ELOW + D,
 //                     rows 3..5 hold D, where D is the minimum over all 2^B
 //                     columns of E_sd(o) - E_sd(super-block start) and ELOW the
-//                     low-low coupling energy of the low pattern at o
+//                     low-low coupling energy of the low pattern at o;
+//                     then SL[64][4]: SL[w][t] = coupling of prefix variable w
+//                     with the low variable A-1-t (0 when equal), so a flip of
+//                     w moves the low fields by scalar loads only
 //   Qf  [n][n] fp32   caller's float32 Q (fp32 instances only, for rescoring)
 #pragma once
 
@@ -27,8 +30,9 @@ constexpr int kWave = 64;
 constexpr int kSuperLog = 5;          // unrolled super-block: 32 Gray steps
 constexpr int kLowLevels = 4;         // Gray levels with static patterns in a super-block
 constexpr int kPatterns = 1 << kLowLevels;
-constexpr int kKTable = 6 * kPatterns;  // ints in the per-instance K table
-constexpr int kVgprLevels = 12;       // M_int rows of levels 0..11 held in VGPRs
+constexpr int kKBound = 6 * kPatterns;   // bound constants at the head of a K table
+constexpr int kKTable = kKBound + 4 * kWave;  // + SL[w][t], t < 4: ints per K table
+constexpr int kMaxVgprLevels = 12;    // at most Gray levels 0..11 keep their M_int row in VGPRs
 constexpr int32_t kNoEnergy = 1 << 30;  // above every energy the walk can meet
 
 struct ItemRes;
@@ -71,12 +75,17 @@ hipError_t launch_tables(const Inst *d_insts, int n_inst, int max_A, unsigned lo
 
 // Persistent Gray walk over all items; `waves` resident wavefronts.  d_k is
 // the contiguous array of K tables (instance i's at insts[i].kslot*kKTable).
-hipError_t launch_walk(int mcols, int tier, const Inst *d_insts, int n_inst, uint64_t total_items,
-                       unsigned long long *d_counter, const int32_t *d_k, int waves,
-                       hipStream_t stream);
+// Variant: mcols columns per lane (B = 6 + log2 mcols), the M_int rows of
+// Gray levels below vgpr_levels cached in VGPRs (higher ones from L2), tier.
+hipError_t launch_walk(int mcols, int vgpr_levels, int tier, const Inst *d_insts, int n_inst,
+                       uint64_t total_items, unsigned long long *d_counter, const int32_t *d_k,
+                       int waves, hipStream_t stream);
+
+// Whether a (mcols, vgpr_levels) walk variant is compiled in.
+bool walk_variant_exists(int mcols, int vgpr_levels);
 
 // Resident walk wavefronts per CU for a variant (occupancy query, >= 1).
-int walk_occupancy(int mcols, int tier);
+int walk_occupancy(int mcols, int vgpr_levels, int tier);
 
 // Per-instance reduction of item results (insts[i].res[0..n_items)), argmin
 // rescan (or direct evaluation for tiny n) and float64 rescoring; one

@@ -94,10 +94,11 @@ __device__ __forceinline__ int32_t tree_min(const int32_t *e)
 // four row results through the scalar unit.
 __device__ __forceinline__ int32_t wave_min(int32_t v)
 {
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xF, 0xF, false));  // row_ror:4
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xF, 0xF, false));  // row_ror:8
+    constexpr int32_t I = INT32_MAX;
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x124, 0xF, 0xF, false));  // row_ror:4
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x128, 0xF, 0xF, false));  // row_ror:8
     const int32_t a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
     const int32_t c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
     return min(min(a, b), min(c, d));
@@ -186,6 +187,12 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
         I.S[e] = v;
     }
     if (blockIdx.x != 0) return;
+    for (uint32_t e = threadIdx.x; e < uint32_t(A) * 4u; e += blockDim.x) {
+        const int w = int(e / 4), t = int(e % 4), l = A - 1 - t;
+        int32_t v = 0;
+        if (l != w) v = (l < w) ? T[l * n + w] : T[w * n + l];
+        I.K[kKBound + e] = v;
+    }
     // Tier-2 bound constants.  Inside a 32-step super-block the four lowest
     // Gray levels follow the static pattern p(o) = g(o) & 15 from 0, and the
     // level-4 bit moves once (by +-1) at o = 16, so
@@ -242,12 +249,14 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
 // 16 lanes, then row broadcasts, result in lane 63.
 __device__ __forceinline__ int32_t wave_min_bcast(int32_t v)
 {
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xF, 0xF, false));  // row_ror:4
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xF, 0xF, false));  // row_ror:8
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    // lanes a DPP source leaves unwritten read INT32_MAX, the identity of min
+    constexpr int32_t I = INT32_MAX;
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x124, 0xF, 0xF, false));  // row_ror:4
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x128, 0xF, 0xF, false));  // row_ror:8
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    v = min(v, __builtin_amdgcn_update_dpp(I, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
     return __builtin_amdgcn_readlane(v, 63);
 }
 
@@ -257,14 +266,25 @@ __device__ __forceinline__ int32_t wave_min_bcast(int32_t v)
 //         at offset o the chunk minimum is at least W0 + D(o) (table K), so
 //         the step needs only the scalar test W0 <= THR - D(o); the exact
 //         minimum is formed only when that test passes.
-template <int MC, int TIER>
-__global__ __launch_bounds__(kWave) void walk_kernel(const Inst *__restrict__ insts, int n_inst,
+// Resident waves per SIMD each variant is register-allocated for: the full
+// 12-level row cache fits 256 VGPRs (2 waves); the 8-level cache leaves room
+// for a third (MC=16) or a fourth (MC=8) wave.
+template <int MC, int G>
+constexpr int walk_waves_per_simd()
+{
+    return G >= 12 ? (MC >= 16 ? 2 : (MC >= 8 ? 3 : 4)) : (MC >= 16 ? 3 : 4);
+}
+// (G = 6 and 8 with MC = 16 both target 3 waves; 8 spills a few cold values.)
+
+template <int MC, int G, int TIER>
+__global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_kernel(
+    const Inst *__restrict__ insts, int n_inst,
                                                      uint64_t total_items,
                                                      unsigned long long *__restrict__ counter,
                                                      const int32_t *__restrict__ kall)
 {
     static_assert(TIER == 1 || TIER == 2, "tier");
-    constexpr int G = kVgprLevels;
+    static_assert(G > kSuperLog && G <= kMaxVgprLevels, "VGPR-resident levels");
     constexpr int H16 = kPatterns;   // steps per half super-block
     const int lane = int(threadIdx.x);
 
@@ -276,6 +296,7 @@ __global__ __launch_bounds__(kWave) void walk_kernel(const Inst *__restrict__ in
     uint64_t item_begin = 0, item_local0 = 0;
     int32_t R[G][MC];        // M_int rows of Gray levels 0..G-1 (variable A-1-t)
     int32_t S4 = 0;          // couplings of the level-4 variable, one lane each
+    int32_t S4L[kLowLevels];  // couplings of the level-4 variable with the low ones
     int32_t diagl = 0;       // T[l][l] on lane l < A
     int32_t CR[kPatterns];   // low-low coupling increments per pattern
     int32_t best = kNoEnergy;
@@ -314,6 +335,10 @@ __global__ __launch_bounds__(kWave) void walk_kernel(const Inst *__restrict__ in
                 for (int j = 0; j < MC; j++) R[t][j] = have ? M[(v * MC + j) * kWave + lane] : 0;
             });
             S4 = S[(A - 5) * kWave + lane];
+            static_for<0, kLowLevels>([&](auto tc) {
+                constexpr int t = decltype(tc)::value;
+                S4L[t] = kall[kbase + kKBound + (A - 5) * 4 + t];
+            });
             diagl = lane < A ? I.T[lane * I.n + lane] : 0;
             // Sll(t,u): coupling of the low variables A-1-t and A-1-u
             int32_t Sll[kLowLevels][kLowLevels];
@@ -385,32 +410,40 @@ __global__ __launch_bounds__(kWave) void walk_kernel(const Inst *__restrict__ in
                 THR[p] = THR[pp] - H[t] - CR[p];
             });
         };
-        // TIER 2: TP[o'] = best - E_p(pattern at offset o) - D(o) for the 16
-        // offsets of the current half super-block (table tab of K).
-        int32_t TP[H16];
-        auto build_tp = [&](int half, int tab) {
-            const int32_t base = best - Enl;
+        // TIER 2: for the 16 offsets o of half super-block `half`,
+        //   tp(o) = best - E_p(low pattern at o) - D(o)   (K table tab),
+        // computed by walking the Gray sequence of patterns; hs = the sum of
+        // H[t] over the set low bits.  The first half walks the patterns
+        // g(o2), the second half g(o2) ^ 8 (the same bit sequence with bit 3
+        // inverted).  f(o2, tp) is called for every offset.  Step o can hold a
+        // candidate only if W0 <= tp(o).
+        auto for_each_tp = [&](int half, int tab, auto &&f) {
             int32_t hs = half ? H[kLowLevels - 1] : 0;   // pattern 8 opens the second half
             static_for<0, H16>([&](auto oc) {
                 constexpr int o2 = decltype(oc)::value;
                 if constexpr (o2 > 0) {
-                    // pattern changes by one bit between consecutive offsets
                     constexpr int pa0 = (o2 - 1) ^ ((o2 - 1) >> 1), pa1 = o2 ^ (o2 >> 1);
                     constexpr int t = cx_ctz(pa0 ^ pa1);
-                    // first half walks the patterns g(o2); the second half walks
-                    // g(o2) ^ 8: the same bit sequence with bit 3 inverted
                     constexpr bool rise0 = ((pa1 >> t) & 1) != 0;
                     const bool rise = (half && t == kLowLevels - 1) ? !rise0 : rise0;
                     hs = rise ? hs + H[t] : hs - H[t];
                 }
-                TP[o2] = base - hs - kall[kbase + tab * kPatterns + o2];
+                // best is read afresh: a candidate found at an earlier offset
+                // of the same half has already lowered it
+                f(oc, (best - Enl) - hs - kall[kbase + tab * kPatterns + o2]);
             });
+        };
+        // Thresholds of the current half, kept in SGPRs.
+        int32_t TP[H16];
+        auto build_tp = [&](int half, int tab) {
+            for_each_tp(half, tab, [&](auto oc, int32_t tp) { TP[decltype(oc)::value] = tp; });
         };
         if constexpr (TIER == 1) build_thr();
         else build_tp(0, 0);
 
-        // A non-low prefix variable w flips (direction up: 0 -> 1).
-        auto nonlow_flip = [&](int w, bool up, int32_t Scol) {
+        // A non-low prefix variable w flips (direction up: 0 -> 1); SLw[t] is
+        // its coupling with the low variable A-1-t.
+        auto nonlow_flip = [&](int w, bool up, int32_t Scol, const int32_t *SLw) {
             const int32_t Fw = __builtin_amdgcn_readlane(F, w);
             if (up) {
                 Enl += Fw;
@@ -421,7 +454,7 @@ __global__ __launch_bounds__(kWave) void walk_kernel(const Inst *__restrict__ in
             }
             static_for<0, kLowLevels>([&](auto tc) {
                 constexpr int t = decltype(tc)::value;
-                H[t] = __builtin_amdgcn_readlane(F, A - 1 - t);
+                H[t] = up ? H[t] + SLw[t] : H[t] - SLw[t];
             });
         };
 
@@ -453,83 +486,116 @@ __global__ __launch_bounds__(kWave) void walk_kernel(const Inst *__restrict__ in
             }
         };
 
-        for (uint64_t sb = sb0; sb < sbEnd; sb++) {
-            static_for<0, 32>([&](auto oc) {
-                constexpr int o = decltype(oc)::value;
-                constexpr int pat = (o ^ (o >> 1)) & (kPatterns - 1);
-                const uint64_t i = (sb << kSuperLog) | uint64_t(o);
-                // ---- evaluate the chunk of Gray step i
-                if constexpr (TIER == 1) {
-                    candidate(tree_min<MC>(E), THR[pat], i);
-                } else {
-                    if constexpr (o == 0) W0 = wave_min_bcast(tree_min<MC>(E));
-                    if (W0 <= TP[o % H16]) {
-                        const int32_t thr =
-                            TP[o % H16] + kall[kbase + (3 + tab2) * kPatterns + (o % H16)];
-                        candidate(tree_min<MC>(E), thr, i);
-                    }
-                }
-                // ---- flip one prefix bit (Alg. 2: E_sd += delta M_int[k])
-                if constexpr (o < 31) {
-                    constexpr int t = cx_ctz(o + 1);
-                    if constexpr (t < kLowLevels) {
-                        constexpr bool up = ((((o + 1) ^ ((o + 1) >> 1)) >> t) & 1) != 0;
+        // Low flip of static level t (< 4) with static direction (Alg. 2:
+        // E_sd += delta M_int[k]).
+        auto low_flip = [&](auto tc, auto upc) {
+            constexpr int t = decltype(tc)::value;
+            constexpr bool up = decltype(upc)::value;
 #pragma unroll
-                        for (int j = 0; j < MC; j++) E[j] = up ? E[j] + R[t][j] : E[j] - R[t][j];
+            for (int j = 0; j < MC; j++) E[j] = up ? E[j] + R[t][j] : E[j] - R[t][j];
+        };
+        // Level-4 flip in the middle of super-block sb.
+        auto middle_flip = [&](uint64_t sb) {
+            const bool up = (sb & 1) == 0;
+            if (up) {
+#pragma unroll
+                for (int j = 0; j < MC; j++) E[j] += R[4][j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < MC; j++) E[j] -= R[4][j];
+            }
+            nonlow_flip(A - 5, up, S4, S4L);
+            return up;
+        };
+        // Flip entering super-block sb + 1 (Gray level >= 5).
+        auto boundary_flip = [&](uint64_t sb) {
+            const uint64_t ip1 = (sb + 1) << kSuperLog;
+            const int t = __builtin_ctzll(ip1);
+            const bool up = ((ip1 >> (t + 1)) & 1) == 0;
+            const int w = A - 1 - t;
+            bool done = false;
+            static_for<kSuperLog, G>([&](auto tc) {
+                constexpr int tt = decltype(tc)::value;
+                if (t == tt) {
+                    if (up) {
+#pragma unroll
+                        for (int j = 0; j < MC; j++) E[j] += R[tt][j];
                     } else {
-                        const bool up = (sb & 1) == 0;
-                        if (up) {
 #pragma unroll
-                            for (int j = 0; j < MC; j++) E[j] += R[4][j];
-                        } else {
-#pragma unroll
-                            for (int j = 0; j < MC; j++) E[j] -= R[4][j];
-                        }
-                        nonlow_flip(A - 5, up, S4);
-                        if constexpr (TIER == 1) {
-                            build_thr();
-                        } else {
-                            tab2 = up ? 1 : 2;
-                            build_tp(1, tab2);
-                        }
+                        for (int j = 0; j < MC; j++) E[j] -= R[tt][j];
                     }
-                } else {
-                    if (sb + 1 < sbEnd) {
-                        const uint64_t ip1 = (sb + 1) << kSuperLog;
-                        const int t = __builtin_ctzll(ip1);
-                        const bool up = ((ip1 >> (t + 1)) & 1) == 0;
-                        const int w = A - 1 - t;
-                        bool done = false;
-                        static_for<kSuperLog, G>([&](auto tc) {
-                            constexpr int tt = decltype(tc)::value;
-                            if (t == tt) {
-                                if (up) {
-#pragma unroll
-                                    for (int j = 0; j < MC; j++) E[j] += R[tt][j];
-                                } else {
-#pragma unroll
-                                    for (int j = 0; j < MC; j++) E[j] -= R[tt][j];
-                                }
-                                done = true;
-                            }
-                        });
-                        if (!done) {
-#pragma unroll
-                            for (int j = 0; j < MC; j++) {
-                                const int32_t r = M[(w * MC + j) * kWave + lane];
-                                E[j] = up ? E[j] + r : E[j] - r;
-                            }
-                        }
-                        nonlow_flip(w, up, S[w * kWave + lane]);
-                        if constexpr (TIER == 1) {
-                            build_thr();
-                        } else {
-                            tab2 = 0;
-                            build_tp(0, 0);
-                        }
-                    }
+                    done = true;
                 }
             });
+            if (!done) {
+#pragma unroll
+                for (int j = 0; j < MC; j++) {
+                    const int32_t r = M[(w * MC + j) * kWave + lane];
+                    E[j] = up ? E[j] + r : E[j] - r;
+                }
+            }
+            int32_t SLw[kLowLevels];
+            static_for<0, kLowLevels>([&](auto tc) {
+                constexpr int tt = decltype(tc)::value;
+                SLw[tt] = kall[kbase + kKBound + w * 4 + tt];
+            });
+            nonlow_flip(w, up, S[w * kWave + lane], SLw);
+        };
+
+        if constexpr (TIER == 1) {
+            for (uint64_t sb = sb0; sb < sbEnd; sb++) {
+                static_for<0, 32>([&](auto oc) {
+                    constexpr int o = decltype(oc)::value;
+                    constexpr int pat = (o ^ (o >> 1)) & (kPatterns - 1);
+                    candidate(tree_min<MC>(E), THR[pat], (sb << kSuperLog) | uint64_t(o));
+                    if constexpr (o < 31) {
+                        constexpr int t = cx_ctz(o + 1);
+                        if constexpr (t < kLowLevels) {
+                            constexpr bool up = ((((o + 1) ^ ((o + 1) >> 1)) >> t) & 1) != 0;
+                            low_flip(std::integral_constant<int, t>{}, std::integral_constant<bool, up>{});
+                        } else {
+                            middle_flip(sb);
+                            build_thr();
+                        }
+                    } else if (sb + 1 < sbEnd) {
+                        boundary_flip(sb);
+                        build_thr();
+                    }
+                });
+            }
+        } else {
+            for (uint64_t sb = sb0; sb < sbEnd; sb++) {
+                W0 = wave_min_bcast(tree_min<MC>(E));
+                static_for<0, 2>([&](auto hc) {
+                    constexpr int h = decltype(hc)::value;
+                    // the 16 steps of half h, with (CHECK) or without the
+                    // per-step bound test, and the 15 low flips between them
+                    // Every step's chunk energies stay observable through the
+                    // (rarely taken) test, so each state gets its add.
+                    static_for<0, H16>([&](auto oc) {
+                        constexpr int o2 = decltype(oc)::value;
+                        constexpr int o = h * H16 + o2;
+                        if (__builtin_expect(W0 <= TP[o2], 0)) {
+                            const int32_t thr = TP[o2] + kall[kbase + (3 + tab2) * kPatterns + o2];
+                            candidate(tree_min<MC>(E), thr, (sb << kSuperLog) | uint64_t(o));
+                        }
+                        if constexpr (o2 < H16 - 1) {
+                            constexpr int t = cx_ctz(o + 1);
+                            constexpr bool up = ((((o + 1) ^ ((o + 1) >> 1)) >> t) & 1) != 0;
+                            low_flip(std::integral_constant<int, t>{},
+                                     std::integral_constant<bool, up>{});
+                        }
+                    });
+                    if constexpr (h == 0) {
+                        tab2 = middle_flip(sb) ? 1 : 2;
+                        build_tp(1, tab2);
+                    } else if (sb + 1 < sbEnd) {
+                        boundary_flip(sb);
+                        tab2 = 0;
+                        build_tp(0, 0);
+                    }
+                });
+            }
         }
 
         if (lane == 0) {
@@ -628,56 +694,80 @@ hipError_t launch_tables(const Inst *d_insts, int n_inst, int max_A, unsigned lo
     return hipGetLastError();
 }
 
-template <int MC>
-static hipError_t launch_walk_mc(int tier, const Inst *d_insts, int n_inst, uint64_t total_items,
-                                 unsigned long long *d_counter, const int32_t *d_k, int waves,
-                                 hipStream_t stream)
+template <int MC, int G>
+static hipError_t launch_walk_g(int tier, const Inst *d_insts, int n_inst, uint64_t total_items,
+                                unsigned long long *d_counter, const int32_t *d_k, int waves,
+                                hipStream_t stream)
 {
     if (tier == 1)
-        hipLaunchKernelGGL((walk_kernel<MC, 1>), dim3(waves), dim3(kWave), 0, stream, d_insts,
+        hipLaunchKernelGGL((walk_kernel<MC, G, 1>), dim3(waves), dim3(kWave), 0, stream, d_insts,
                            n_inst, total_items, d_counter, d_k);
     else if (tier == 2)
-        hipLaunchKernelGGL((walk_kernel<MC, 2>), dim3(waves), dim3(kWave), 0, stream, d_insts,
+        hipLaunchKernelGGL((walk_kernel<MC, G, 2>), dim3(waves), dim3(kWave), 0, stream, d_insts,
                            n_inst, total_items, d_counter, d_k);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-template <int MC>
-static int occupancy_mc(int tier)
+template <int MC, int G>
+static int occupancy_g(int tier)
 {
     int blocks = 0;
-    hipError_t e = tier == 2
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, 2>, kWave, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, 1>, kWave, 0);
+    hipError_t e =
+        tier == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, G, 2>, kWave, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, G, 1>, kWave, 0);
     if (e != hipSuccess || blocks < 1) return 1;
     return blocks;
 }
 
-int walk_occupancy(int mcols, int tier)
+// Variants built: every MC with G = 12; MC = 8 and 16 with G = 8; MC = 16
+// with G = 6.
+bool walk_variant_exists(int mcols, int vgpr_levels)
 {
+    if (vgpr_levels == 12) return mcols == 1 || mcols == 2 || mcols == 4 || mcols == 8 || mcols == 16;
+    if (vgpr_levels == 8) return mcols == 8 || mcols == 16;
+    if (vgpr_levels == 6) return mcols == 16;
+    return false;
+}
+
+int walk_occupancy(int mcols, int vgpr_levels, int tier)
+{
+    if (vgpr_levels == 6) return occupancy_g<16, 6>(tier);
+    if (vgpr_levels == 8) return mcols == 8 ? occupancy_g<8, 8>(tier) : occupancy_g<16, 8>(tier);
     switch (mcols) {
-    case 1: return occupancy_mc<1>(tier);
-    case 2: return occupancy_mc<2>(tier);
-    case 4: return occupancy_mc<4>(tier);
-    case 8: return occupancy_mc<8>(tier);
-    default: return occupancy_mc<16>(tier);
+    case 1: return occupancy_g<1, 12>(tier);
+    case 2: return occupancy_g<2, 12>(tier);
+    case 4: return occupancy_g<4, 12>(tier);
+    case 8: return occupancy_g<8, 12>(tier);
+    default: return occupancy_g<16, 12>(tier);
     }
 }
 
-hipError_t launch_walk(int mcols, int tier, const Inst *d_insts, int n_inst, uint64_t total_items,
-                       unsigned long long *d_counter, const int32_t *d_k, int waves,
-                       hipStream_t stream)
+hipError_t launch_walk(int mcols, int vgpr_levels, int tier, const Inst *d_insts, int n_inst,
+                       uint64_t total_items, unsigned long long *d_counter, const int32_t *d_k,
+                       int waves, hipStream_t stream)
 {
+#define QK_ARGS tier, d_insts, n_inst, total_items, d_counter, d_k, waves, stream
+    if (vgpr_levels == 6) {
+        if (mcols == 16) return launch_walk_g<16, 6>(QK_ARGS);
+        return hipErrorInvalidValue;
+    }
+    if (vgpr_levels == 8) {
+        if (mcols == 8) return launch_walk_g<8, 8>(QK_ARGS);
+        if (mcols == 16) return launch_walk_g<16, 8>(QK_ARGS);
+        return hipErrorInvalidValue;
+    }
+    if (vgpr_levels != 12) return hipErrorInvalidValue;
     switch (mcols) {
-    case 1: return launch_walk_mc<1>(tier, d_insts, n_inst, total_items, d_counter, d_k, waves, stream);
-    case 2: return launch_walk_mc<2>(tier, d_insts, n_inst, total_items, d_counter, d_k, waves, stream);
-    case 4: return launch_walk_mc<4>(tier, d_insts, n_inst, total_items, d_counter, d_k, waves, stream);
-    case 8: return launch_walk_mc<8>(tier, d_insts, n_inst, total_items, d_counter, d_k, waves, stream);
-    case 16: return launch_walk_mc<16>(tier, d_insts, n_inst, total_items, d_counter, d_k, waves, stream);
+    case 1: return launch_walk_g<1, 12>(QK_ARGS);
+    case 2: return launch_walk_g<2, 12>(QK_ARGS);
+    case 4: return launch_walk_g<4, 12>(QK_ARGS);
+    case 8: return launch_walk_g<8, 12>(QK_ARGS);
+    case 16: return launch_walk_g<16, 12>(QK_ARGS);
     default: return hipErrorInvalidValue;
     }
+#undef QK_ARGS
 }
 
 hipError_t launch_finish(const Inst *d_insts, int n_inst, FinalRes *d_out, hipStream_t stream)

@@ -110,6 +110,11 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
         return QUBO_EINVAL;
     }
     const int tier = (opt && opt->tier) ? opt->tier : kDefaultTier;
+    int vgpr_levels = (opt && opt->vgpr_levels) ? opt->vgpr_levels : 0;
+    if (vgpr_levels != 0 && vgpr_levels != 12 && vgpr_levels != 8 && vgpr_levels != 6) {
+        *msg = "option vgpr_levels must be 0, 6, 8 or 12";
+        return QUBO_EINVAL;
+    }
     P.direct = n <= kDirectMaxN;
     if (!P.direct && n - B < kSuper) B = n - kSuper;  // the prefix must hold one super-block
     if (P.direct) {
@@ -127,6 +132,14 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
     P.A = n - B;
     P.mcols = (1 << B) / kWave;
     P.tier = tier;
+    // Default row cache: 6 VGPR-resident levels for B = 10 (three waves per
+    // SIMD without spills), all 12 for narrower suffixes.
+    if (vgpr_levels == 0) vgpr_levels = P.mcols == 16 ? 6 : 12;
+    if ((vgpr_levels == 8 && P.mcols < 8) || (vgpr_levels == 6 && P.mcols != 16)) {
+        *msg = "vgpr_levels 8 needs B = 9 or 10, vgpr_levels 6 needs B = 10";
+        return QUBO_EINVAL;
+    }
+    P.vgpr_levels = vgpr_levels;
 
     // Work items: 2^L consecutive Gray steps each.  Default 2^14 steps (the
     // per-item set-up, about A*MC adds plus the prefix fields, stays below

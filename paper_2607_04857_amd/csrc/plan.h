@@ -29,7 +29,8 @@ struct Plan {
     int A = 0, B = 0;      // prefix / suffix bits
     int mcols = 0;         // suffix columns per lane = 2^B / 64
     int L = 0;             // log2 Gray steps per work item
-    int tier = 0;          // 0: exact lane-min each step; 1: block lower bound
+    int tier = 0;          // 0 direct; 1: exact lane-min each step; 2: block lower bound
+    int vgpr_levels = 0;   // Gray levels whose M_int rows are VGPR-resident
     int p = 0;             // fixed-point exponent (fp32)
     double eps_q = 0.0;    // per-state quantisation bound (fp32)
     int64_t sum_abs = 0;   // sum |T| over i <= j (of the int32 matrix solved)

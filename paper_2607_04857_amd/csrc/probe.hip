@@ -1,0 +1,87 @@
+// probe.hip -- int32 VALU throughput probe (the measured ceiling of the walk).
+//
+// Each wave keeps 16 independent accumulators and issues 256 instructions per
+// loop iteration, so no dependency chain limits issue; the grid places
+// waves_per_simd waves on every SIMD of the device.
+#include <hip/hip_runtime.h>
+
+#include "runtime.h"
+
+namespace {
+
+template <int OP>
+__global__ __launch_bounds__(64) void valu_probe_kernel(int iters, int32_t *__restrict__ out)
+{
+    int32_t a[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) a[k] = int32_t(threadIdx.x) * 7 + k;
+    const int32_t b = int32_t(blockIdx.x) | 1, c = int32_t(threadIdx.x) ^ 5;
+    for (int it = 0; it < iters; it++) {
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                if constexpr (OP == 0)
+                    asm volatile("v_add_u32 %0, %1, %0" : "+v"(a[k]) : "v"(b));
+                else
+                    asm volatile("v_min3_i32 %0, %0, %1, %2" : "+v"(a[k]) : "v"(b), "v"(c));
+            }
+        }
+    }
+    int32_t x = 0;
+#pragma unroll
+    for (int k = 0; k < 16; k++) x ^= a[k];
+    out[blockIdx.x * 64 + threadIdx.x] = x;
+}
+
+}  // namespace
+
+extern "C" qubo_status_t qubo_probe_valu(int op, int waves_per_simd, int iters,
+                                         double *lane_ops_per_s, double *ms)
+{
+    qrt::set_error("");
+    if ((op != 0 && op != 1) || waves_per_simd < 1 || waves_per_simd > 8 || iters < 1) {
+        qrt::set_error("bad probe arguments");
+        return QUBO_EINVAL;
+    }
+    qrt::DeviceInfo di;
+    qubo_status_t st = qrt::device_info(&di);
+    if (st != QUBO_OK) return st;
+    const int blocks = di.cus * 4 * waves_per_simd;
+    int32_t *d_out = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    QRT_HIP(hipMalloc(&d_out, size_t(blocks) * 64 * sizeof(int32_t)), "hipMalloc");
+    qubo_status_t rs = QUBO_OK;
+    float t = 0.f;
+    do {
+        hipError_t e;
+        if ((e = hipStreamCreate(&s)) != hipSuccess || (e = hipEventCreate(&e0)) != hipSuccess ||
+            (e = hipEventCreate(&e1)) != hipSuccess) {
+            rs = qrt::device_error("probe set-up", e);
+            break;
+        }
+        for (int rep = 0; rep < 2; rep++) {   // first launch warms up clocks and code
+            (void)hipEventRecord(e0, s);
+            if (op == 0)
+                hipLaunchKernelGGL(valu_probe_kernel<0>, dim3(blocks), dim3(64), 0, s, iters, d_out);
+            else
+                hipLaunchKernelGGL(valu_probe_kernel<1>, dim3(blocks), dim3(64), 0, s, iters, d_out);
+            (void)hipEventRecord(e1, s);
+        }
+        if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess ||
+            (e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) {
+            rs = qrt::device_error("probe run", e);
+            break;
+        }
+    } while (false);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    (void)hipFree(d_out);
+    if (rs != QUBO_OK) return rs;
+    const double ops = double(blocks) * 64.0 * double(iters) * 256.0;
+    if (lane_ops_per_s) *lane_ops_per_s = ops / (double(t) * 1e-3);
+    if (ms) *ms = t;
+    return QUBO_OK;
+}

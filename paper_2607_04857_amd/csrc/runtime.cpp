@@ -103,14 +103,17 @@ qubo_status_t job_layout(Job *job, int waves_per_cu)
     job->states = 0.0;
     job->mcols = 0;
     job->tier = 0;
+    job->vgpr_levels = 0;
     for (const qplan::Plan &P : job->plans) {
         job->states += std::ldexp(1.0, P.n);
         if (P.direct) continue;
         if (job->mcols == 0) {
             job->mcols = P.mcols;
             job->tier = P.tier;
-        } else if (job->mcols != P.mcols || job->tier != P.tier) {
-            set_error("all walked instances of one job must share B and tier");
+            job->vgpr_levels = P.vgpr_levels;
+        } else if (job->mcols != P.mcols || job->tier != P.tier ||
+                   job->vgpr_levels != P.vgpr_levels) {
+            set_error("all walked instances of one job must share B, tier and vgpr_levels");
             return QUBO_EINVAL;
         }
         if (P.A > job->max_A) job->max_A = P.A;
@@ -120,7 +123,12 @@ qubo_status_t job_layout(Job *job, int waves_per_cu)
     qubo_status_t st = device_info(&di);
     if (st != QUBO_OK) return st;
     int wpc = waves_per_cu;
-    if (wpc <= 0) wpc = qk::walk_occupancy(job->mcols ? job->mcols : 16, job->tier ? job->tier : 1);
+    if (job->mcols && !qk::walk_variant_exists(job->mcols, job->vgpr_levels)) {
+        set_error("no walk kernel built for this B / vgpr_levels");
+        return QUBO_EINVAL;
+    }
+    if (wpc <= 0)
+        wpc = job->mcols ? qk::walk_occupancy(job->mcols, job->vgpr_levels, job->tier) : 1;
     if (wpc <= 0) wpc = 1;
     uint64_t waves = uint64_t(di.cus) * uint64_t(wpc);
     if (job->total_items < waves) waves = job->total_items;
@@ -183,8 +191,8 @@ qubo_status_t job_enqueue_kernels(const Job &job, hipStream_t stream, hipEvent_t
     QRT_HIP(qk::launch_tables(job.d_insts, ni, job.max_A, job.d_counter, stream), "tables kernel");
     if (walk_begin) QRT_HIP(hipEventRecord(walk_begin, stream), "hipEventRecord");
     if (job.total_items > 0)
-        QRT_HIP(qk::launch_walk(job.mcols, job.tier, job.d_insts, ni, job.total_items, job.d_counter,
-                                job.d_k, job.waves, stream),
+        QRT_HIP(qk::launch_walk(job.mcols, job.vgpr_levels, job.tier, job.d_insts, ni,
+                                job.total_items, job.d_counter, job.d_k, job.waves, stream),
                 "walk kernel");
     if (walk_end) QRT_HIP(hipEventRecord(walk_end, stream), "hipEventRecord");
     QRT_HIP(qk::launch_finish(job.d_insts, ni, job.d_out, stream), "finish kernel");
@@ -208,6 +216,7 @@ qubo_status_t job_result(const Job &job, int i, const qk::FinalRes &fr, qubo_res
     out->B = P.B;
     out->L = P.L;
     out->tier = P.tier;
+    out->vgpr_levels = P.direct ? 0 : P.vgpr_levels;
     out->states = (P.n >= 64) ? ~0ull : (1ull << P.n);
     return QUBO_OK;
 }
@@ -406,6 +415,7 @@ qubo_status_t qubo_plan_info(const void *Q, int n, qubo_dtype_t dtype, const qub
         info->L = P.L;
         info->tier = P.tier;
         info->direct = P.direct ? 1 : 0;
+        info->vgpr_levels = P.vgpr_levels;
         info->p = P.p;
         info->eps_q = P.eps_q;
         info->sum_abs_t = P.sum_abs;

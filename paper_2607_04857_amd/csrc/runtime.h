@@ -34,7 +34,7 @@ qubo_status_t device_info(DeviceInfo *info);
 struct Job {
     std::vector<qplan::Plan> plans;
     std::vector<const float *> qf;       // caller's fp32 Q per instance (host) or null
-    int mcols = 0, tier = 0;             // shared walk variant of all walked instances
+    int mcols = 0, tier = 0, vgpr_levels = 0;   // shared walk variant of the walked instances
     int max_A = 0;
     uint64_t total_items = 0;
     double states = 0.0;                 // sum of 2^n

@@ -235,8 +235,8 @@ qubo_status_t enqueue_tick(qubo_server *s, TickBuf &t, bool *launched)
         QRT_HIP(hipMemsetAsync(s->d_counter, 0, sizeof(unsigned long long), s->stream), "hipMemsetAsync");
         const int waves = int(std::min<uint64_t>(g, uint64_t(s->waves_cap)));
         const qrt::Job &j0 = walkers[0]->job;
-        QRT_HIP(qk::launch_walk(j0.mcols, j0.tier, t.d_walk, nw, g, s->d_counter, s->d_karena, waves,
-                                s->stream),
+        QRT_HIP(qk::launch_walk(j0.mcols, j0.vgpr_levels, j0.tier, t.d_walk, nw, g, s->d_counter,
+                                s->d_karena, waves, s->stream),
                 "walk kernel");
     }
     if (!finishers.empty()) {
@@ -351,7 +351,7 @@ qubo_status_t server_init(qubo_server *s, size_t budget, int max_slots)
     qrt::DeviceInfo di;
     qubo_status_t st = qrt::device_info(&di);
     if (st != QUBO_OK) return st;
-    s->waves_cap = di.cus * qk::walk_occupancy(16, 2);
+    s->waves_cap = di.cus * qk::walk_occupancy(16, 6, 2);
     s->tick_items = uint64_t(s->waves_cap) * 2;
     QRT_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "hipStreamCreate");
     QRT_HIP(hipMalloc(&s->d_karena, size_t(max_slots) * qk::kKTable * sizeof(int32_t)), "hipMalloc");

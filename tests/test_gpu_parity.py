@@ -56,6 +56,15 @@ def test_split_invariance(q, orc, B, L, tier):
 
 
 @pytest.mark.parametrize("tier", TIERS)
+@pytest.mark.parametrize("B,G", [(9, 8), (10, 8), (10, 6)])
+@pytest.mark.parametrize("L", [5, 9])
+def test_vgpr_levels(q, orc, B, G, L, tier):
+    Q = inputs.uniform_int(23, -500, 500, 78)
+    got = _check(q, orc, Q, B=B, L=L, tier=tier, vgpr_levels=G)
+    assert got.vgpr_levels == G
+
+
+@pytest.mark.parametrize("tier", TIERS)
 def test_ties_zero_matrix(q, orc, tier):
     for n in (15, 18):
         _check(q, orc, np.zeros((n, n), dtype=np.int32), tier=tier)
