@@ -98,7 +98,7 @@ typedef struct {
     int tier;
     int waves_per_cu;
     int vgpr_levels;     /* Gray levels whose M_int rows stay in VGPRs: 0 = default
-                            (6 for B = 10, else 12), 12, 8 (B = 9 or 10) or 6
+                            (6 for B = 10, else 12), 12, 8 (B = 9 or 10), 6 or 5
                             (B = 10); fewer levels free VGPRs for a third/fourth
                             wave per SIMD, the higher rows being read from L2
                             when they flip                                    */
@@ -172,9 +172,11 @@ qubo_status_t qubo_server_info(qubo_server_t *srv, size_t *mem_in_use, size_t *m
 void qubo_server_destroy(qubo_server_t *srv);
 
 /* Measurement: int32 VALU throughput of this device.  Runs wave64 streams of
- * independent `op` instructions (0: v_add_u32, 1: v_min3_i32) with
- * waves_per_simd resident waves on every SIMD and reports lane-operations per
- * second and the kernel time. */
+ * independent `op` instructions (0: v_add_u32, 1: v_min3_i32, 2: v_add_u32
+ * with one scalar add per two vector adds, 3: v_add_u32 with one never-taken
+ * scalar compare-and-branch per 16 vector adds) with waves_per_simd resident
+ * waves on every SIMD and reports vector lane-operations per second and the
+ * kernel time. */
 qubo_status_t qubo_probe_valu(int op, int waves_per_simd, int iters, double *lane_ops_per_s,
                               double *ms);
 

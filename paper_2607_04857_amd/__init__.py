@@ -339,9 +339,13 @@ def plan_info(Q, *, B: int = 0, L: int = 0, tier: int = 0, vgpr_levels: int = 0)
 
 
 def probe_valu(op: str = "add", waves_per_simd: int = 4, iters: int = 4096):
-    """Measured int32 VALU lane-operations per second (op 'add' or 'min3')."""
+    """Measured int32 VALU lane-operations per second.
+
+    op: 'add', 'min3', 'add+salu' (a scalar add per two vector adds) or
+    'add+branch' (a never-taken compare/branch per 16 vector adds)."""
     rate, ms = ctypes.c_double(), ctypes.c_double()
-    _check(lib().qubo_probe_valu({"add": 0, "min3": 1}[op], int(waves_per_simd), int(iters),
+    ops = {"add": 0, "min3": 1, "add+salu": 2, "add+branch": 3}
+    _check(lib().qubo_probe_valu(ops[op], int(waves_per_simd), int(iters),
                                  ctypes.byref(rate), ctypes.byref(ms)))
     return rate.value, ms.value
 

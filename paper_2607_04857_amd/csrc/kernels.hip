@@ -272,9 +272,10 @@ __device__ __forceinline__ int32_t wave_min_bcast(int32_t v)
 template <int MC, int G>
 constexpr int walk_waves_per_simd()
 {
-    return G >= 12 ? (MC >= 16 ? 2 : (MC >= 8 ? 3 : 4)) : (MC >= 16 ? 3 : 4);
+    return G >= 12 ? (MC >= 16 ? 2 : (MC >= 8 ? 3 : 4)) : (G <= 5 ? 4 : (MC >= 16 ? 3 : 4));
 }
-// (G = 6 and 8 with MC = 16 both target 3 waves; 8 spills a few cold values.)
+// (G = 6 and 8 with MC = 16 target 3 waves, G = 5 four; 8 and 5 spill a few
+// values outside the unrolled steps.)
 
 template <int MC, int G, int TIER>
 __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_kernel(
@@ -284,7 +285,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
                                                      const int32_t *__restrict__ kall)
 {
     static_assert(TIER == 1 || TIER == 2, "tier");
-    static_assert(G > kSuperLog && G <= kMaxVgprLevels, "VGPR-resident levels");
+    static_assert(G >= kSuperLog && G <= kMaxVgprLevels, "VGPR-resident levels");
     constexpr int H16 = kPatterns;   // steps per half super-block
     const int lane = int(threadIdx.x);
 
@@ -722,17 +723,18 @@ static int occupancy_g(int tier)
 }
 
 // Variants built: every MC with G = 12; MC = 8 and 16 with G = 8; MC = 16
-// with G = 6.
+// with G = 6 and 5.
 bool walk_variant_exists(int mcols, int vgpr_levels)
 {
     if (vgpr_levels == 12) return mcols == 1 || mcols == 2 || mcols == 4 || mcols == 8 || mcols == 16;
     if (vgpr_levels == 8) return mcols == 8 || mcols == 16;
-    if (vgpr_levels == 6) return mcols == 16;
+    if (vgpr_levels == 6 || vgpr_levels == 5) return mcols == 16;
     return false;
 }
 
 int walk_occupancy(int mcols, int vgpr_levels, int tier)
 {
+    if (vgpr_levels == 5) return occupancy_g<16, 5>(tier);
     if (vgpr_levels == 6) return occupancy_g<16, 6>(tier);
     if (vgpr_levels == 8) return mcols == 8 ? occupancy_g<8, 8>(tier) : occupancy_g<16, 8>(tier);
     switch (mcols) {
@@ -749,9 +751,9 @@ hipError_t launch_walk(int mcols, int vgpr_levels, int tier, const Inst *d_insts
                        int waves, hipStream_t stream)
 {
 #define QK_ARGS tier, d_insts, n_inst, total_items, d_counter, d_k, waves, stream
-    if (vgpr_levels == 6) {
-        if (mcols == 16) return launch_walk_g<16, 6>(QK_ARGS);
-        return hipErrorInvalidValue;
+    if (vgpr_levels == 6 || vgpr_levels == 5) {
+        if (mcols != 16) return hipErrorInvalidValue;
+        return vgpr_levels == 6 ? launch_walk_g<16, 6>(QK_ARGS) : launch_walk_g<16, 5>(QK_ARGS);
     }
     if (vgpr_levels == 8) {
         if (mcols == 8) return launch_walk_g<8, 8>(QK_ARGS);

@@ -111,8 +111,9 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
     }
     const int tier = (opt && opt->tier) ? opt->tier : kDefaultTier;
     int vgpr_levels = (opt && opt->vgpr_levels) ? opt->vgpr_levels : 0;
-    if (vgpr_levels != 0 && vgpr_levels != 12 && vgpr_levels != 8 && vgpr_levels != 6) {
-        *msg = "option vgpr_levels must be 0, 6, 8 or 12";
+    if (vgpr_levels != 0 && vgpr_levels != 12 && vgpr_levels != 8 && vgpr_levels != 6 &&
+        vgpr_levels != 5) {
+        *msg = "option vgpr_levels must be 0, 5, 6, 8 or 12";
         return QUBO_EINVAL;
     }
     P.direct = n <= kDirectMaxN;
@@ -135,8 +136,8 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
     // Default row cache: 6 VGPR-resident levels for B = 10 (three waves per
     // SIMD without spills), all 12 for narrower suffixes.
     if (vgpr_levels == 0) vgpr_levels = P.mcols == 16 ? 6 : 12;
-    if ((vgpr_levels == 8 && P.mcols < 8) || (vgpr_levels == 6 && P.mcols != 16)) {
-        *msg = "vgpr_levels 8 needs B = 9 or 10, vgpr_levels 6 needs B = 10";
+    if ((vgpr_levels == 8 && P.mcols < 8) || (vgpr_levels <= 6 && vgpr_levels && P.mcols != 16)) {
+        *msg = "vgpr_levels 8 needs B = 9 or 10, vgpr_levels 5 and 6 need B = 10";
         return QUBO_EINVAL;
     }
     P.vgpr_levels = vgpr_levels;

@@ -1,8 +1,11 @@
 // probe.hip -- int32 VALU throughput probe (the measured ceiling of the walk).
 //
-// Each wave keeps 16 independent accumulators and issues 256 instructions per
-// loop iteration, so no dependency chain limits issue; the grid places
-// waves_per_simd waves on every SIMD of the device.
+// Each wave keeps 16 independent accumulators and issues 256 vector
+// instructions per loop iteration, so no dependency chain limits issue; the
+// grid places waves_per_simd waves on every SIMD of the device.  Ops: 0
+// v_add_u32; 1 v_min3_i32; 2 v_add_u32 with one s_add_i32 per two vector adds;
+// 3 v_add_u32 with one never-taken s_cmp/s_cbranch per 16 vector adds.  Only
+// vector lane-operations are counted.
 #include <hip/hip_runtime.h>
 
 #include "runtime.h"
@@ -16,18 +19,24 @@ __global__ __launch_bounds__(64) void valu_probe_kernel(int iters, int32_t *__re
 #pragma unroll
     for (int k = 0; k < 16; k++) a[k] = int32_t(threadIdx.x) * 7 + k;
     const int32_t b = int32_t(blockIdx.x) | 1, c = int32_t(threadIdx.x) ^ 5;
+    int32_t sc = int32_t(blockIdx.x);   // scalar work for OP 2 and 3 (wave-uniform)
     for (int it = 0; it < iters; it++) {
 #pragma unroll
         for (int r = 0; r < 16; r++) {
 #pragma unroll
             for (int k = 0; k < 16; k++) {
-                if constexpr (OP == 0)
-                    asm volatile("v_add_u32 %0, %1, %0" : "+v"(a[k]) : "v"(b));
-                else
+                if constexpr (OP == 1)
                     asm volatile("v_min3_i32 %0, %0, %1, %2" : "+v"(a[k]) : "v"(b), "v"(c));
+                else
+                    asm volatile("v_add_u32 %0, %1, %0" : "+v"(a[k]) : "v"(b));
+                if constexpr (OP == 2)   // one scalar add per two vector adds
+                    if (k % 2 == 1) asm volatile("s_add_i32 %0, %0, 3" : "+s"(sc) : : "scc");
             }
+            if constexpr (OP == 3)       // a never-taken compare and branch per 16 adds
+                asm volatile("s_cmp_eq_u32 %0, 0x7fffffff\n\ts_cbranch_scc1 1f\n1:" : : "s"(sc) : "scc");
         }
     }
+    if constexpr (OP == 2) a[0] ^= sc;
     int32_t x = 0;
 #pragma unroll
     for (int k = 0; k < 16; k++) x ^= a[k];
@@ -40,7 +49,7 @@ extern "C" qubo_status_t qubo_probe_valu(int op, int waves_per_simd, int iters,
                                          double *lane_ops_per_s, double *ms)
 {
     qrt::set_error("");
-    if ((op != 0 && op != 1) || waves_per_simd < 1 || waves_per_simd > 8 || iters < 1) {
+    if (op < 0 || op > 3 || waves_per_simd < 1 || waves_per_simd > 8 || iters < 1) {
         qrt::set_error("bad probe arguments");
         return QUBO_EINVAL;
     }
@@ -65,8 +74,12 @@ extern "C" qubo_status_t qubo_probe_valu(int op, int waves_per_simd, int iters,
             (void)hipEventRecord(e0, s);
             if (op == 0)
                 hipLaunchKernelGGL(valu_probe_kernel<0>, dim3(blocks), dim3(64), 0, s, iters, d_out);
-            else
+            else if (op == 1)
                 hipLaunchKernelGGL(valu_probe_kernel<1>, dim3(blocks), dim3(64), 0, s, iters, d_out);
+            else if (op == 2)
+                hipLaunchKernelGGL(valu_probe_kernel<2>, dim3(blocks), dim3(64), 0, s, iters, d_out);
+            else
+                hipLaunchKernelGGL(valu_probe_kernel<3>, dim3(blocks), dim3(64), 0, s, iters, d_out);
             (void)hipEventRecord(e1, s);
         }
         if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess ||
