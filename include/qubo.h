@@ -174,9 +174,10 @@ void qubo_server_destroy(qubo_server_t *srv);
 /* Measurement: int32 VALU throughput of this device.  Runs wave64 streams of
  * independent `op` instructions (0: v_add_u32, 1: v_min3_i32, 2: v_add_u32
  * with one scalar add per two vector adds, 3: v_add_u32 with one never-taken
- * scalar compare-and-branch per 16 vector adds) with waves_per_simd resident
- * waves on every SIMD and reports vector lane-operations per second and the
- * kernel time. */
+ * scalar compare-and-branch per 16 vector adds, 4: v_pk_add_u16, 5:
+ * v_pk_min_i16) with waves_per_simd resident waves on every SIMD and reports
+ * vector lane-operations per second (a packed instruction counts once per
+ * lane) and the kernel time. */
 qubo_status_t qubo_probe_valu(int op, int waves_per_simd, int iters, double *lane_ops_per_s,
                               double *ms);
 
@@ -193,6 +194,60 @@ typedef struct {
 qubo_status_t qubo_plan_info(const void *Q, int n, qubo_dtype_t dtype,
                              const qubo_options_t *opt, qubo_plan_info_t *info,
                              int32_t *T_out);
+
+/* ---------------------------------------------------------------- tuning
+ * The walk has knobs whose best setting depends on n and on the device: the
+ * suffix width B (columns per lane), the row-cache depth vgpr_levels, the
+ * bound tier and the work-item size L.  The paper tuned its kernel by hand
+ * on its GPU (Sec. IV); here the library times every plan it can run and
+ * keeps the fastest per (n, dtype) in a process-wide table that the planner
+ * consults whenever the caller's options override none of B, L, tier and
+ * vgpr_levels (all zero or opt == NULL).  Batches and the server use the
+ * tuned B / vgpr_levels / tier but their own L.  The table starts empty
+ * (built-in defaults) unless QUBO_TUNE_CACHE names a cache file, which is
+ * then loaded at the first solve, batch or server submission. */
+typedef struct {
+    int n;                 /* variables, 15..60                                  */
+    qubo_dtype_t dtype;
+    int B, L, tier, vgpr_levels;   /* L = 0: the planner's default item size   */
+    double walk_ms;        /* measured walk time of this plan (informational)   */
+} qubo_tune_entry_t;
+
+/* Time every runnable plan for each n in [n_min, n_max] (15 <= n_min <= n_max
+ * <= 48) on a synthetic instance of `dtype` on the current device: each
+ * candidate once, then the four fastest `reps` more times (minimum kept).
+ * Fails with QUBO_EINTERNAL if two plans disagree on (E*, index*).  The
+ * winners go into the process table; with cache_path they are also merged
+ * into that JSON file (created if absent; entries made for this device that it
+ * already holds are kept unless re-tuned).  out[0..min(out_cap, count)-1]
+ * receive the winners in n order and *out_count their number (both may be
+ * NULL / 0).  Cost: about 60 solves per n, dominated by the largest n. */
+qubo_status_t qubo_autotune(int n_min, int n_max, qubo_dtype_t dtype, int reps,
+                            const char *cache_path, qubo_tune_entry_t *out,
+                            int out_cap, int *out_count);
+
+/* Load a cache file into the process table.  device_key: the key the file
+ * must carry; NULL = this device's key (qubo_device_key).  A file made on
+ * another device, malformed JSON or an entry naming a plan this build cannot
+ * run is rejected as a whole with QUBO_EINVAL.  *loaded = entries read. */
+qubo_status_t qubo_tune_load(const char *path, const char *device_key, int *loaded);
+
+/* Write the whole process table to path under device_key (NULL = this
+ * device's key), replacing the file. */
+qubo_status_t qubo_tune_save(const char *path, const char *device_key);
+
+/* Put entries into the process table directly (validated as by
+ * qubo_tune_load; nothing is stored if any entry is invalid). */
+qubo_status_t qubo_tune_set(const qubo_tune_entry_t *entries, int count);
+
+/* 1 and *out filled (out may be NULL) if the table holds (n, dtype), else 0. */
+int qubo_tune_lookup(int n, qubo_dtype_t dtype, qubo_tune_entry_t *out);
+
+/* Empty the process table (built-in defaults again). */
+void qubo_tune_clear(void);
+
+/* This device's cache key, "<gfx arch>/<compute units>cu", e.g. "gfx950/256cu". */
+qubo_status_t qubo_device_key(char *buf, int cap);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *qubo_last_error(void);

@@ -61,6 +61,12 @@ class _PlanInfo(ctypes.Structure):
                 ("items", ctypes.c_uint64)]
 
 
+class _TuneEntry(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("dtype", ctypes.c_int), ("B", ctypes.c_int),
+                ("L", ctypes.c_int), ("tier", ctypes.c_int), ("vgpr_levels", ctypes.c_int),
+                ("walk_ms", ctypes.c_double)]
+
+
 # name -> (restype, argtypes); mirrors include/qubo.h
 _VP, _I, _U64P = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)
 _SIGS = {
@@ -91,6 +97,14 @@ _SIGS = {
                             ctypes.POINTER(ctypes.c_int32)]),
     "qubo_probe_valu": (_I, [_I, _I, _I, ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(ctypes.c_double)]),
+    "qubo_autotune": (_I, [_I, _I, _I, _I, ctypes.c_char_p, ctypes.POINTER(_TuneEntry), _I,
+                           ctypes.POINTER(_I)]),
+    "qubo_tune_load": (_I, [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(_I)]),
+    "qubo_tune_save": (_I, [ctypes.c_char_p, ctypes.c_char_p]),
+    "qubo_tune_set": (_I, [ctypes.POINTER(_TuneEntry), _I]),
+    "qubo_tune_lookup": (_I, [_I, _I, ctypes.POINTER(_TuneEntry)]),
+    "qubo_tune_clear": (None, []),
+    "qubo_device_key": (_I, [ctypes.c_char_p, _I]),
     "qubo_last_error": (ctypes.c_char_p, []),
     "qubo_version": (ctypes.c_char_p, []),
 }
@@ -341,13 +355,73 @@ def plan_info(Q, *, B: int = 0, L: int = 0, tier: int = 0, vgpr_levels: int = 0)
 def probe_valu(op: str = "add", waves_per_simd: int = 4, iters: int = 4096):
     """Measured int32 VALU lane-operations per second.
 
-    op: 'add', 'min3', 'add+salu' (a scalar add per two vector adds) or
-    'add+branch' (a never-taken compare/branch per 16 vector adds)."""
+    op: 'add', 'min3', 'add+salu' (a scalar add per two vector adds),
+    'add+branch' (a never-taken compare/branch per 16 vector adds), 'pk_add16'
+    or 'pk_min16' (packed 16-bit pairs; one lane-op covers two values)."""
     rate, ms = ctypes.c_double(), ctypes.c_double()
-    ops = {"add": 0, "min3": 1, "add+salu": 2, "add+branch": 3}
+    ops = {"add": 0, "min3": 1, "add+salu": 2, "add+branch": 3, "pk_add16": 4, "pk_min16": 5}
     _check(lib().qubo_probe_valu(ops[op], int(waves_per_simd), int(iters),
                                  ctypes.byref(rate), ctypes.byref(ms)))
     return rate.value, ms.value
+
+
+_DTYPES = {"int32": QUBO_INT32, "fp32": QUBO_FP32}
+
+
+def _entry_dict(e: _TuneEntry) -> dict:
+    return {"n": e.n, "dtype": "fp32" if e.dtype == QUBO_FP32 else "int32", "B": e.B, "L": e.L,
+            "tier": e.tier, "vgpr_levels": e.vgpr_levels, "walk_ms": e.walk_ms}
+
+
+def autotune(n_min: int, n_max: int, dtype: str = "int32", reps: int = 2,
+             cache_path: Optional[str] = None) -> List[dict]:
+    """Time every runnable walk plan for n in [n_min, n_max] and install the
+    fastest per n (see ``qubo_autotune``); returns the winners."""
+    cap = n_max - n_min + 1
+    out = (_TuneEntry * max(cap, 1))()
+    cnt = ctypes.c_int()
+    _check(lib().qubo_autotune(int(n_min), int(n_max), _DTYPES[dtype], int(reps),
+                               cache_path.encode() if cache_path else None, out, cap,
+                               ctypes.byref(cnt)))
+    return [_entry_dict(out[k]) for k in range(min(cnt.value, cap))]
+
+
+def tune_load(path: str, device_key: Optional[str] = None) -> int:
+    """Load a tuning cache (device_key None: must match this device)."""
+    cnt = ctypes.c_int()
+    _check(lib().qubo_tune_load(path.encode(), device_key.encode() if device_key else None,
+                                ctypes.byref(cnt)))
+    return cnt.value
+
+
+def tune_save(path: str, device_key: Optional[str] = None):
+    _check(lib().qubo_tune_save(path.encode(), device_key.encode() if device_key else None))
+
+
+def tune_set(entries: Sequence[dict]):
+    arr = (_TuneEntry * max(len(entries), 1))()
+    for k, e in enumerate(entries):
+        arr[k] = _TuneEntry(int(e["n"]), _DTYPES[e.get("dtype", "int32")], int(e["B"]),
+                            int(e.get("L", 0)), int(e["tier"]), int(e["vgpr_levels"]),
+                            float(e.get("walk_ms", 0.0)))
+    _check(lib().qubo_tune_set(arr, len(entries)))
+
+
+def tune_lookup(n: int, dtype: str = "int32") -> Optional[dict]:
+    e = _TuneEntry()
+    if lib().qubo_tune_lookup(int(n), _DTYPES[dtype], ctypes.byref(e)):
+        return _entry_dict(e)
+    return None
+
+
+def tune_clear():
+    lib().qubo_tune_clear()
+
+
+def device_key() -> str:
+    buf = ctypes.create_string_buffer(128)
+    _check(lib().qubo_device_key(buf, 128))
+    return buf.value.decode()
 
 
 def version() -> str:

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cstring>
 #include <numeric>
+#include <tuple>
 
 #include "runtime.h"
 
@@ -49,6 +50,7 @@ qubo_status_t batch_build(qubo_batch *b, int count, const void *const *Q, const 
 {
     std::vector<qplan::Plan> plans(static_cast<size_t>(count));
     std::string msg;
+    qrt::tune_autoload();
     for (int i = 0; i < count; i++) {
         if (!Q[i]) {
             qrt::set_error("null Q in batch at " + std::to_string(i));
@@ -60,13 +62,17 @@ qubo_status_t batch_build(qubo_batch *b, int count, const void *const *Q, const 
             return st;
         }
     }
-    // Walk order: most walk work first; direct (tiny) instances last.
+    // Walk order: grouped by walk kernel variant (one persistent launch per
+    // group), most walk work first inside a group; direct (tiny) instances last.
     b->order.resize(size_t(count));
     std::iota(b->order.begin(), b->order.end(), 0);
     std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
         const qplan::Plan &px = plans[size_t(x)], &py = plans[size_t(y)];
-        const int ax = px.direct ? -1 : px.n, ay = py.direct ? -1 : py.n;
-        return ax > ay;
+        if (px.direct != py.direct) return !px.direct;
+        const auto kx = std::make_tuple(px.mcols, px.vgpr_levels, px.tier);
+        const auto ky = std::make_tuple(py.mcols, py.vgpr_levels, py.tier);
+        if (kx != ky) return kx > ky;
+        return px.n > py.n;
     });
     b->qf_copy.resize(size_t(count));
     for (int w = 0; w < count; w++) {

@@ -68,10 +68,9 @@ struct FinalRes {
     int32_t pad;
 };
 
-// Builds M, EB, S, K for every instance and zeroes the item counter
-// (d_counter may be null).
-hipError_t launch_tables(const Inst *d_insts, int n_inst, int max_A, unsigned long long *d_counter,
-                         hipStream_t stream);
+// Builds M, EB, S, K for every instance and zeroes n_counters item counters.
+hipError_t launch_tables(const Inst *d_insts, int n_inst, int max_A, unsigned long long *d_counters,
+                         int n_counters, hipStream_t stream);
 
 // Persistent Gray walk over all items; `waves` resident wavefronts.  d_k is
 // the contiguous array of K tables (instance i's at insts[i].kslot*kKTable).

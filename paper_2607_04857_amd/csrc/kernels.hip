@@ -149,10 +149,12 @@ __device__ __forceinline__ void lexmin(int64_t &bE, uint64_t &bI, int64_t e, uin
 // ---------------------------------------------------------------- tables
 
 __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ insts,
-                                                     unsigned long long *__restrict__ counter)
+                                                     unsigned long long *__restrict__ counters,
+                                                     int n_counters)
 {
     const Inst I = insts[blockIdx.y];
-    if (counter && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *counter = 0ull;
+    if (blockIdx.x == 0 && blockIdx.y == 0)
+        for (int c = int(threadIdx.x); c < n_counters; c += int(blockDim.x)) counters[c] = 0ull;
     if (I.direct) return;
     const int n = I.n, A = I.A, B = I.B;
     const uint32_t NS = 1u << B;
@@ -685,13 +687,14 @@ __global__ __launch_bounds__(256) void finish_kernel(const Inst *__restrict__ in
 
 // ---------------------------------------------------------------- launchers
 
-hipError_t launch_tables(const Inst *d_insts, int n_inst, int max_A, unsigned long long *d_counter,
-                         hipStream_t stream)
+hipError_t launch_tables(const Inst *d_insts, int n_inst, int max_A, unsigned long long *d_counters,
+                         int n_counters, hipStream_t stream)
 {
     int bx = (max_A * 1024 + 255) / 256;
     if (bx < 1) bx = 1;
     if (bx > 64) bx = 64;
-    hipLaunchKernelGGL(tables_kernel, dim3(bx, n_inst), dim3(256), 0, stream, d_insts, d_counter);
+    hipLaunchKernelGGL(tables_kernel, dim3(bx, n_inst), dim3(256), 0, stream, d_insts, d_counters,
+                       n_counters);
     return hipGetLastError();
 }
 

@@ -1,8 +1,12 @@
 // plan.cpp -- fold, exactness proof / fixed-point scale, split and work items.
 #include "plan.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <utility>
 
 namespace qplan {
 
@@ -15,7 +19,77 @@ constexpr int kMinB = 6;           // one column per lane
 constexpr int kMaxB = 10;          // 16 columns per lane (VGPR budget)
 constexpr int kDefaultTier = 2;
 
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, TuneEntry> g_tune;   // (n, dtype) -> entry
+
+bool variant_built(int mcols, int G)
+{
+    if (G == 12) return mcols == 1 || mcols == 2 || mcols == 4 || mcols == 8 || mcols == 16;
+    if (G == 8) return mcols == 8 || mcols == 16;
+    if (G == 6 || G == 5) return mcols == 16;
+    return false;
+}
+
 }  // namespace
+
+void tune_put(const TuneEntry &e)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[{e.n, int(e.dtype)}] = e;
+}
+
+bool tune_get(int n, qubo_dtype_t dtype, TuneEntry *out)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find({n, int(dtype)});
+    if (it == g_tune.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+void tune_clear()
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+}
+
+std::vector<TuneEntry> tune_all()
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::vector<TuneEntry> v;
+    for (const auto &kv : g_tune) v.push_back(kv.second);
+    return v;
+}
+
+bool tune_valid(const TuneEntry &e, std::string *msg)
+{
+    if (e.n <= kDirectMaxN || e.n > kMaxN) {
+        *msg = "tuning entry n must be in [15, 60]";
+        return false;
+    }
+    if (e.dtype != QUBO_INT32 && e.dtype != QUBO_FP32) {
+        *msg = "tuning entry has an unknown dtype";
+        return false;
+    }
+    if (e.B < kMinB || e.B > kMaxB || e.n - e.B < kSuper) {
+        *msg = "tuning entry B must be in [6, 10] with n - B >= 5";
+        return false;
+    }
+    if (e.tier != 1 && e.tier != 2) {
+        *msg = "tuning entry tier must be 1 or 2";
+        return false;
+    }
+    if (!variant_built((1 << e.B) / kWave, e.vgpr_levels)) {
+        *msg = "tuning entry names a (B, vgpr_levels) walk variant that is not built";
+        return false;
+    }
+    const int A = e.n - e.B;
+    if (e.L != 0 && (e.L < kSuper || e.L > A || A - e.L > 20)) {
+        *msg = "tuning entry L must be 0 or in [max(5, A - 20), A]";
+        return false;
+    }
+    return true;
+}
 
 qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_options_t *opt,
                         Plan *out, std::string *msg, bool many)
@@ -100,7 +174,12 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
         P.eps_q = double(nnz) * std::ldexp(1.0, -p - 1);
     }
 
-    int B = (opt && opt->B) ? opt->B : kDefaultB;
+    // A tuned choice applies when the caller overrides none of the walk knobs.
+    TuneEntry tuned;
+    const bool overridden = opt && (opt->B || opt->L || opt->tier || opt->vgpr_levels);
+    const bool use_tune = !overridden && n > kDirectMaxN && tune_get(n, dtype, &tuned);
+
+    int B = (opt && opt->B) ? opt->B : (use_tune ? tuned.B : kDefaultB);
     if (opt && opt->B && (opt->B < kMinB || opt->B > kMaxB)) {
         *msg = "option B must be in [6, 10]";
         return QUBO_EINVAL;
@@ -109,8 +188,8 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
         *msg = "option tier must be 0 (default), 1 or 2";
         return QUBO_EINVAL;
     }
-    const int tier = (opt && opt->tier) ? opt->tier : kDefaultTier;
-    int vgpr_levels = (opt && opt->vgpr_levels) ? opt->vgpr_levels : 0;
+    const int tier = (opt && opt->tier) ? opt->tier : (use_tune ? tuned.tier : kDefaultTier);
+    int vgpr_levels = (opt && opt->vgpr_levels) ? opt->vgpr_levels : (use_tune ? tuned.vgpr_levels : 0);
     if (vgpr_levels != 0 && vgpr_levels != 12 && vgpr_levels != 8 && vgpr_levels != 6 &&
         vgpr_levels != 5) {
         *msg = "option vgpr_levels must be 0, 5, 6, 8 or 12";
@@ -154,6 +233,8 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
             *msg = "option L must be in [5, A]";
             return QUBO_EINVAL;
         }
+    } else if (use_tune && tuned.L && !many && tuned.B == P.B) {
+        L = tuned.L;
     } else {
         L = P.A < 14 ? P.A : 14;
         if (!many && P.A - L < 11) L = P.A - 11 < 9 ? 9 : P.A - 11;

@@ -38,9 +38,28 @@ struct Plan {
     std::vector<int32_t> T;    // folded (and scaled) upper-triangular n x n
 };
 
+// One tuned walk choice for instances of n variables and a dtype.
+struct TuneEntry {
+    int n = 0;
+    qubo_dtype_t dtype = QUBO_INT32;
+    int B = 0, L = 0, tier = 0, vgpr_levels = 0;
+    double walk_ms = 0.0;      // measured walk time of the chosen plan
+};
+
+// Process-wide tuning table (thread-safe).  make_plan consults it when the
+// caller overrides none of B, L, tier and vgpr_levels.
+void tune_put(const TuneEntry &e);
+bool tune_get(int n, qubo_dtype_t dtype, TuneEntry *out);
+void tune_clear();
+std::vector<TuneEntry> tune_all();
+
+// Check that a tuning entry describes a plan this build can run.
+bool tune_valid(const TuneEntry &e, std::string *msg);
+
 // Build a plan from a host Q.  Returns QUBO_OK or an error with msg set.
 // `many`: the instance shares its walk launch with others (batch, server),
-// so it needs no item-level parallelism of its own.
+// so it needs no item-level parallelism of its own (a tuned L is then
+// ignored: it was measured for a lone instance).
 qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_options_t *opt,
                         Plan *out, std::string *msg, bool many = false);
 

@@ -4,8 +4,9 @@
 // instructions per loop iteration, so no dependency chain limits issue; the
 // grid places waves_per_simd waves on every SIMD of the device.  Ops: 0
 // v_add_u32; 1 v_min3_i32; 2 v_add_u32 with one s_add_i32 per two vector adds;
-// 3 v_add_u32 with one never-taken s_cmp/s_cbranch per 16 vector adds.  Only
-// vector lane-operations are counted.
+// 3 v_add_u32 with one never-taken s_cmp/s_cbranch per 16 vector adds; 4
+// v_pk_add_u16; 5 v_pk_min_i16.  Vector instructions x 64 lanes are counted
+// (a packed instruction is one lane-operation on two 16-bit halves).
 #include <hip/hip_runtime.h>
 
 #include "runtime.h"
@@ -27,6 +28,10 @@ __global__ __launch_bounds__(64) void valu_probe_kernel(int iters, int32_t *__re
             for (int k = 0; k < 16; k++) {
                 if constexpr (OP == 1)
                     asm volatile("v_min3_i32 %0, %0, %1, %2" : "+v"(a[k]) : "v"(b), "v"(c));
+                else if constexpr (OP == 4)
+                    asm volatile("v_pk_add_u16 %0, %0, %1" : "+v"(a[k]) : "v"(b));
+                else if constexpr (OP == 5)
+                    asm volatile("v_pk_min_i16 %0, %0, %1" : "+v"(a[k]) : "v"(b));
                 else
                     asm volatile("v_add_u32 %0, %1, %0" : "+v"(a[k]) : "v"(b));
                 if constexpr (OP == 2)   // one scalar add per two vector adds
@@ -49,7 +54,7 @@ extern "C" qubo_status_t qubo_probe_valu(int op, int waves_per_simd, int iters,
                                          double *lane_ops_per_s, double *ms)
 {
     qrt::set_error("");
-    if (op < 0 || op > 3 || waves_per_simd < 1 || waves_per_simd > 8 || iters < 1) {
+    if (op < 0 || op > 5 || waves_per_simd < 1 || waves_per_simd > 8 || iters < 1) {
         qrt::set_error("bad probe arguments");
         return QUBO_EINVAL;
     }
@@ -78,8 +83,12 @@ extern "C" qubo_status_t qubo_probe_valu(int op, int waves_per_simd, int iters,
                 hipLaunchKernelGGL(valu_probe_kernel<1>, dim3(blocks), dim3(64), 0, s, iters, d_out);
             else if (op == 2)
                 hipLaunchKernelGGL(valu_probe_kernel<2>, dim3(blocks), dim3(64), 0, s, iters, d_out);
-            else
+            else if (op == 3)
                 hipLaunchKernelGGL(valu_probe_kernel<3>, dim3(blocks), dim3(64), 0, s, iters, d_out);
+            else if (op == 4)
+                hipLaunchKernelGGL(valu_probe_kernel<4>, dim3(blocks), dim3(64), 0, s, iters, d_out);
+            else
+                hipLaunchKernelGGL(valu_probe_kernel<5>, dim3(blocks), dim3(64), 0, s, iters, d_out);
             (void)hipEventRecord(e1, s);
         }
         if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess ||

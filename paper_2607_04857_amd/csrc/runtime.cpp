@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <mutex>
 
 namespace qrt {
@@ -75,7 +76,7 @@ static JobOffsets compute_offsets(const Job &job, size_t *stage_bytes, size_t *b
     }
     *stage_bytes = off;
     o.counter = off;
-    off = align_up(off + sizeof(unsigned long long), 256);
+    off = align_up(off + std::max<size_t>(1, job.groups.size()) * sizeof(unsigned long long), 256);
     for (size_t i = 0; i < ni; i++) {
         const qplan::Plan &P = job.plans[i];
         const size_t A = P.direct ? 0 : size_t(P.A), NS = P.direct ? 0 : (size_t(1) << P.B);
@@ -96,43 +97,50 @@ static JobOffsets compute_offsets(const Job &job, size_t *stage_bytes, size_t *b
     return o;
 }
 
+bool same_variant(const qplan::Plan &a, const qplan::Plan &b)
+{
+    return a.mcols == b.mcols && a.vgpr_levels == b.vgpr_levels && a.tier == b.tier;
+}
+
 qubo_status_t job_layout(Job *job, int waves_per_cu)
 {
     job->max_A = 0;
     job->total_items = 0;
     job->states = 0.0;
-    job->mcols = 0;
-    job->tier = 0;
-    job->vgpr_levels = 0;
-    for (const qplan::Plan &P : job->plans) {
-        job->states += std::ldexp(1.0, P.n);
-        if (P.direct) continue;
-        if (job->mcols == 0) {
-            job->mcols = P.mcols;
-            job->tier = P.tier;
-            job->vgpr_levels = P.vgpr_levels;
-        } else if (job->mcols != P.mcols || job->tier != P.tier ||
-                   job->vgpr_levels != P.vgpr_levels) {
-            set_error("all walked instances of one job must share B, tier and vgpr_levels");
-            return QUBO_EINVAL;
-        }
-        if (P.A > job->max_A) job->max_A = P.A;
-        job->total_items += P.items;
-    }
+    job->groups.clear();
     DeviceInfo di;
     qubo_status_t st = device_info(&di);
     if (st != QUBO_OK) return st;
-    int wpc = waves_per_cu;
-    if (job->mcols && !qk::walk_variant_exists(job->mcols, job->vgpr_levels)) {
-        set_error("no walk kernel built for this B / vgpr_levels");
-        return QUBO_EINVAL;
+    for (size_t i = 0; i < job->plans.size(); i++) {
+        const qplan::Plan &P = job->plans[i];
+        job->states += std::ldexp(1.0, P.n);
+        if (P.direct) continue;
+        if (job->groups.empty() || !same_variant(job->plans[size_t(job->groups.back().first)], P) ||
+            size_t(job->groups.back().first + job->groups.back().count) != i) {
+            if (!qk::walk_variant_exists(P.mcols, P.vgpr_levels)) {
+                set_error("no walk kernel built for this B / vgpr_levels");
+                return QUBO_EINVAL;
+            }
+            WalkGroup g;
+            g.first = int(i);
+            g.mcols = P.mcols;
+            g.vgpr_levels = P.vgpr_levels;
+            g.tier = P.tier;
+            job->groups.push_back(g);
+        }
+        WalkGroup &g = job->groups.back();
+        g.count = int(i) + 1 - g.first;
+        g.items += P.items;
+        if (P.A > job->max_A) job->max_A = P.A;
+        job->total_items += P.items;
     }
-    if (wpc <= 0)
-        wpc = job->mcols ? qk::walk_occupancy(job->mcols, job->vgpr_levels, job->tier) : 1;
-    if (wpc <= 0) wpc = 1;
-    uint64_t waves = uint64_t(di.cus) * uint64_t(wpc);
-    if (job->total_items < waves) waves = job->total_items;
-    job->waves = int(waves);
+    for (WalkGroup &g : job->groups) {
+        int wpc = waves_per_cu > 0 ? waves_per_cu : qk::walk_occupancy(g.mcols, g.vgpr_levels, g.tier);
+        if (wpc <= 0) wpc = 1;
+        uint64_t waves = uint64_t(di.cus) * uint64_t(wpc);
+        if (g.items < waves) waves = g.items;
+        g.waves = int(waves);
+    }
     size_t sb = 0, b = 0;
     (void)compute_offsets(*job, &sb, &b);
     job->stage_bytes = sb;
@@ -154,7 +162,16 @@ qubo_status_t job_bind(Job *job, void *d_mem)
     job->d_out = reinterpret_cast<qk::FinalRes *>(base + o.out);
     job->d_k = reinterpret_cast<int32_t *>(base + o.K);
     std::vector<qk::Inst> insts(job->plans.size());
-    uint64_t item = 0;
+    uint64_t item = 0;        // result slot of the instance's first item (whole job)
+    // walk numbering restarts at 0 in every group
+    std::vector<uint64_t> group_base(job->plans.size(), 0);
+    for (const WalkGroup &g : job->groups) {
+        uint64_t acc = 0;
+        for (int k = g.first; k < g.first + g.count; k++) {
+            group_base[size_t(k)] = acc;
+            acc += job->plans[size_t(k)].items;
+        }
+    }
     for (size_t i = 0; i < job->plans.size(); i++) {
         const qplan::Plan &P = job->plans[i];
         qk::Inst &I = insts[i];
@@ -171,9 +188,9 @@ qubo_status_t job_bind(Job *job, void *d_mem)
         I.L = P.L;
         I.direct = P.direct ? 1 : 0;
         I.kslot = int(i);
-        I.item_begin = item;
+        I.item_begin = group_base[i];
+        I.item_end = group_base[i] + (P.direct ? 0 : P.items);
         item += P.direct ? 0 : P.items;
-        I.item_end = item;
         I.item_local0 = 0;
         I.n_items = P.direct ? 0 : P.items;
         const size_t nn = size_t(P.n) * P.n;
@@ -188,12 +205,16 @@ qubo_status_t job_enqueue_kernels(const Job &job, hipStream_t stream, hipEvent_t
                                   hipEvent_t walk_end)
 {
     const int ni = int(job.plans.size());
-    QRT_HIP(qk::launch_tables(job.d_insts, ni, job.max_A, job.d_counter, stream), "tables kernel");
+    QRT_HIP(qk::launch_tables(job.d_insts, ni, job.max_A, job.d_counter, int(job.groups.size()),
+                              stream),
+            "tables kernel");
     if (walk_begin) QRT_HIP(hipEventRecord(walk_begin, stream), "hipEventRecord");
-    if (job.total_items > 0)
-        QRT_HIP(qk::launch_walk(job.mcols, job.vgpr_levels, job.tier, job.d_insts, ni,
-                                job.total_items, job.d_counter, job.d_k, job.waves, stream),
+    for (size_t k = 0; k < job.groups.size(); k++) {
+        const WalkGroup &g = job.groups[k];
+        QRT_HIP(qk::launch_walk(g.mcols, g.vgpr_levels, g.tier, job.d_insts + g.first, g.count,
+                                g.items, job.d_counter + k, job.d_k, g.waves, stream),
                 "walk kernel");
+    }
     if (walk_end) QRT_HIP(hipEventRecord(walk_end, stream), "hipEventRecord");
     QRT_HIP(qk::launch_finish(job.d_insts, ni, job.d_out, stream), "finish kernel");
     return QUBO_OK;
@@ -225,7 +246,7 @@ qubo_status_t job_result(const Job &job, int i, const qk::FinalRes &fr, qubo_res
 
 // ------------------------------------------------------------------ C ABI
 
-namespace {
+namespace qrt {
 
 hipStream_t thread_stream(qubo_status_t *st)
 {
@@ -295,6 +316,13 @@ qubo_status_t solve_planned(qrt::Job &job, hipStream_t stream, int waves_per_cu,
     return QUBO_OK;
 }
 
+}  // namespace qrt
+
+namespace {
+
+using qrt::solve_planned;
+using qrt::thread_stream;
+
 qubo_status_t check_k(int k, int n, qubo_state_t *topk)
 {
     if (k < 0 || k > 1024) {
@@ -325,6 +353,7 @@ qubo_status_t solve_host(const void *Q, int n, qubo_dtype_t dtype, int k, const 
     }
     qubo_status_t st = check_k(k, n, topk);
     if (st != QUBO_OK) return st;
+    qrt::tune_autoload();
     qrt::Job job;
     job.plans.resize(1);
     std::string msg;

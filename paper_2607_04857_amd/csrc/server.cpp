@@ -25,6 +25,7 @@
 #include <deque>
 #include <mutex>
 #include <thread>
+#include <tuple>
 #include <unordered_map>
 
 #include "runtime.h"
@@ -32,6 +33,10 @@
 namespace {
 
 using Clock = std::chrono::steady_clock;
+
+// Walk launches per tick are one per distinct walk kernel variant among the
+// active requests; this bounds the number of built variants (B x cache x tier).
+constexpr int kMaxTickLaunches = 32;
 
 enum class RState { Queued, Active, Done, Failed };
 
@@ -65,7 +70,7 @@ struct qubo_server {
     int dev = 0;
     size_t budget = 0;
     int max_slots = 0;
-    int waves_cap = 0;            // resident walk waves of the device
+    int cus = 0;                  // compute units of the device
     uint64_t tick_items = 0;      // work items per tick (two per resident wave)
     hipStream_t stream = nullptr;
     int32_t *d_karena = nullptr;  // max_slots K tables
@@ -180,7 +185,7 @@ qubo_status_t setup_request(qubo_server *s, Request *r)
     QRT_HIP(hipMemcpyAsync(r->d_mem, r->job.stage.data(), r->job.stage_bytes, hipMemcpyHostToDevice,
                            s->stream),
             "hipMemcpyAsync H2D");
-    QRT_HIP(qk::launch_tables(r->job.d_insts, 1, r->job.max_A, nullptr, s->stream), "tables kernel");
+    QRT_HIP(qk::launch_tables(r->job.d_insts, 1, r->job.max_A, nullptr, 0, s->stream), "tables kernel");
     return QUBO_OK;
 }
 
@@ -206,38 +211,66 @@ qubo_status_t enqueue_tick(qubo_server *s, TickBuf &t, bool *launched)
             walkers.push_back(r);
         }
     }
-    // water-filling over the per-tick item budget, fewest remaining first
+    // water-filling over the per-tick item budget, fewest remaining first,
+    // then grouped by walk variant (one launch per variant group)
     std::sort(walkers.begin(), walkers.end(), [](Request *a, Request *b) {
         return a->job.plans[0].items - a->next_item < b->job.plans[0].items - b->next_item;
     });
-    uint64_t budget = s->tick_items, g = 0;
-    int nw = 0;
+    std::vector<uint64_t> share(walkers.size(), 0);
+    uint64_t budget = s->tick_items, total = 0;
     for (size_t k = 0; k < walkers.size(); k++) {
         Request *r = walkers[k];
         const uint64_t left = r->job.plans[0].items - r->next_item;
-        const uint64_t share = std::max<uint64_t>(1, budget / (walkers.size() - k));
-        const uint64_t c = std::min(left, share);
+        const uint64_t fair = std::max<uint64_t>(1, budget / (walkers.size() - k));
+        share[k] = std::min(left, fair);
+        budget = budget > share[k] ? budget - share[k] : 0;
+        total += share[k];
+    }
+    if (total == 0 && finishers.empty()) return QUBO_OK;
+    // descriptors grouped by variant; item numbering restarts in every group
+    std::vector<size_t> idx(walkers.size());
+    for (size_t k = 0; k < idx.size(); k++) idx[k] = k;
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) {
+        const qplan::Plan &a = walkers[x]->job.plans[0], &b = walkers[y]->job.plans[0];
+        return std::make_tuple(a.mcols, a.vgpr_levels, a.tier) < std::make_tuple(b.mcols, b.vgpr_levels, b.tier);
+    });
+    struct Launch { int first, count; uint64_t items; const qplan::Plan *P; };
+    std::vector<Launch> launches;
+    int nw = 0;
+    uint64_t g = 0;
+    for (size_t k : idx) {
+        Request *r = walkers[k];
+        const uint64_t c = share[k];
+        const qplan::Plan &P = r->job.plans[0];
+        if (launches.empty() || !qrt::same_variant(*launches.back().P, P)) {
+            launches.push_back({nw, 0, 0, &P});
+            g = 0;
+        }
         qk::Inst I = r->base;
         I.item_begin = g;
         I.item_end = g + c;
         I.item_local0 = r->next_item;
         t.h_walk[nw++] = I;
         g += c;
-        budget = budget > c ? budget - c : 0;
+        launches.back().count++;
+        launches.back().items += c;
         r->next_item += c;
-        if (r->next_item == r->job.plans[0].items) finishers.push_back(r);
+        if (r->next_item == P.items) finishers.push_back(r);
     }
-    if (g == 0 && finishers.empty()) return QUBO_OK;
-    if (g > 0) {
+    if (nw > 0) {
         QRT_HIP(hipMemcpyAsync(t.d_walk, t.h_walk, size_t(nw) * sizeof(qk::Inst), hipMemcpyHostToDevice,
                                s->stream),
                 "hipMemcpyAsync tick");
-        QRT_HIP(hipMemsetAsync(s->d_counter, 0, sizeof(unsigned long long), s->stream), "hipMemsetAsync");
-        const int waves = int(std::min<uint64_t>(g, uint64_t(s->waves_cap)));
-        const qrt::Job &j0 = walkers[0]->job;
-        QRT_HIP(qk::launch_walk(j0.mcols, j0.vgpr_levels, j0.tier, t.d_walk, nw, g, s->d_counter,
-                                s->d_karena, waves, s->stream),
-                "walk kernel");
+        QRT_HIP(hipMemsetAsync(s->d_counter, 0, launches.size() * sizeof(unsigned long long), s->stream),
+                "hipMemsetAsync");
+        for (size_t k = 0; k < launches.size(); k++) {
+            const Launch &L = launches[k];
+            const int occ = qk::walk_occupancy(L.P->mcols, L.P->vgpr_levels, L.P->tier);
+            const int waves = int(std::min<uint64_t>(L.items, uint64_t(s->cus) * uint64_t(occ)));
+            QRT_HIP(qk::launch_walk(L.P->mcols, L.P->vgpr_levels, L.P->tier, t.d_walk + L.first, L.count,
+                                    L.items, s->d_counter + k, s->d_karena, waves, s->stream),
+                    "walk kernel");
+        }
     }
     if (!finishers.empty()) {
         for (size_t i = 0; i < finishers.size(); i++) t.h_fin[i] = finishers[i]->base;
@@ -351,11 +384,12 @@ qubo_status_t server_init(qubo_server *s, size_t budget, int max_slots)
     qrt::DeviceInfo di;
     qubo_status_t st = qrt::device_info(&di);
     if (st != QUBO_OK) return st;
-    s->waves_cap = di.cus * qk::walk_occupancy(16, 6, 2);
-    s->tick_items = uint64_t(s->waves_cap) * 2;
+    s->cus = di.cus;
+    s->tick_items = uint64_t(di.cus) * uint64_t(qk::walk_occupancy(16, 6, 2)) * 2;
     QRT_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "hipStreamCreate");
     QRT_HIP(hipMalloc(&s->d_karena, size_t(max_slots) * qk::kKTable * sizeof(int32_t)), "hipMalloc");
-    QRT_HIP(hipMalloc(&s->d_counter, sizeof(unsigned long long)), "hipMalloc");
+    // one item counter per walk variant launched in a tick
+    QRT_HIP(hipMalloc(&s->d_counter, kMaxTickLaunches * sizeof(unsigned long long)), "hipMalloc");
     for (int k = max_slots - 1; k >= 0; k--) s->free_kslots.push_back(k);
     for (TickBuf &t : s->ticks) {
         QRT_HIP(hipEventCreateWithFlags(&t.done, hipEventDisableTiming), "hipEventCreate");
@@ -414,6 +448,7 @@ qubo_status_t qubo_server_submit(qubo_server_t *s, const void *Q, int n, qubo_dt
         Request *r = new Request();
         r->job.plans.resize(1);
         std::string msg;
+        qrt::tune_autoload();
         qubo_status_t st = qplan::make_plan(Q, n, dtype, nullptr, &r->job.plans[0], &msg, true);
         if (st != QUBO_OK) {
             delete r;

@@ -1,0 +1,707 @@
+// tune.cpp -- empirical choice of the walk plan per (n, dtype) and its cache.
+//
+// The walk has several knobs whose best setting depends on n and on the
+// device: the suffix width B (columns per lane, i.e. the wave's block shape),
+// the row-cache depth (Gray levels whose M_int rows stay in VGPRs, which
+// trades VGPRs for resident waves), the bound tier and the work-item size L.
+// The paper reports reaching its kernel's speed by extensive experimentation
+// on its GPU (Sec. IV); here that experimentation is a function: time every
+// plan this build can run on a synthetic instance of each n, keep the
+// fastest, and let the planner use it.  Every candidate must return the same
+// (E*, index*) -- plan invariance is checked on every tuning run.
+//
+// Cache file: a JSON object
+//   {"format": "qubo-tune-1", "device": "<arch>/<CUs>cu",
+//    "entries": [{"n": .., "dtype": "int32"|"fp32", "B": .., "L": ..,
+//                 "tier": .., "vgpr_levels": .., "walk_ms": ..}, ...]}
+#include <algorithm>
+#include <cctype>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "runtime.h"
+
+namespace {
+
+// ------------------------------------------------------------ small JSON
+
+struct JVal {
+    enum Kind { Null, Bool, Num, Str, Arr, Obj } kind = Null;
+    double num = 0.0;
+    std::string str;
+    std::vector<JVal> arr;
+    std::vector<std::pair<std::string, JVal>> obj;
+
+    const JVal *get(const char *key) const
+    {
+        for (const auto &kv : obj)
+            if (kv.first == key) return &kv.second;
+        return nullptr;
+    }
+};
+
+struct JParser {
+    const std::string &s;
+    size_t i = 0;
+    std::string err;
+
+    explicit JParser(const std::string &text) : s(text) {}
+
+    void ws()
+    {
+        while (i < s.size() && std::isspace(static_cast<unsigned char>(s[i]))) i++;
+    }
+    bool fail(const char *what)
+    {
+        if (err.empty()) err = std::string(what) + " at offset " + std::to_string(i);
+        return false;
+    }
+    bool lit(const char *w)
+    {
+        const size_t n = std::strlen(w);
+        if (s.compare(i, n, w) != 0) return fail("bad literal");
+        i += n;
+        return true;
+    }
+    bool string(std::string *out)
+    {
+        if (i >= s.size() || s[i] != '"') return fail("expected string");
+        i++;
+        out->clear();
+        while (i < s.size() && s[i] != '"') {
+            char c = s[i++];
+            if (c == '\\') {
+                if (i >= s.size()) return fail("bad escape");
+                char e = s[i++];
+                switch (e) {
+                case 'n': c = '\n'; break;
+                case 't': c = '\t'; break;
+                case 'r': c = '\r'; break;
+                case 'b': c = '\b'; break;
+                case 'f': c = '\f'; break;
+                case '"': case '\\': case '/': c = e; break;
+                default: return fail("unsupported escape");
+                }
+            }
+            out->push_back(c);
+        }
+        if (i >= s.size()) return fail("unterminated string");
+        i++;
+        return true;
+    }
+    bool value(JVal *v, int depth)
+    {
+        if (depth > 32) return fail("nesting too deep");
+        ws();
+        if (i >= s.size()) return fail("unexpected end");
+        const char c = s[i];
+        if (c == '{') {
+            v->kind = JVal::Obj;
+            i++;
+            ws();
+            if (i < s.size() && s[i] == '}') {
+                i++;
+                return true;
+            }
+            for (;;) {
+                ws();
+                std::pair<std::string, JVal> kv;
+                if (!string(&kv.first)) return false;
+                ws();
+                if (i >= s.size() || s[i] != ':') return fail("expected ':'");
+                i++;
+                if (!value(&kv.second, depth + 1)) return false;
+                v->obj.push_back(std::move(kv));
+                ws();
+                if (i < s.size() && s[i] == ',') {
+                    i++;
+                    continue;
+                }
+                if (i < s.size() && s[i] == '}') {
+                    i++;
+                    return true;
+                }
+                return fail("expected ',' or '}'");
+            }
+        }
+        if (c == '[') {
+            v->kind = JVal::Arr;
+            i++;
+            ws();
+            if (i < s.size() && s[i] == ']') {
+                i++;
+                return true;
+            }
+            for (;;) {
+                JVal e;
+                if (!value(&e, depth + 1)) return false;
+                v->arr.push_back(std::move(e));
+                ws();
+                if (i < s.size() && s[i] == ',') {
+                    i++;
+                    continue;
+                }
+                if (i < s.size() && s[i] == ']') {
+                    i++;
+                    return true;
+                }
+                return fail("expected ',' or ']'");
+            }
+        }
+        if (c == '"') {
+            v->kind = JVal::Str;
+            return string(&v->str);
+        }
+        if (c == 't') {
+            v->kind = JVal::Bool;
+            v->num = 1;
+            return lit("true");
+        }
+        if (c == 'f') {
+            v->kind = JVal::Bool;
+            return lit("false");
+        }
+        if (c == 'n') return lit("null");
+        const char *b = s.c_str() + i;
+        char *e = nullptr;
+        v->num = std::strtod(b, &e);
+        if (e == b) return fail("bad value");
+        v->kind = JVal::Num;
+        i += size_t(e - b);
+        return true;
+    }
+    bool parse(JVal *root)
+    {
+        if (!value(root, 0)) return false;
+        ws();
+        if (i != s.size()) return fail("trailing characters");
+        return true;
+    }
+};
+
+constexpr const char *kFormat = "qubo-tune-1";
+
+const char *dtype_name(qubo_dtype_t d) { return d == QUBO_FP32 ? "fp32" : "int32"; }
+
+bool int_field(const JVal &o, const char *key, int *out, std::string *msg)
+{
+    const JVal *v = o.get(key);
+    if (!v || v->kind != JVal::Num || v->num != std::floor(v->num) || std::fabs(v->num) > 1e9) {
+        *msg = std::string("entry field '") + key + "' missing or not an integer";
+        return false;
+    }
+    *out = int(v->num);
+    return true;
+}
+
+// Parse a cache text into entries; checks the format tag and device key.
+bool parse_cache(const std::string &text, const std::string &device_key,
+                 std::vector<qplan::TuneEntry> *entries, std::string *msg)
+{
+    JVal root;
+    JParser p(text);
+    if (!p.parse(&root)) {
+        *msg = "tuning cache is not valid JSON: " + p.err;
+        return false;
+    }
+    if (root.kind != JVal::Obj) {
+        *msg = "tuning cache must be a JSON object";
+        return false;
+    }
+    const JVal *fmt = root.get("format");
+    if (!fmt || fmt->kind != JVal::Str || fmt->str != kFormat) {
+        *msg = std::string("tuning cache format must be \"") + kFormat + "\"";
+        return false;
+    }
+    const JVal *dev = root.get("device");
+    if (!dev || dev->kind != JVal::Str) {
+        *msg = "tuning cache has no device key";
+        return false;
+    }
+    if (dev->str != device_key) {
+        *msg = "tuning cache was made on " + dev->str + ", this device is " + device_key;
+        return false;
+    }
+    const JVal *arr = root.get("entries");
+    if (!arr || arr->kind != JVal::Arr) {
+        *msg = "tuning cache has no entries array";
+        return false;
+    }
+    for (const JVal &o : arr->arr) {
+        if (o.kind != JVal::Obj) {
+            *msg = "tuning cache entry is not an object";
+            return false;
+        }
+        qplan::TuneEntry e;
+        const JVal *dt = o.get("dtype");
+        if (!dt || dt->kind != JVal::Str || (dt->str != "int32" && dt->str != "fp32")) {
+            *msg = "entry field 'dtype' must be \"int32\" or \"fp32\"";
+            return false;
+        }
+        e.dtype = dt->str == "fp32" ? QUBO_FP32 : QUBO_INT32;
+        if (!int_field(o, "n", &e.n, msg) || !int_field(o, "B", &e.B, msg) ||
+            !int_field(o, "L", &e.L, msg) || !int_field(o, "tier", &e.tier, msg) ||
+            !int_field(o, "vgpr_levels", &e.vgpr_levels, msg))
+            return false;
+        const JVal *ms = o.get("walk_ms");
+        e.walk_ms = (ms && ms->kind == JVal::Num) ? ms->num : 0.0;
+        if (!qplan::tune_valid(e, msg)) {
+            *msg = "n=" + std::to_string(e.n) + ": " + *msg;
+            return false;
+        }
+        entries->push_back(e);
+    }
+    return true;
+}
+
+std::string format_cache(const std::vector<qplan::TuneEntry> &entries, const std::string &key)
+{
+    std::ostringstream o;
+    o << "{\"format\": \"" << kFormat << "\", \"device\": \"" << key << "\", \"entries\": [";
+    for (size_t k = 0; k < entries.size(); k++) {
+        const qplan::TuneEntry &e = entries[k];
+        char buf[256];
+        std::snprintf(buf, sizeof(buf),
+                      "%s\n  {\"n\": %d, \"dtype\": \"%s\", \"B\": %d, \"L\": %d, \"tier\": %d, "
+                      "\"vgpr_levels\": %d, \"walk_ms\": %.6g}",
+                      k ? "," : "", e.n, dtype_name(e.dtype), e.B, e.L, e.tier, e.vgpr_levels,
+                      e.walk_ms);
+        o << buf;
+    }
+    o << "\n]}\n";
+    return o.str();
+}
+
+bool read_file(const char *path, std::string *out, std::string *msg)
+{
+    std::ifstream f(path, std::ios::binary);
+    if (!f) {
+        *msg = std::string("cannot open ") + path;
+        return false;
+    }
+    std::ostringstream ss;
+    ss << f.rdbuf();
+    *out = ss.str();
+    if (out->size() > (16u << 20)) {
+        *msg = "tuning cache larger than 16 MiB";
+        return false;
+    }
+    return true;
+}
+
+bool write_file(const char *path, const std::string &text, std::string *msg)
+{
+    // write a sibling temporary and rename, so readers never see half a file
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream f(tmp, std::ios::binary | std::ios::trunc);
+        if (!f) {
+            *msg = std::string("cannot write ") + tmp;
+            return false;
+        }
+        f << text;
+        if (!f) {
+            *msg = std::string("write failed: ") + tmp;
+            return false;
+        }
+    }
+    if (std::rename(tmp.c_str(), path) != 0) {
+        *msg = std::string("cannot rename to ") + path;
+        return false;
+    }
+    return true;
+}
+
+qubo_status_t current_device_key(std::string *key)
+{
+    int dev = 0;
+    QRT_HIP(hipGetDevice(&dev), "hipGetDevice");
+    hipDeviceProp_t prop;
+    QRT_HIP(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+    std::string arch(prop.gcnArchName);
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+    *key = arch + "/" + std::to_string(prop.multiProcessorCount) + "cu";
+    return QUBO_OK;
+}
+
+qubo_status_t load_into_table(const char *path, const std::string &key, int *loaded)
+{
+    std::string text, msg;
+    if (!read_file(path, &text, &msg)) {
+        qrt::set_error(msg);
+        return QUBO_EINVAL;
+    }
+    std::vector<qplan::TuneEntry> entries;
+    if (!parse_cache(text, key, &entries, &msg)) {
+        qrt::set_error(msg);
+        return QUBO_EINVAL;
+    }
+    for (const auto &e : entries) qplan::tune_put(e);
+    if (loaded) *loaded = int(entries.size());
+    return QUBO_OK;
+}
+
+// ------------------------------------------------------------ tuning runs
+
+// Synthetic tuning instance: counter-based SplitMix64 stream (seeded by n),
+// int32 entries uniform in [-100, 100] or float32 uniform in [-1, 1).  The
+// walk's cost does not depend on the values, only on n and the plan.
+uint64_t splitmix64(uint64_t x)
+{
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+std::vector<uint32_t> tuning_instance(int n, qubo_dtype_t dtype)
+{
+    std::vector<uint32_t> q(size_t(n) * size_t(n));
+    for (size_t k = 0; k < q.size(); k++) {
+        const uint64_t r = splitmix64((uint64_t(n) << 32) ^ k);
+        if (dtype == QUBO_INT32) {
+            const int32_t v = int32_t(r % 201) - 100;
+            std::memcpy(&q[k], &v, 4);
+        } else {
+            const float v = float(double(r >> 40) * 0x1.0p-23 - 1.0);
+            std::memcpy(&q[k], &v, 4);
+        }
+    }
+    return q;
+}
+
+struct Candidate {
+    qubo_options_t opt;
+    double best_ms = 1e300;
+};
+
+// Every plan this build can run for n: suffix widths, row caches, tiers and
+// work-item sizes around the default.
+qubo_status_t candidates(const void *Q, int n, qubo_dtype_t dtype, std::vector<Candidate> *out)
+{
+    static const int kCaches[] = {12, 8, 6, 5};
+    for (int B = 6; B <= 10; B++) {
+        if (n - B < qplan::kSuper) continue;
+        const int mcols = (1 << B) / qplan::kWave;
+        for (int G : kCaches) {
+            if (!qk::walk_variant_exists(mcols, G)) continue;
+            for (int tier = 1; tier <= 2; tier++) {
+                qubo_options_t o{};
+                o.B = B;
+                o.tier = tier;
+                o.vgpr_levels = G;
+                qplan::Plan P;
+                std::string msg;
+                qubo_status_t st = qplan::make_plan(Q, n, dtype, &o, &P, &msg);
+                if (st != QUBO_OK) {
+                    qrt::set_error(msg);
+                    return st;
+                }
+                for (int dL = -2; dL <= 2; dL += 2) {
+                    const int L = P.L + dL;
+                    if (L < qplan::kSuper || L > P.A || P.A - L > 20) continue;
+                    Candidate c;
+                    c.opt = o;
+                    c.opt.L = L;
+                    out->push_back(c);
+                }
+            }
+        }
+    }
+    return QUBO_OK;
+}
+
+qubo_status_t run_candidate(const void *Q, int n, qubo_dtype_t dtype, const qubo_options_t &o,
+                            hipStream_t stream, qubo_result_t *r)
+{
+    qrt::Job job;
+    job.plans.resize(1);
+    std::string msg;
+    qubo_status_t st = qplan::make_plan(Q, n, dtype, &o, &job.plans[0], &msg);
+    if (st != QUBO_OK) {
+        qrt::set_error(msg);
+        return st;
+    }
+    job.qf.push_back(dtype == QUBO_FP32 ? static_cast<const float *>(Q) : nullptr);
+    return qrt::solve_planned(job, stream, 0, r);
+}
+
+qubo_status_t tune_one(int n, qubo_dtype_t dtype, int reps, hipStream_t stream,
+                       qplan::TuneEntry *winner)
+{
+    const std::vector<uint32_t> q = tuning_instance(n, dtype);
+    std::vector<Candidate> cands;
+    qubo_status_t st = candidates(q.data(), n, dtype, &cands);
+    if (st != QUBO_OK) return st;
+    if (cands.empty()) {
+        qrt::set_error("no walk plan for n = " + std::to_string(n));
+        return QUBO_EINVAL;
+    }
+    qubo_result_t ref{}, r{};
+    // warm-up (first launches load code objects), and the reference answer
+    if ((st = run_candidate(q.data(), n, dtype, cands[0].opt, stream, &ref)) != QUBO_OK) return st;
+    auto check = [&](const qubo_result_t &x, const qubo_options_t &o) {
+        if (x.best.energy_i == ref.best.energy_i && x.best.index == ref.best.index) return true;
+        char buf[200];
+        std::snprintf(buf, sizeof(buf),
+                      "plan invariance violated at n=%d: B=%d L=%d tier=%d vgpr_levels=%d gave "
+                      "(%lld, %llu), expected (%lld, %llu)",
+                      n, o.B, o.L, o.tier, o.vgpr_levels, (long long)x.best.energy_i,
+                      (unsigned long long)x.best.index, (long long)ref.best.energy_i,
+                      (unsigned long long)ref.best.index);
+        qrt::set_error(buf);
+        return false;
+    };
+    // pass 1: every candidate once
+    for (Candidate &c : cands) {
+        if ((st = run_candidate(q.data(), n, dtype, c.opt, stream, &r)) != QUBO_OK) return st;
+        if (!check(r, c.opt)) return QUBO_EINTERNAL;
+        c.best_ms = r.kernel_ms;
+    }
+    // pass 2: the four fastest again, keeping each one's minimum
+    std::stable_sort(cands.begin(), cands.end(),
+                     [](const Candidate &a, const Candidate &b) { return a.best_ms < b.best_ms; });
+    const size_t top = std::min<size_t>(4, cands.size());
+    for (int rep = 0; rep < reps; rep++)
+        for (size_t k = 0; k < top; k++) {
+            if ((st = run_candidate(q.data(), n, dtype, cands[k].opt, stream, &r)) != QUBO_OK) return st;
+            if (!check(r, cands[k].opt)) return QUBO_EINTERNAL;
+            cands[k].best_ms = std::min(cands[k].best_ms, double(r.kernel_ms));
+        }
+    std::stable_sort(cands.begin(), cands.begin() + long(top),
+                     [](const Candidate &a, const Candidate &b) { return a.best_ms < b.best_ms; });
+    const Candidate &w = cands[0];
+    winner->n = n;
+    winner->dtype = dtype;
+    winner->B = w.opt.B;
+    winner->L = w.opt.L;
+    winner->tier = w.opt.tier;
+    winner->vgpr_levels = w.opt.vgpr_levels;
+    winner->walk_ms = w.best_ms;
+    return QUBO_OK;
+}
+
+void to_abi(const qplan::TuneEntry &e, qubo_tune_entry_t *o)
+{
+    o->n = e.n;
+    o->dtype = e.dtype;
+    o->B = e.B;
+    o->L = e.L;
+    o->tier = e.tier;
+    o->vgpr_levels = e.vgpr_levels;
+    o->walk_ms = e.walk_ms;
+}
+
+std::once_flag g_autoload_once;
+
+}  // namespace
+
+namespace qrt {
+
+void tune_autoload()
+{
+    std::call_once(g_autoload_once, [] {
+        const char *path = std::getenv("QUBO_TUNE_CACHE");
+        if (!path || !*path) return;
+        std::string key;
+        if (current_device_key(&key) != QUBO_OK) return;
+        const std::string saved = last_error_cstr();
+        int loaded = 0;
+        if (load_into_table(path, key, &loaded) != QUBO_OK)
+            std::fprintf(stderr, "qubo: ignoring QUBO_TUNE_CACHE=%s: %s\n", path, last_error_cstr());
+        set_error(saved);
+    });
+}
+
+}  // namespace qrt
+
+extern "C" {
+
+qubo_status_t qubo_device_key(char *buf, int cap)
+{
+    try {
+        qrt::set_error("");
+        if (!buf || cap < 1) {
+            qrt::set_error("null buffer");
+            return QUBO_EINVAL;
+        }
+        std::string key;
+        qubo_status_t st = current_device_key(&key);
+        if (st != QUBO_OK) return st;
+        if (int(key.size()) >= cap) {
+            qrt::set_error("buffer too small for the device key");
+            return QUBO_EINVAL;
+        }
+        std::memcpy(buf, key.c_str(), key.size() + 1);
+        return QUBO_OK;
+    } catch (...) {
+        qrt::set_error("unexpected exception");
+        return QUBO_EINTERNAL;
+    }
+}
+
+qubo_status_t qubo_tune_set(const qubo_tune_entry_t *entries, int count)
+{
+    try {
+        qrt::set_error("");
+        if (count < 0 || (count > 0 && !entries)) {
+            qrt::set_error("bad entries");
+            return QUBO_EINVAL;
+        }
+        std::vector<qplan::TuneEntry> v(static_cast<size_t>(count));
+        for (int k = 0; k < count; k++) {
+            qplan::TuneEntry &e = v[size_t(k)];
+            e.n = entries[k].n;
+            e.dtype = entries[k].dtype;
+            e.B = entries[k].B;
+            e.L = entries[k].L;
+            e.tier = entries[k].tier;
+            e.vgpr_levels = entries[k].vgpr_levels;
+            e.walk_ms = entries[k].walk_ms;
+            std::string msg;
+            if (!qplan::tune_valid(e, &msg)) {
+                qrt::set_error("entry " + std::to_string(k) + ": " + msg);
+                return QUBO_EINVAL;
+            }
+        }
+        for (const auto &e : v) qplan::tune_put(e);
+        return QUBO_OK;
+    } catch (...) {
+        qrt::set_error("unexpected exception");
+        return QUBO_EINTERNAL;
+    }
+}
+
+int qubo_tune_lookup(int n, qubo_dtype_t dtype, qubo_tune_entry_t *out)
+{
+    qplan::TuneEntry e;
+    if (!qplan::tune_get(n, dtype, &e)) return 0;
+    if (out) to_abi(e, out);
+    return 1;
+}
+
+void qubo_tune_clear(void) { qplan::tune_clear(); }
+
+qubo_status_t qubo_tune_load(const char *path, const char *device_key, int *loaded)
+{
+    try {
+        qrt::set_error("");
+        if (!path) {
+            qrt::set_error("null path");
+            return QUBO_EINVAL;
+        }
+        std::string key;
+        if (device_key) {
+            key = device_key;
+        } else {
+            qubo_status_t st = current_device_key(&key);
+            if (st != QUBO_OK) return st;
+        }
+        return load_into_table(path, key, loaded);
+    } catch (const std::bad_alloc &) {
+        qrt::set_error("host allocation failed");
+        return QUBO_ENOMEM;
+    } catch (...) {
+        qrt::set_error("unexpected exception");
+        return QUBO_EINTERNAL;
+    }
+}
+
+qubo_status_t qubo_tune_save(const char *path, const char *device_key)
+{
+    try {
+        qrt::set_error("");
+        if (!path) {
+            qrt::set_error("null path");
+            return QUBO_EINVAL;
+        }
+        std::string key;
+        if (device_key) {
+            key = device_key;
+        } else {
+            qubo_status_t st = current_device_key(&key);
+            if (st != QUBO_OK) return st;
+        }
+        if (key.find('"') != std::string::npos || key.find('\\') != std::string::npos) {
+            qrt::set_error("device key may not contain quotes or backslashes");
+            return QUBO_EINVAL;
+        }
+        std::string msg;
+        if (!write_file(path, format_cache(qplan::tune_all(), key), &msg)) {
+            qrt::set_error(msg);
+            return QUBO_EINVAL;
+        }
+        return QUBO_OK;
+    } catch (...) {
+        qrt::set_error("unexpected exception");
+        return QUBO_EINTERNAL;
+    }
+}
+
+qubo_status_t qubo_autotune(int n_min, int n_max, qubo_dtype_t dtype, int reps,
+                            const char *cache_path, qubo_tune_entry_t *out, int out_cap,
+                            int *out_count)
+{
+    try {
+        qrt::set_error("");
+        if (n_min < qplan::kDirectMaxN + 1 || n_max > 48 || n_min > n_max) {
+            qrt::set_error("autotune range must satisfy 15 <= n_min <= n_max <= 48");
+            return QUBO_EINVAL;
+        }
+        if (dtype != QUBO_INT32 && dtype != QUBO_FP32) {
+            qrt::set_error("unknown dtype");
+            return QUBO_EINVAL;
+        }
+        if (reps < 0 || reps > 100 || out_cap < 0 || (out_cap > 0 && !out)) {
+            qrt::set_error("bad reps or output buffer");
+            return QUBO_EINVAL;
+        }
+        qubo_status_t st;
+        hipStream_t stream = qrt::thread_stream(&st);
+        if (st != QUBO_OK) return st;
+        std::string key;
+        if ((st = current_device_key(&key)) != QUBO_OK) return st;
+        std::vector<qplan::TuneEntry> won;
+        for (int n = n_min; n <= n_max; n++) {
+            qplan::TuneEntry e;
+            if ((st = tune_one(n, dtype, reps, stream, &e)) != QUBO_OK) return st;
+            won.push_back(e);
+        }
+        if (cache_path) {
+            // merge with what the file already holds for this device
+            std::string text, msg;
+            if (read_file(cache_path, &text, &msg)) {
+                std::vector<qplan::TuneEntry> old;
+                if (parse_cache(text, key, &old, &msg))
+                    for (const auto &e : old) qplan::tune_put(e);
+            }
+        }
+        for (const auto &e : won) qplan::tune_put(e);
+        if (cache_path) {
+            std::string msg;
+            if (!write_file(cache_path, format_cache(qplan::tune_all(), key), &msg)) {
+                qrt::set_error(msg);
+                return QUBO_EINVAL;
+            }
+        }
+        for (int k = 0; k < out_cap && k < int(won.size()); k++) to_abi(won[size_t(k)], &out[k]);
+        if (out_count) *out_count = int(won.size());
+        return QUBO_OK;
+    } catch (const std::bad_alloc &) {
+        qrt::set_error("host allocation failed");
+        return QUBO_ENOMEM;
+    } catch (...) {
+        qrt::set_error("unexpected exception");
+        return QUBO_EINTERNAL;
+    }
+}
+
+}  // extern "C"
