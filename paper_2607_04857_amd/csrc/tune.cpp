@@ -270,7 +270,7 @@ std::string format_cache(const std::vector<qplan::TuneEntry> &entries, const std
         char buf[256];
         std::snprintf(buf, sizeof(buf),
                       "%s\n  {\"n\": %d, \"dtype\": \"%s\", \"B\": %d, \"L\": %d, \"tier\": %d, "
-                      "\"vgpr_levels\": %d, \"walk_ms\": %.6g}",
+                      "\"vgpr_levels\": %d, \"walk_ms\": %.17g}",
                       k ? "," : "", e.n, dtype_name(e.dtype), e.B, e.L, e.tier, e.vgpr_levels,
                       e.walk_ms);
         o << buf;
