@@ -60,6 +60,42 @@ struct ItemRes {
     uint64_t row;      // prefix row (U_A row) of that chunk
 };
 
+// Top-k (k > 1) state of one walk launch over a single instance.  Each
+// wave keeps, in LDS, the k smallest chunk keys (E_p + min over the chunk,
+// prefix row) it has met; a chunk can belong to the instance's k smallest
+// chunks only if its minimum is at most the largest E of any full list, so
+// waves share that bound through gthr (atomic min).
+struct TopkWalk {
+    int32_t *listE;      // [waves][k] chunk minima
+    uint64_t *listR;     // [waves][k] prefix rows of those chunks
+    int32_t *listCount;  // [waves] entries used (written by every wave on exit)
+    int32_t *gthr;       // shared bound, kNoEnergy before the walk
+    int k;
+};
+
+// One state of a top-k answer; the same layout as qubo_state_t.
+struct TopkState {
+    int64_t E;           // exact integer energy
+    double E64;          // float64 rescore (fp32) or (double)E
+    uint64_t index;      // U_N row
+};
+
+// Device buffers of the top-k finish of a single instance.
+struct TopkBufs {
+    TopkWalk walk;
+    int waves;           // lists in walk.listE (walked instances)
+    int32_t *chunkE;     // [k] the k smallest chunk keys ...
+    uint64_t *chunkR;    // [k] ... and their prefix rows
+    int32_t *chunkCount; // [1] chunks selected (min(k, chunks met))
+    int32_t *stE;        // [k << B] (or [2^n] direct) candidate state energies
+    uint64_t *stI;       // same, U_N rows
+    int32_t *segCount;   // [k] valid states per rescanned chunk ([1] direct)
+    int32_t *selE;       // [k] the k smallest states, sorted by (E, index)
+    uint64_t *selR;
+    int32_t *selCount;   // [1]
+    TopkState *out;      // [k] answer (fp32: sorted by (E64, index))
+};
+
 struct FinalRes {
     int64_t E;         // exact integer energy of the answer
     uint64_t index;    // U_N row of the answer
@@ -76,15 +112,33 @@ hipError_t launch_tables(const Inst *d_insts, int n_inst, int max_A, unsigned lo
 // the contiguous array of K tables (instance i's at insts[i].kslot*kKTable).
 // Variant: mcols columns per lane (B = 6 + log2 mcols), the M_int rows of
 // Gray levels below vgpr_levels cached in VGPRs (higher ones from L2), tier.
+// Tier 3 (top-k lists) needs `tk` and exactly one instance; tiers 1 and 2
+// ignore it (may be null).
 hipError_t launch_walk(int mcols, int vgpr_levels, int tier, const Inst *d_insts, int n_inst,
                        uint64_t total_items, unsigned long long *d_counter, const int32_t *d_k,
-                       int waves, hipStream_t stream);
+                       int waves, hipStream_t stream, const TopkWalk *tk = nullptr);
 
 // Whether a (mcols, vgpr_levels) walk variant is compiled in.
 bool walk_variant_exists(int mcols, int vgpr_levels);
 
-// Resident walk wavefronts per CU for a variant (occupancy query, >= 1).
-int walk_occupancy(int mcols, int vgpr_levels, int tier);
+// Resident walk wavefronts per CU for a variant (occupancy query, >= 1);
+// topk_k > 1 accounts for tier 3's LDS list.
+int walk_occupancy(int mcols, int vgpr_levels, int tier, int topk_k = 0);
+
+// LDS bytes of one tier-3 wave's list.
+constexpr int kTopkMetaWords = 9;   // 64-bit words of list scalars ahead of the entries
+inline size_t topk_lds_bytes(int k)
+{
+    return size_t(kTopkMetaWords) * 8 + size_t(k) * (sizeof(uint64_t) + sizeof(int32_t));
+}
+
+// Top-k finish of one instance (descriptor d_inst, host copy hI): select the
+// k smallest chunks of the walk lists, rescan them (or, direct, evaluate all
+// 2^n states), select and sort the k smallest states, verify their energies
+// and write buf.out and *d_best (status 3: an energy did not verify; 4:
+// fewer than k states).
+hipError_t launch_topk_finish(const Inst *d_inst, const Inst &hI, const TopkBufs &buf, int k,
+                              FinalRes *d_best, hipStream_t stream);
 
 // Per-instance reduction of item results (insts[i].res[0..n_items)), argmin
 // rescan (or direct evaluation for tiny n) and float64 rescoring; one

@@ -29,6 +29,7 @@
 #include <type_traits>
 #include <utility>
 
+#include "device_energy.h"
 #include "kernels.h"
 
 namespace qk {
@@ -109,33 +110,6 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v)
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
     return v;
-}
-
-// Energy of U_N row `idx` from the folded upper-triangular T (exact).
-__device__ int64_t energy_int(const int32_t *T, int n, uint64_t idx)
-{
-    int64_t E = 0;
-    for (int i = 0; i < n; i++) {
-        if (!((idx >> (n - 1 - i)) & 1)) continue;
-        int64_t rowsum = 0;
-        for (int j = i; j < n; j++)
-            if ((idx >> (n - 1 - j)) & 1) rowsum += T[i * n + j];
-        E += rowsum;
-    }
-    return E;
-}
-
-// E(x) = sum_{i,j} Q_ij x_i x_j in float64 from the caller's float32 Q,
-// summed i ascending then j ascending over the set bits.
-__device__ double energy_f64(const float *Q, int n, uint64_t idx)
-{
-    double E = 0.0;
-    for (int i = 0; i < n; i++) {
-        if (!((idx >> (n - 1 - i)) & 1)) continue;
-        for (int j = 0; j < n; j++)
-            if ((idx >> (n - 1 - j)) & 1) E += double(Q[i * n + j]);
-    }
-    return E;
 }
 
 __device__ __forceinline__ void lexmin(int64_t &bE, uint64_t &bI, int64_t e, uint64_t i)
@@ -279,14 +253,162 @@ constexpr int walk_waves_per_simd()
 // (G = 6 and 8 with MC = 16 target 3 waves, G = 5 four; 8 and 5 spill a few
 // values outside the unrolled steps.)
 
+// ---- tier-3 list (top-k).  One wave per workgroup; the list lives in
+// dynamic LDS: 9 64-bit words of scalars, then k rows and k energies.  All
+// list state stays in LDS (not SGPRs) and the list code sits in functions
+// that are not inlined: only the rare candidate path touches it, and the
+// walk's registers stay those of tier 2.
+//   M[0] entries used  M[1] slot of the largest key  M[2] its E (kNoEnergy
+//   until the list is full)  M[3] lowest shared bound seen  M[4] k
+//   P[0] the largest key's row  P[1] gthr  P[2] listE  P[3] listR
+//   P[4] listCount   (M = words 0..3 as int32, P = words 4..8)
+extern __shared__ uint64_t tk_lds[];
+
+__device__ __forceinline__ int32_t *tk_M() { return reinterpret_cast<int32_t *>(tk_lds); }
+__device__ __forceinline__ uint64_t *tk_P() { return tk_lds + 4; }
+__device__ __forceinline__ uint64_t *tk_R() { return tk_lds + kTopkMetaWords; }
+__device__ __forceinline__ int32_t *tk_E(int k) { return reinterpret_cast<int32_t *>(tk_R() + k); }
+__device__ __forceinline__ int32_t *tk_gthr()
+{
+    return reinterpret_cast<int32_t *>(sread64(tk_P()[1]));
+}
+
+__device__ __forceinline__ void tk_init(const TopkWalk &tk)
+{
+    if (threadIdx.x == 0) {
+        int32_t *M = tk_M();
+        uint64_t *P = tk_P();
+        M[0] = 0;
+        M[1] = 0;
+        M[2] = kNoEnergy;
+        M[3] = kNoEnergy;
+        M[4] = tk.k;
+        P[0] = 0;
+        P[1] = reinterpret_cast<uint64_t>(tk.gthr);
+        P[2] = reinterpret_cast<uint64_t>(tk.listE);
+        P[3] = reinterpret_cast<uint64_t>(tk.listR);
+        P[4] = reinterpret_cast<uint64_t>(tk.listCount);
+    }
+    __syncthreads();
+}
+
+// Threshold at an item start: min(largest E of the full list, shared bound).
+__device__ __noinline__ int32_t tk_threshold()
+{
+    int32_t *M = tk_M();
+    const int32_t g = sread(__hip_atomic_load(tk_gthr(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const int32_t gm = min(sread(M[3]), g);
+    const int32_t t = min(sread(M[2]), gm);
+    __syncthreads();
+    if (threadIdx.x == 0) M[3] = gm;
+    __syncthreads();
+    return t;
+}
+
+// Largest key (E, row) of the full list: store it and its slot, publish its
+// E to the shared bound; returns that E.
+__device__ int32_t tk_rescan(int k)
+{
+    __syncthreads();              // lane 0's LDS stores are visible to the wave
+    const int lane = int(threadIdx.x);
+    const int32_t *E = tk_E(k);
+    const uint64_t *R = tk_R();
+    int32_t mE = INT32_MIN;
+    uint64_t mR = 0;
+    int mP = 0;
+    for (int p = lane; p < k; p += kWave) {
+        const int32_t e = E[p];
+        const uint64_t r = R[p];
+        if (e > mE || (e == mE && r > mR)) {
+            mE = e;
+            mR = r;
+            mP = p;
+        }
+    }
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) {
+        const int32_t oE = __shfl_xor(mE, off, kWave);
+        const uint64_t oR = __shfl_xor(mR, off, kWave);
+        const int oP = __shfl_xor(mP, off, kWave);
+        if (oE > mE || (oE == mE && oR > mR)) {
+            mE = oE;
+            mR = oR;
+            mP = oP;
+        }
+    }
+    mE = sread(mE);
+    if (lane == 0) {
+        int32_t *M = tk_M();
+        M[1] = mP;
+        M[2] = mE;
+        M[3] = min(M[3], mE);
+        tk_P()[0] = mR;
+        atomicMin(tk_gthr(), mE);
+    }
+    return mE;
+}
+
+// Offer chunk key (Ec, rc), Ec <= the current threshold: append while the
+// list has room, else replace the largest key if (Ec, rc) is smaller.
+// Returns the new threshold.
+__device__ __noinline__ int32_t tk_insert(int32_t Ec, uint64_t rc)
+{
+    Ec = sread(Ec);
+    rc = sread64(rc);
+    int32_t *M = tk_M();
+    __syncthreads();
+    const int cnt = sread(M[0]);
+    const int k = sread(M[4]);
+    int32_t lkth = sread(M[2]);
+    if (cnt < k) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            tk_E(k)[cnt] = Ec;
+            tk_R()[cnt] = rc;
+            M[0] = cnt + 1;
+        }
+        if (cnt + 1 == k) lkth = tk_rescan(k);
+    } else {
+        const uint64_t lkR = sread64(tk_P()[0]);
+        if (Ec < lkth || (Ec == lkth && rc < lkR)) {
+            const int pos = sread(M[1]);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                tk_E(k)[pos] = Ec;
+                tk_R()[pos] = rc;
+            }
+            lkth = tk_rescan(k);
+        }
+    }
+    __syncthreads();
+    return min(lkth, sread(M[3]));
+}
+
+// Copy the wave's list to listE/listR at slot blockIdx.x * k.
+__device__ __noinline__ void tk_flush()
+{
+    __syncthreads();
+    const int32_t *M = tk_M();
+    const uint64_t *P = tk_P();
+    const int cnt = sread(M[0]);
+    const int k = sread(M[4]);
+    int32_t *gE = reinterpret_cast<int32_t *>(sread64(P[2])) + size_t(blockIdx.x) * size_t(k);
+    uint64_t *gR = reinterpret_cast<uint64_t *>(sread64(P[3])) + size_t(blockIdx.x) * size_t(k);
+    for (int p = int(threadIdx.x); p < cnt; p += kWave) {
+        gE[p] = tk_E(k)[p];
+        gR[p] = tk_R()[p];
+    }
+    if (threadIdx.x == 0) reinterpret_cast<int32_t *>(sread64(P[4]))[blockIdx.x] = cnt;
+}
+
+// TIER 3: tier 2's bound test against a top-k threshold instead of the best
+//         energy: the wave keeps the k smallest chunk keys it has met in LDS.
 template <int MC, int G, int TIER>
 __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_kernel(
-    const Inst *__restrict__ insts, int n_inst,
-                                                     uint64_t total_items,
-                                                     unsigned long long *__restrict__ counter,
-                                                     const int32_t *__restrict__ kall)
+    const Inst *__restrict__ insts, int n_inst, uint64_t total_items,
+    unsigned long long *__restrict__ counter, const int32_t *__restrict__ kall, TopkWalk tk)
 {
-    static_assert(TIER == 1 || TIER == 2, "tier");
+    static_assert(TIER >= 1 && TIER <= 3, "tier");
     static_assert(G >= kSuperLog && G <= kMaxVgprLevels, "VGPR-resident levels");
     constexpr int H16 = kPatterns;   // steps per half super-block
     const int lane = int(threadIdx.x);
@@ -302,8 +424,10 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
     int32_t S4L[kLowLevels];  // couplings of the level-4 variable with the low ones
     int32_t diagl = 0;       // T[l][l] on lane l < A
     int32_t CR[kPatterns];   // low-low coupling increments per pattern
-    int32_t best = kNoEnergy;
+    int32_t best = kNoEnergy;     // tier 3: the current top-k threshold
     uint64_t bestRow = ~0ull;
+
+    if constexpr (TIER == 3) tk_init(tk);
 
     for (;;) {
         uint64_t g = 0;
@@ -400,6 +524,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
             constexpr int t = decltype(tc)::value;
             H[t] = __builtin_amdgcn_readlane(F, A - 1 - t);
         });
+        if constexpr (TIER == 3) best = tk_threshold();
 
         // TIER 1: THR[p] = best - E_p(low pattern p): the chunk holds a
         // candidate when its minimum E_sd is <= THR of the current pattern.
@@ -485,6 +610,21 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
                         if constexpr (TIER == 1) THR[p] += d;
                         else TP[p] += d;
                     });
+                }
+            }
+        };
+
+        // TIER 3 candidate: the chunk key (E_p + chunk minimum, row) enters
+        // the wave's list if the list has room or the key beats its largest;
+        // the threshold is then min(largest key's E when full, shared bound).
+        auto candidate3 = [&](int32_t lm, int32_t thr, uint64_t i) {
+            if (__builtin_amdgcn_ballot_w64(lm <= thr)) {
+                const int32_t Ec = wave_min(lm) + (best - thr);
+                if (Ec <= best) {
+                    const int32_t nb = sread(tk_insert(Ec, i ^ (i >> 1)));
+                    const int32_t d = nb - best;
+                    best = nb;
+                    static_for<0, kPatterns>([&](auto pc) { TP[decltype(pc)::value] += d; });
                 }
             }
         };
@@ -580,7 +720,10 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
                         constexpr int o = h * H16 + o2;
                         if (__builtin_expect(W0 <= TP[o2], 0)) {
                             const int32_t thr = TP[o2] + kall[kbase + (3 + tab2) * kPatterns + o2];
-                            candidate(tree_min<MC>(E), thr, (sb << kSuperLog) | uint64_t(o));
+                            if constexpr (TIER == 3)
+                                candidate3(tree_min<MC>(E), thr, (sb << kSuperLog) | uint64_t(o));
+                            else
+                                candidate(tree_min<MC>(E), thr, (sb << kSuperLog) | uint64_t(o));
                         }
                         if constexpr (o2 < H16 - 1) {
                             constexpr int t = cx_ctz(o + 1);
@@ -601,7 +744,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
             }
         }
 
-        if (lane == 0) {
+        if (TIER != 3 && lane == 0) {
             ItemRes r;
             r.E = found ? itemE : kNoEnergy;
             r.found = found;
@@ -609,6 +752,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
             ires[qloc] = r;
         }
     }
+    if constexpr (TIER == 3) tk_flush();
 }
 
 // ---------------------------------------------------------------- finish
@@ -701,26 +845,38 @@ hipError_t launch_tables(const Inst *d_insts, int n_inst, int max_A, unsigned lo
 template <int MC, int G>
 static hipError_t launch_walk_g(int tier, const Inst *d_insts, int n_inst, uint64_t total_items,
                                 unsigned long long *d_counter, const int32_t *d_k, int waves,
-                                hipStream_t stream)
+                                hipStream_t stream, const TopkWalk *tk)
 {
-    if (tier == 1)
+    TopkWalk none{};
+    if (tier == 1) {
         hipLaunchKernelGGL((walk_kernel<MC, G, 1>), dim3(waves), dim3(kWave), 0, stream, d_insts,
-                           n_inst, total_items, d_counter, d_k);
-    else if (tier == 2)
+                           n_inst, total_items, d_counter, d_k, none);
+    } else if (tier == 2) {
         hipLaunchKernelGGL((walk_kernel<MC, G, 2>), dim3(waves), dim3(kWave), 0, stream, d_insts,
-                           n_inst, total_items, d_counter, d_k);
-    else
+                           n_inst, total_items, d_counter, d_k, none);
+    } else if (tier == 3) {
+        if (!tk || tk->k < 2 || n_inst != 1) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((walk_kernel<MC, G, 3>), dim3(waves), dim3(kWave),
+                           topk_lds_bytes(tk->k), stream, d_insts, n_inst, total_items, d_counter,
+                           d_k, *tk);
+    } else {
         return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 template <int MC, int G>
-static int occupancy_g(int tier)
+static int occupancy_g(int tier, int topk_k)
 {
     int blocks = 0;
-    hipError_t e =
-        tier == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, G, 2>, kWave, 0)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, G, 1>, kWave, 0);
+    hipError_t e;
+    if (tier == 3)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, G, 3>, kWave,
+                                                         topk_lds_bytes(topk_k));
+    else if (tier == 2)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, G, 2>, kWave, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, G, 1>, kWave, 0);
     if (e != hipSuccess || blocks < 1) return 1;
     return blocks;
 }
@@ -735,25 +891,26 @@ bool walk_variant_exists(int mcols, int vgpr_levels)
     return false;
 }
 
-int walk_occupancy(int mcols, int vgpr_levels, int tier)
+int walk_occupancy(int mcols, int vgpr_levels, int tier, int topk_k)
 {
-    if (vgpr_levels == 5) return occupancy_g<16, 5>(tier);
-    if (vgpr_levels == 6) return occupancy_g<16, 6>(tier);
-    if (vgpr_levels == 8) return mcols == 8 ? occupancy_g<8, 8>(tier) : occupancy_g<16, 8>(tier);
+    if (vgpr_levels == 5) return occupancy_g<16, 5>(tier, topk_k);
+    if (vgpr_levels == 6) return occupancy_g<16, 6>(tier, topk_k);
+    if (vgpr_levels == 8)
+        return mcols == 8 ? occupancy_g<8, 8>(tier, topk_k) : occupancy_g<16, 8>(tier, topk_k);
     switch (mcols) {
-    case 1: return occupancy_g<1, 12>(tier);
-    case 2: return occupancy_g<2, 12>(tier);
-    case 4: return occupancy_g<4, 12>(tier);
-    case 8: return occupancy_g<8, 12>(tier);
-    default: return occupancy_g<16, 12>(tier);
+    case 1: return occupancy_g<1, 12>(tier, topk_k);
+    case 2: return occupancy_g<2, 12>(tier, topk_k);
+    case 4: return occupancy_g<4, 12>(tier, topk_k);
+    case 8: return occupancy_g<8, 12>(tier, topk_k);
+    default: return occupancy_g<16, 12>(tier, topk_k);
     }
 }
 
 hipError_t launch_walk(int mcols, int vgpr_levels, int tier, const Inst *d_insts, int n_inst,
                        uint64_t total_items, unsigned long long *d_counter, const int32_t *d_k,
-                       int waves, hipStream_t stream)
+                       int waves, hipStream_t stream, const TopkWalk *tk)
 {
-#define QK_ARGS tier, d_insts, n_inst, total_items, d_counter, d_k, waves, stream
+#define QK_ARGS tier, d_insts, n_inst, total_items, d_counter, d_k, waves, stream, tk
     if (vgpr_levels == 6 || vgpr_levels == 5) {
         if (mcols != 16) return hipErrorInvalidValue;
         return vgpr_levels == 6 ? launch_walk_g<16, 6>(QK_ARGS) : launch_walk_g<16, 5>(QK_ARGS);

@@ -17,6 +17,9 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct JobOffsets {
     size_t insts = 0, counter = 0, res = 0, out = 0, K = 0;
     std::vector<size_t> T, Qf, M, EB, S;
+    // top-k (k > 1, one instance)
+    size_t gthr = 0, listE = 0, listR = 0, listCount = 0, chunkE = 0, chunkR = 0, chunkCount = 0,
+           stE = 0, stI = 0, segCount = 0, selE = 0, selR = 0, selCount = 0, topk = 0;
 };
 
 }  // namespace
@@ -74,6 +77,11 @@ static JobOffsets compute_offsets(const Job &job, size_t *stage_bytes, size_t *b
             o.Qf.push_back(size_t(-1));
         }
     }
+    const size_t k = size_t(job.topk);
+    if (k > 1) {   // the shared top-k bound starts in the uploaded image
+        o.gthr = off;
+        off = align_up(off + sizeof(int32_t), 256);
+    }
     *stage_bytes = off;
     o.counter = off;
     off = align_up(off + std::max<size_t>(1, job.groups.size()) * sizeof(unsigned long long), 256);
@@ -93,6 +101,28 @@ static JobOffsets compute_offsets(const Job &job, size_t *stage_bytes, size_t *b
     off = align_up(off + size_t(job.total_items) * sizeof(qk::ItemRes), 256);
     o.out = off;
     off = align_up(off + ni * sizeof(qk::FinalRes), 256);
+    if (k > 1) {
+        const qplan::Plan &P = job.plans[0];
+        const size_t W = job.groups.empty() ? 0 : size_t(job.groups[0].waves);
+        const size_t nst = P.direct ? (size_t(1) << P.n) : (k << P.B);
+        auto put = [&](size_t *field, size_t bytes_) {
+            *field = off;
+            off = align_up(off + std::max<size_t>(bytes_, 1), 256);
+        };
+        put(&o.listE, W * k * sizeof(int32_t));
+        put(&o.listR, W * k * sizeof(uint64_t));
+        put(&o.listCount, W * sizeof(int32_t));
+        put(&o.chunkE, k * sizeof(int32_t));
+        put(&o.chunkR, k * sizeof(uint64_t));
+        put(&o.chunkCount, sizeof(int32_t));
+        put(&o.stE, nst * sizeof(int32_t));
+        put(&o.stI, nst * sizeof(uint64_t));
+        put(&o.segCount, k * sizeof(int32_t));
+        put(&o.selE, k * sizeof(int32_t));
+        put(&o.selR, k * sizeof(uint64_t));
+        put(&o.selCount, sizeof(int32_t));
+        put(&o.topk, k * sizeof(qk::TopkState));
+    }
     *bytes = off;
     return o;
 }
@@ -134,8 +164,13 @@ qubo_status_t job_layout(Job *job, int waves_per_cu)
         if (P.A > job->max_A) job->max_A = P.A;
         job->total_items += P.items;
     }
+    if (job->topk > 1 && (job->plans.size() != 1 || (!job->groups.empty() && job->groups[0].tier != 3))) {
+        set_error("internal: top-k jobs hold one instance planned for tier 3");
+        return QUBO_EINTERNAL;
+    }
     for (WalkGroup &g : job->groups) {
-        int wpc = waves_per_cu > 0 ? waves_per_cu : qk::walk_occupancy(g.mcols, g.vgpr_levels, g.tier);
+        int wpc = waves_per_cu > 0 ? waves_per_cu
+                                   : qk::walk_occupancy(g.mcols, g.vgpr_levels, g.tier, job->topk);
         if (wpc <= 0) wpc = 1;
         uint64_t waves = uint64_t(di.cus) * uint64_t(wpc);
         if (g.items < waves) waves = g.items;
@@ -198,6 +233,28 @@ qubo_status_t job_bind(Job *job, void *d_mem)
         if (job->qf[i]) std::memcpy(job->stage.data() + o.Qf[i], job->qf[i], nn * sizeof(float));
     }
     std::memcpy(job->stage.data() + o.insts, insts.data(), insts.size() * sizeof(qk::Inst));
+    if (job->topk > 1) {
+        const int32_t none = qk::kNoEnergy;
+        std::memcpy(job->stage.data() + o.gthr, &none, sizeof(none));
+        qk::TopkBufs &t = job->tkb;
+        t.walk.listE = reinterpret_cast<int32_t *>(base + o.listE);
+        t.walk.listR = reinterpret_cast<uint64_t *>(base + o.listR);
+        t.walk.listCount = reinterpret_cast<int32_t *>(base + o.listCount);
+        t.walk.gthr = reinterpret_cast<int32_t *>(base + o.gthr);
+        t.walk.k = job->topk;
+        t.waves = job->groups.empty() ? 0 : job->groups[0].waves;
+        t.chunkE = reinterpret_cast<int32_t *>(base + o.chunkE);
+        t.chunkR = reinterpret_cast<uint64_t *>(base + o.chunkR);
+        t.chunkCount = reinterpret_cast<int32_t *>(base + o.chunkCount);
+        t.stE = reinterpret_cast<int32_t *>(base + o.stE);
+        t.stI = reinterpret_cast<uint64_t *>(base + o.stI);
+        t.segCount = reinterpret_cast<int32_t *>(base + o.segCount);
+        t.selE = reinterpret_cast<int32_t *>(base + o.selE);
+        t.selR = reinterpret_cast<uint64_t *>(base + o.selR);
+        t.selCount = reinterpret_cast<int32_t *>(base + o.selCount);
+        t.out = reinterpret_cast<qk::TopkState *>(base + o.topk);
+        job->h_inst0 = insts[0];
+    }
     return QUBO_OK;
 }
 
@@ -212,11 +269,16 @@ qubo_status_t job_enqueue_kernels(const Job &job, hipStream_t stream, hipEvent_t
     for (size_t k = 0; k < job.groups.size(); k++) {
         const WalkGroup &g = job.groups[k];
         QRT_HIP(qk::launch_walk(g.mcols, g.vgpr_levels, g.tier, job.d_insts + g.first, g.count,
-                                g.items, job.d_counter + k, job.d_k, g.waves, stream),
+                                g.items, job.d_counter + k, job.d_k, g.waves, stream,
+                                job.topk > 1 ? &job.tkb.walk : nullptr),
                 "walk kernel");
     }
     if (walk_end) QRT_HIP(hipEventRecord(walk_end, stream), "hipEventRecord");
-    QRT_HIP(qk::launch_finish(job.d_insts, ni, job.d_out, stream), "finish kernel");
+    if (job.topk > 1)
+        QRT_HIP(qk::launch_topk_finish(job.d_insts, job.h_inst0, job.tkb, job.topk, job.d_out, stream),
+                "top-k kernels");
+    else
+        QRT_HIP(qk::launch_finish(job.d_insts, ni, job.d_out, stream), "finish kernel");
     return QUBO_OK;
 }
 
@@ -270,7 +332,8 @@ hipStream_t thread_stream(qubo_status_t *st)
     return s;
 }
 
-qubo_status_t solve_planned(qrt::Job &job, hipStream_t stream, int waves_per_cu, qubo_result_t *out)
+qubo_status_t solve_planned(qrt::Job &job, hipStream_t stream, int waves_per_cu, qubo_result_t *out,
+                            qubo_state_t *topk)
 {
     using clock = std::chrono::steady_clock;
     const auto t0 = clock::now();
@@ -281,6 +344,7 @@ qubo_status_t solve_planned(qrt::Job &job, hipStream_t stream, int waves_per_cu,
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     qubo_status_t rs = QUBO_OK;
     qk::FinalRes fr{};
+    std::vector<qk::TopkState> tk_host;
     do {
         if ((rs = qrt::job_bind(&job, d_mem)) != QUBO_OK) break;
         hipError_t e;
@@ -299,6 +363,15 @@ qubo_status_t solve_planned(qrt::Job &job, hipStream_t stream, int waves_per_cu,
             rs = qrt::device_error("hipMemcpyAsync D2H", e);
             break;
         }
+        if (job.topk > 1) {
+            static_assert(sizeof(qk::TopkState) == sizeof(qubo_state_t), "top-k state layout");
+            tk_host.resize(size_t(job.topk));
+            if ((e = hipMemcpyAsync(tk_host.data(), job.tkb.out, tk_host.size() * sizeof(qk::TopkState),
+                                    hipMemcpyDeviceToHost, stream)) != hipSuccess) {
+                rs = qrt::device_error("hipMemcpyAsync D2H top-k", e);
+                break;
+            }
+        }
     } while (false);
     hipError_t ef = hipFreeAsync(d_mem, stream);
     hipError_t es = hipStreamSynchronize(stream);
@@ -311,6 +384,14 @@ qubo_status_t solve_planned(qrt::Job &job, hipStream_t stream, int waves_per_cu,
     if (ef != hipSuccess) return qrt::device_error("hipFreeAsync", ef);
     st = qrt::job_result(job, 0, fr, out);
     if (st != QUBO_OK) return st;
+    if (job.topk > 1 && topk) {
+        const bool fp = job.plans[0].dtype == QUBO_FP32;
+        for (int i = 0; i < job.topk; i++) {
+            topk[i].energy_i = tk_host[size_t(i)].E;
+            topk[i].index = tk_host[size_t(i)].index;
+            topk[i].energy = fp ? tk_host[size_t(i)].E64 : double(tk_host[size_t(i)].E);
+        }
+    }
     out->kernel_ms = ms;
     out->total_ms = std::chrono::duration<double, std::milli>(clock::now() - t0).count();
     return QUBO_OK;
@@ -334,12 +415,10 @@ qubo_status_t check_k(int k, int n, qubo_state_t *topk)
             qrt::set_error("topk output required for k > 1");
             return QUBO_EINVAL;
         }
-        if (n < 11 && (1 << n) < k) {
+        if (n >= 1 && n < 11 && (1 << n) < k) {
             qrt::set_error("k exceeds the number of states");
             return QUBO_EINVAL;
         }
-        qrt::set_error("k > 1 is not supported by this build");
-        return QUBO_EINVAL;
     }
     return QUBO_OK;
 }
@@ -363,7 +442,12 @@ qubo_status_t solve_host(const void *Q, int n, qubo_dtype_t dtype, int k, const 
         return st;
     }
     job.qf.push_back(dtype == QUBO_FP32 ? static_cast<const float *>(Q) : nullptr);
-    st = solve_planned(job, stream, opt ? opt->waves_per_cu : 0, out);
+    if (k > 1) {
+        // the top-k walk keeps candidate lists (tier 3); the finish selects
+        job.topk = k;
+        if (!job.plans[0].direct) job.plans[0].tier = 3;
+    }
+    st = solve_planned(job, stream, opt ? opt->waves_per_cu : 0, out, topk);
     if (st == QUBO_OK && k == 1 && topk) topk[0] = out->best;
     return st;
 }
@@ -377,7 +461,8 @@ qubo_status_t qubo_solve_ex(const void *Q, int n, qubo_dtype_t dtype, int k,
 {
     try {
         qrt::set_error("");
-        qubo_status_t st;
+        qubo_status_t st = check_k(k, n, topk);
+        if (st != QUBO_OK) return st;
         hipStream_t s = thread_stream(&st);
         if (st != QUBO_OK) return st;
         return solve_host(Q, n, dtype, k, opt, s, out, topk);
@@ -405,6 +490,8 @@ qubo_status_t qubo_solve_device(const void *dQ, int n, qubo_dtype_t dtype, int k
             qrt::set_error("bad device Q or n");
             return QUBO_EINVAL;
         }
+        qubo_status_t st = check_k(k, n, topk);
+        if (st != QUBO_OK) return st;
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
         // The planner's fold and exactness proof run on the host over the
         // n x n input (at most 14.4 KB), so fetch it first.

@@ -59,6 +59,11 @@ struct Job {
     qk::ItemRes *d_res = nullptr;
     qk::FinalRes *d_out = nullptr;
     int32_t *d_k = nullptr;              // all K tables, instance i at i * kKTable
+
+    // top-k (k > 1): one instance, walked at tier 3
+    int topk = 0;
+    qk::TopkBufs tkb{};
+    qk::Inst h_inst0{};                  // host copy of the descriptor
 };
 
 // Lay out plans (already made) into a Job; `waves_per_cu` 0 = occupancy.
@@ -85,7 +90,8 @@ hipStream_t thread_stream(qubo_status_t *st);
 
 // Lay out, upload, run and read back a one-instance job on `stream`
 // (synchronous); fills kernel_ms (walk events) and total_ms.
-qubo_status_t solve_planned(Job &job, hipStream_t stream, int waves_per_cu, qubo_result_t *out);
+qubo_status_t solve_planned(Job &job, hipStream_t stream, int waves_per_cu, qubo_result_t *out,
+                            qubo_state_t *topk = nullptr);
 
 // Load the tuning cache named by the QUBO_TUNE_CACHE environment variable,
 // once per process (a no-op when unset; a cache made on another device is

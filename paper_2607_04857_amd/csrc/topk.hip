@@ -1,0 +1,364 @@
+// topk.hip -- the k lowest-energy states of one instance (k > 1).
+//
+// The paper's kernel returns the minimum; it names the k lowest energies as
+// an extension (Sec. VI).  Here the answer is the k smallest (E, index)
+// pairs, index = U_N row.  Let a chunk be the 2^B states of one prefix row
+// and its key (E_p + min over the chunk, row).  The k smallest states lie in
+// the k smallest chunks by key: if a chunk c holding one of them were not
+// among those, k chunks with smaller keys would each hold a state smaller
+// than it.  So:
+//   1. the tier-3 walk leaves per-wave lists of candidate chunk keys that
+//      together contain the k smallest chunks (kernels.hip);
+//   2. select the k smallest chunk keys of the lists;
+//   3. rescan those chunks: every state's energy from the tables,
+//      E = E_p(row) + E_s(s) + x_p M_int[:, s] (Sec. II-C);
+//   4. select the k smallest (E, index) among them, sorted;
+//   5. verify each energy from T, rescore fp32 instances in float64 and sort
+//      those by (E64, index).
+// Selection is an exact radix select on the energy (order-preserving
+// unsigned key) and, where the k-th energy is tied, on the row/index among
+// the tied entries; keys are unique (a row is walked once, an index occurs
+// once), so exactly min(k, candidates) entries are kept.
+#include "device_energy.h"
+#include "kernels.h"
+
+namespace qk {
+
+namespace {
+
+constexpr int kSelThreads = 1024;   // also the largest k
+
+struct SelArgs {
+    const int32_t *E;
+    const uint64_t *R;
+    const int32_t *segCount;   // valid entries at the head of each segment
+    uint32_t nseg, stride;     // segment s = entries [s*stride, s*stride + segCount[s])
+    int k;
+    int32_t *oE;               // [k] output, sorted by (E, R)
+    uint64_t *oR;
+    int32_t *oCount;
+};
+
+__device__ __forceinline__ uint32_t ukey(int32_t e) { return uint32_t(e) ^ 0x80000000u; }
+
+__device__ __forceinline__ bool key_less(int32_t ea, uint64_t ra, int32_t eb, uint64_t rb)
+{
+    return ea < eb || (ea == eb && ra < rb);
+}
+
+// Visit every valid entry: f(E, R).
+template <typename F>
+__device__ __forceinline__ void for_valid(const SelArgs &a, F &&f)
+{
+    const uint32_t N = a.nseg * a.stride;
+    for (uint32_t x = threadIdx.x; x < N; x += kSelThreads) {
+        const uint32_t seg = x / a.stride;
+        if (int32_t(x - seg * a.stride) < a.segCount[seg]) f(a.E[x], a.R[x]);
+    }
+}
+
+// Bin of the histogram where the running count reaches `need`.
+__device__ void pick_bin(const uint32_t *hist, uint32_t need, uint32_t *bin, uint32_t *rest,
+                         uint32_t *inbin)
+{
+    uint32_t cum = 0;
+    for (uint32_t b = 0; b < 256; b++) {
+        if (cum + hist[b] >= need) {
+            *bin = b;
+            *rest = need - cum;
+            *inbin = hist[b];
+            return;
+        }
+        cum += hist[b];
+    }
+    *bin = 255;      // unreachable when need <= total
+    *rest = 0;
+    *inbin = 0;
+}
+
+__global__ __launch_bounds__(kSelThreads) void topk_select_kernel(SelArgs a)
+{
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t sh_total, sh_pos, sh_bin, sh_rest, sh_in;
+    __shared__ int32_t sE[kSelThreads];
+    __shared__ uint64_t sR[kSelThreads];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t k = uint32_t(a.k);
+
+    if (tid == 0) {
+        uint32_t t = 0;
+        for (uint32_t s = 0; s < a.nseg; s++) t += uint32_t(a.segCount[s]);
+        sh_total = t;
+        sh_pos = 0;
+    }
+    __syncthreads();
+    const uint32_t total = sh_total;
+
+    bool take_all = total <= k;
+    uint32_t uk = 0xFFFFFFFFu;      // energy key of the k-th entry
+    bool all_eq = true;             // take every entry whose key equals uk
+    uint64_t rk = ~0ull;            // else those with R <= rk
+    if (!take_all) {
+        uint32_t prefix = 0, mask = 0, need = k;
+        for (int shift = 24; shift >= 0; shift -= 8) {
+            for (uint32_t b = tid; b < 256; b += kSelThreads) hist[b] = 0;
+            __syncthreads();
+            for_valid(a, [&](int32_t e, uint64_t) {
+                const uint32_t u = ukey(e);
+                if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 255u], 1u);
+            });
+            __syncthreads();
+            if (tid == 0) pick_bin(hist, need, &sh_bin, &sh_rest, &sh_in);
+            __syncthreads();
+            prefix |= sh_bin << shift;
+            mask |= 255u << shift;
+            need = sh_rest;
+            __syncthreads();
+        }
+        uk = prefix;
+        all_eq = need == sh_in;     // every entry with energy key uk is kept
+        if (!all_eq) {
+            uint64_t rprefix = 0, rmask = 0;
+            for (int shift = 56; shift >= 0; shift -= 8) {
+                for (uint32_t b = tid; b < 256; b += kSelThreads) hist[b] = 0;
+                __syncthreads();
+                for_valid(a, [&](int32_t e, uint64_t r) {
+                    if (ukey(e) == uk && (r & rmask) == rprefix)
+                        atomicAdd(&hist[uint32_t(r >> shift) & 255u], 1u);
+                });
+                __syncthreads();
+                if (tid == 0) pick_bin(hist, need, &sh_bin, &sh_rest, &sh_in);
+                __syncthreads();
+                rprefix |= uint64_t(sh_bin) << shift;
+                rmask |= uint64_t(255) << shift;
+                need = sh_rest;
+                __syncthreads();
+            }
+            rk = rprefix;
+        }
+    }
+    // compaction into LDS (at most k entries)
+    for_valid(a, [&](int32_t e, uint64_t r) {
+        const uint32_t u = ukey(e);
+        if (take_all || u < uk || (u == uk && (all_eq || r <= rk))) {
+            const uint32_t p = atomicAdd(&sh_pos, 1u);
+            if (p < k) {
+                sE[p] = e;
+                sR[p] = r;
+            }
+        }
+    });
+    __syncthreads();
+    const uint32_t cnt = min(sh_pos, k);
+    // bitonic sort of the kept entries by (E, R), padded to a power of two
+    uint32_t P = 1;
+    while (P < cnt) P <<= 1;
+    if (tid >= cnt && tid < P) {
+        sE[tid] = INT32_MAX;
+        sR[tid] = ~0ull;
+    }
+    __syncthreads();
+    for (uint32_t size = 2; size <= P; size <<= 1) {
+        for (uint32_t st = size >> 1; st > 0; st >>= 1) {
+            const uint32_t j = tid ^ st;
+            if (tid < P && j > tid) {
+                const bool asc = (tid & size) == 0;
+                const bool jl = key_less(sE[j], sR[j], sE[tid], sR[tid]);
+                if (jl == asc) {
+                    const int32_t te = sE[tid];
+                    const uint64_t tr = sR[tid];
+                    sE[tid] = sE[j];
+                    sR[tid] = sR[j];
+                    sE[j] = te;
+                    sR[j] = tr;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (tid < cnt) {
+        a.oE[tid] = sE[tid];
+        a.oR[tid] = sR[tid];
+    }
+    if (tid == 0) *a.oCount = int32_t(cnt);
+}
+
+// Step 3: block b rescans chunk rows[b] (if b < *rowCount).
+__global__ __launch_bounds__(256) void topk_rescan_kernel(const Inst *__restrict__ inst,
+                                                          const uint64_t *__restrict__ rows,
+                                                          const int32_t *__restrict__ rowCount,
+                                                          int32_t *__restrict__ stE,
+                                                          uint64_t *__restrict__ stI,
+                                                          int32_t *__restrict__ segCount)
+{
+    __shared__ int64_t red[256];
+    const Inst I = *inst;
+    const int n = I.n, A = I.A, B = I.B;
+    const uint32_t NS = 1u << B;
+    const uint32_t b = blockIdx.x;
+    if (int32_t(b) >= *rowCount) {
+        if (threadIdx.x == 0) segCount[b] = 0;
+        return;
+    }
+    const uint64_t row = rows[b];
+    // E_p(row) = sum over set prefix bits i <= j of T[i][j]; prefix variable
+    // v is bit A-1-v of the U_A row.
+    int64_t part = 0;
+    for (int i = int(threadIdx.x); i < A; i += int(blockDim.x)) {
+        if (!((row >> (A - 1 - i)) & 1)) continue;
+        for (int j = i; j < A; j++)
+            if ((row >> (A - 1 - j)) & 1) part += I.T[i * n + j];
+    }
+    red[threadIdx.x] = part;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (int(threadIdx.x) < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    const int32_t Ep = int32_t(red[0]);
+    for (uint32_t s = threadIdx.x; s < NS; s += blockDim.x) {
+        int32_t e = Ep + I.EB[s];
+        for (int v = 0; v < A; v++)
+            if ((row >> (A - 1 - v)) & 1) e += I.M[uint32_t(v) * NS + s];
+        stE[size_t(b) * NS + s] = e;
+        stI[size_t(b) * NS + s] = (row << B) | s;
+    }
+    if (threadIdx.x == 0) segCount[b] = int32_t(NS);
+}
+
+// Step 3 for direct instances: every state.
+__global__ __launch_bounds__(256) void topk_direct_kernel(const Inst *__restrict__ inst,
+                                                          int32_t *__restrict__ stE,
+                                                          uint64_t *__restrict__ stI,
+                                                          int32_t *__restrict__ segCount)
+{
+    const Inst I = *inst;
+    const uint32_t N = 1u << I.n;
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < N; r += gridDim.x * blockDim.x) {
+        stE[r] = int32_t(energy_int(I.T, I.n, r));
+        stI[r] = r;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) segCount[0] = int32_t(N);
+}
+
+// Step 5: verify, rescore, order; one block of k (<= 1024) threads.
+__global__ __launch_bounds__(kSelThreads) void topk_final_kernel(
+    const Inst *__restrict__ inst, const int32_t *__restrict__ selE,
+    const uint64_t *__restrict__ selR, const int32_t *__restrict__ selCount, int k,
+    TopkState *__restrict__ out, FinalRes *__restrict__ best)
+{
+    __shared__ double sF[kSelThreads];
+    __shared__ uint64_t sI[kSelThreads];
+    __shared__ int64_t sE[kSelThreads];
+    __shared__ int32_t sh_bad;
+    const Inst I = *inst;
+    const uint32_t tid = threadIdx.x;
+    const int cnt = *selCount;
+    if (tid == 0) sh_bad = 0;
+    __syncthreads();
+    if (int(tid) < cnt) {
+        const uint64_t idx = selR[tid];
+        const int64_t e = selE[tid];
+        if (energy_int(I.T, I.n, idx) != e) atomicOr(&sh_bad, 1);
+        sE[tid] = e;
+        sI[tid] = idx;
+        sF[tid] = I.Qf ? energy_f64(I.Qf, I.n, idx) : double(e);
+    }
+    __syncthreads();
+    if (I.Qf) {
+        // the integer order is exact for the scaled energies; report the
+        // float64 energies in their own (E64, index) order
+        uint32_t P = 1;
+        while (P < uint32_t(cnt)) P <<= 1;
+        if (int(tid) >= cnt && tid < P) {
+            sF[tid] = __builtin_huge_val();
+            sI[tid] = ~0ull;
+            sE[tid] = 0;
+        }
+        __syncthreads();
+        for (uint32_t size = 2; size <= P; size <<= 1) {
+            for (uint32_t st = size >> 1; st > 0; st >>= 1) {
+                const uint32_t j = tid ^ st;
+                if (tid < P && j > tid) {
+                    const bool asc = (tid & size) == 0;
+                    const bool jl = sF[j] < sF[tid] || (sF[j] == sF[tid] && sI[j] < sI[tid]);
+                    if (jl == asc) {
+                        const double tf = sF[tid];
+                        const uint64_t ti = sI[tid];
+                        const int64_t te = sE[tid];
+                        sF[tid] = sF[j];
+                        sI[tid] = sI[j];
+                        sE[tid] = sE[j];
+                        sF[j] = tf;
+                        sI[j] = ti;
+                        sE[j] = te;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    if (int(tid) < cnt && int(tid) < k) {
+        TopkState o;
+        o.E = sE[tid];
+        o.E64 = sF[tid];
+        o.index = sI[tid];
+        out[tid] = o;
+    }
+    if (tid == 0) {
+        FinalRes r;
+        const int32_t status = sh_bad ? 3 : (cnt < k ? 4 : 0);
+        r.E = cnt > 0 ? sE[0] : 0;
+        r.index = cnt > 0 ? sI[0] : 0;
+        r.E64 = cnt > 0 ? sF[0] : 0.0;
+        r.status = status;
+        r.pad = 0;
+        *best = r;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_topk_finish(const Inst *d_inst, const Inst &hI, const TopkBufs &buf, int k,
+                              FinalRes *d_best, hipStream_t stream)
+{
+    if (k < 2 || k > kSelThreads) return hipErrorInvalidValue;
+    SelArgs st{};
+    if (hI.direct) {
+        const uint32_t N = 1u << hI.n;
+        const uint32_t blocks = (N + 255) / 256;
+        hipLaunchKernelGGL(topk_direct_kernel, dim3(blocks), dim3(256), 0, stream, d_inst, buf.stE,
+                           buf.stI, buf.segCount);
+        st.nseg = 1;
+        st.stride = N;
+    } else {
+        SelArgs ch{};
+        ch.E = buf.walk.listE;
+        ch.R = buf.walk.listR;
+        ch.segCount = buf.walk.listCount;
+        ch.nseg = uint32_t(buf.waves);
+        ch.stride = uint32_t(k);
+        ch.k = k;
+        ch.oE = buf.chunkE;
+        ch.oR = buf.chunkR;
+        ch.oCount = buf.chunkCount;
+        hipLaunchKernelGGL(topk_select_kernel, dim3(1), dim3(kSelThreads), 0, stream, ch);
+        hipLaunchKernelGGL(topk_rescan_kernel, dim3(k), dim3(256), 0, stream, d_inst, buf.chunkR,
+                           buf.chunkCount, buf.stE, buf.stI, buf.segCount);
+        st.nseg = uint32_t(k);
+        st.stride = 1u << hI.B;
+    }
+    st.E = buf.stE;
+    st.R = buf.stI;
+    st.segCount = buf.segCount;
+    st.k = k;
+    st.oE = buf.selE;
+    st.oR = buf.selR;
+    st.oCount = buf.selCount;
+    hipLaunchKernelGGL(topk_select_kernel, dim3(1), dim3(kSelThreads), 0, stream, st);
+    hipLaunchKernelGGL(topk_final_kernel, dim3(1), dim3(kSelThreads), 0, stream, d_inst, buf.selE,
+                       buf.selR, buf.selCount, k, buf.out, d_best);
+    return hipGetLastError();
+}
+
+}  // namespace qk

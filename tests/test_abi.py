@@ -135,3 +135,12 @@ def test_solve_without_gpu_fails_loudly():
     with pytest.raises(q.QuboError) as e:
         q.solve(inputs.uniform_int(16, -5, 5, 1))
     assert e.value.status == -5
+
+
+def test_topk_argument_checks_need_no_gpu():
+    import paper_2607_04857_amd as q
+    Q = np.zeros((3, 3), dtype=np.int32)
+    for k in (9, 1025, -1):
+        with pytest.raises(q.QuboError) as ei:
+            q.solve(Q, k=k)
+        assert ei.value.status == -1

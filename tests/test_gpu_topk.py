@@ -1,0 +1,112 @@
+"""GPU top-k: the k smallest (E, index) pairs (tier-3 lists, chunk select,
+rescan, state select) against the oracle's exhaustive top-k."""
+import numpy as np
+import pytest
+
+from paper_2607_04857_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _exact(orc, q, Q, k, **kw):
+    res, pairs = q.solve(Q, k=k, **kw)
+    ref = orc.solve(Q, k=k)
+    assert pairs == [(int(e), int(i)) for e, i in ref], (Q.shape, k, kw)
+    assert (res.energy_i, res.index) == pairs[0]
+    return res, pairs
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 10, 11, 13, 14])
+def test_direct_sizes(orc, n):
+    import paper_2607_04857_amd as q
+    Q = inputs.uniform_int(n, -100, 100, 1000 + n)
+    for k in sorted({2, 3, min(2 ** n, 17), min(2 ** n, 1024)}):
+        if k <= 2 ** n and k >= 2:
+            _exact(orc, q, Q, k)
+
+
+@pytest.mark.parametrize("n,k", [(15, 2), (15, 1024), (16, 7), (18, 64), (20, 100), (21, 1000),
+                                 (22, 1024), (24, 33), (26, 512)])
+def test_walk_sizes(orc, n, k):
+    import paper_2607_04857_amd as q
+    Q = inputs.uniform_int(n, -1000, 1000, 1100 + n)
+    res, _ = _exact(orc, q, Q, k)
+    assert res.tier == 3
+    print(f"top-k n={n} k={k} ok ({res.kernel_ms:.3f} ms walk)", flush=True)
+
+
+@pytest.mark.parametrize("B,G", [(6, 12), (7, 12), (8, 12), (9, 12), (9, 8), (10, 12), (10, 8),
+                                 (10, 6), (10, 5)])
+def test_every_walk_variant(orc, B, G):
+    import paper_2607_04857_amd as q
+    Q = inputs.uniform_int(22, -500, 500, 1200 + B * 16 + G)
+    res, _ = _exact(orc, q, Q, 100, B=B, vgpr_levels=G)
+    assert (res.B, res.vgpr_levels, res.tier) == (B, G, 3)
+
+
+def test_ties(orc):
+    import paper_2607_04857_amd as q
+    # all-zero: every state has E = 0; the answer is indices 0..k-1
+    res, pairs = q.solve(np.zeros((18, 18), dtype=np.int32), k=1024)
+    assert pairs == [(0, i) for i in range(1024)]
+    # entries in {-1, 0, 1}: massive ties at every energy
+    rng = np.random.default_rng(77)
+    Q = np.triu(rng.integers(-1, 2, (20, 20))).astype(np.int32)
+    _exact(orc, q, Q, 1024)
+    # diagonal only (closed form: independent bits)
+    d = np.diag(rng.integers(-3, 4, 17)).astype(np.int32)
+    _exact(orc, q, d, 300)
+
+
+def test_small_item_sizes_many_lists(orc):
+    import paper_2607_04857_amd as q
+    Q = inputs.uniform_int(24, -100, 100, 1300)
+    _exact(orc, q, Q, 1024, L=5)          # 2^9 items of 32 steps
+    _exact(orc, q, Q, 50, L=5, waves_per_cu=1)
+
+
+def test_fp32(orc):
+    import paper_2607_04857_amd as q
+    for n, k in [(12, 40), (18, 50), (21, 300)]:
+        Q = inputs.normal_fp32(n, 1400 + n)
+        res, pairs = q.solve(Q, k=k)
+        ref = orc.solve(Q, k=k)
+        assert len(pairs) == k and len({i for _, i in pairs}) == k
+        for (e, i), (re_, _) in zip(pairs, ref):
+            assert abs(e - re_) <= res.tol, (n, e, re_, res.tol)
+            assert e == orc.energy(Q, i)      # the reported value is the state's float64 energy
+        assert [e for e, _ in pairs] == sorted(e for e, _ in pairs)
+
+
+def test_k1_and_k0_unchanged(orc):
+    import paper_2607_04857_amd as q
+    Q = inputs.uniform_int(20, -100, 100, 1500)
+    E, idx = orc.solve(Q, k=1)[0]
+    for k in (0, 1):
+        r = q.solve(Q, k=k)
+        r = r[0] if isinstance(r, tuple) else r
+        assert (r.energy_i, r.index) == (E, idx) and r.tier == 2
+
+
+def test_full_size_properties(orc):
+    """n = 40: the i-th returned energy is at most the i-th smallest energy of
+    any explicit set of states (here the k=1 answer's neighbourhood and random
+    states), the list is sorted, and its head is the k = 1 answer."""
+    import paper_2607_04857_amd as q
+    Q = inputs.uniform_int(40, -10000, 10000, 4)
+    k = 64
+    res, pairs = q.solve(Q, k=k)
+    one = q.solve(Q)
+    assert pairs[0] == (one.energy_i, one.index)
+    assert pairs == sorted(pairs) and len({i for _, i in pairs}) == k
+    for e, i in pairs[:8] + pairs[-8:]:
+        assert e == orc.energy(Q, i)
+    n = 40
+    sample = {one.index} | {one.index ^ (1 << b) for b in range(n)}
+    sample |= {one.index ^ (1 << b) ^ (1 << c) for b in range(n) for c in range(b)}
+    rng = np.random.default_rng(9)
+    sample |= set(int(x) for x in rng.integers(0, 2 ** n, 200, dtype=np.uint64))
+    ref = sorted((orc.energy(Q, s), s) for s in sample)
+    for (e, _), (se, _) in zip(pairs, ref):
+        assert e <= se
+    print(f"n=40 k=64: walk {res.kernel_ms:.1f} ms (k=1: {one.kernel_ms:.1f} ms)", flush=True)
