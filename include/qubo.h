@@ -80,7 +80,8 @@ typedef struct {
     int A, B;            /* prefix / suffix split used (A + B = n); B = 0: direct  */
     int L;               /* log2 Gray steps per work item                          */
     int tier;            /* 0 direct evaluation (n <= 14); 1 exact lane-min every
-                            Gray step; 2 block lower bound, exact min on demand   */
+                            Gray step; 2 block lower bound, exact min on demand;
+                            3 tier 2's test against a top-k threshold (k > 1)  */
     int vgpr_levels;     /* Gray levels with VGPR-resident rows (0 when direct)    */
     uint64_t states;     /* states evaluated = 2^n                                 */
     double kernel_ms;    /* GPU time of the walk kernel (HIP events)               */
@@ -106,9 +107,18 @@ typedef struct {
 } qubo_options_t;
 
 /* Solve one instance held in HOST memory.  k = 0 or 1: best state only
- * (topk may be NULL).  k > 1: additionally the k lexicographically smallest
- * (E, index) pairs into topk[0..k-1] (k <= 1024, k <= 2^n); topk[0] equals
- * out->best.  Uses device 0 (or the current HIP device) and its own stream. */
+ * (topk may be NULL).  k > 1 (the k lowest energies, an extension the paper
+ * names in Sec. VI): additionally the k lexicographically smallest
+ * (E, index) pairs into topk[0..k-1], ascending (2 <= k <= 1024, k <= 2^n),
+ * and out->best = topk[0].  The walk then runs tier 3 (per-wave candidate
+ * lists of chunk keys; a selection of the k smallest chunks, their rescan
+ * and a selection of the k smallest states finish it).  int32: exact.
+ * float32: the k smallest scaled integer energies, reported with their
+ * float64 energies and ordered by (energy, index); the i-th reported energy
+ * is within out->tol of the exact i-th smallest energy.  Batches and the
+ * server return the best state only.  Uses the current HIP device and a
+ * stream of the calling thread.  Errors: QUBO_EINVAL for a bad k (checked
+ * before any device work). */
 qubo_status_t qubo_solve(const void *Q, int n, qubo_dtype_t dtype, int k,
                          qubo_result_t *out, qubo_state_t *topk);
 

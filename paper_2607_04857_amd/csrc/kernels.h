@@ -9,12 +9,13 @@
 //   EB  [2^B]         suffix energies E_s(U_B) (Sec. III-A, preprocessing 2)
 //   S   [A][64]       S[w][l] = T[min(l,w)][max(l,w)] for l != w < A, else 0:
 //                     the prefix couplings, one lane per variable
-//   K   [6][16]       (all instances' K tables are contiguous) tier-2 bound constants per super-block offset o and
-//                     table (0: o < 16; 1: o >= 16, level-4 bit rising;
-//                     2: o >= 16, falling): rows 0..2 hold C2 = ELOW + D,
-//                     rows 3..5 hold D, where D is the minimum over all 2^B
-//                     columns of E_sd(o) - E_sd(super-block start) and ELOW the
-//                     low-low coupling energy of the low pattern at o;
+//   K   [6][16]+[4]   (all instances' K tables are contiguous) tier-2 bound
+//                     constants per super-block offset o and table (0: o < 16;
+//                     1: o >= 16, level-4 bit rising; 2: o >= 16, falling):
+//                     rows 0..2 hold C2 = ELOW + D, rows 3..5 hold D, where D
+//                     is the minimum over all 2^B columns of E_sd(o) -
+//                     E_sd(super-block start) and ELOW the low-low coupling
+//                     energy of the low pattern at o; then min_o C2 per table;
 //                     then SL[64][4]: SL[w][t] = coupling of prefix variable w
 //                     with the low variable A-1-t (0 when equal), so a flip of
 //                     w moves the low fields by scalar loads only
@@ -30,7 +31,8 @@ constexpr int kWave = 64;
 constexpr int kSuperLog = 5;          // unrolled super-block: 32 Gray steps
 constexpr int kLowLevels = 4;         // Gray levels with static patterns in a super-block
 constexpr int kPatterns = 1 << kLowLevels;
-constexpr int kKBound = 6 * kPatterns;   // bound constants at the head of a K table
+constexpr int kKC2Min = 6 * kPatterns;   // min over o of C2 per table (3 used of 4)
+constexpr int kKBound = kKC2Min + 4;     // bound constants at the head of a K table
 constexpr int kKTable = kKBound + 4 * kWave;  // + SL[w][t], t < 4: ints per K table
 constexpr int kMaxVgprLevels = 12;    // at most Gray levels 0..11 keep their M_int row in VGPRs
 constexpr int32_t kNoEnergy = 1 << 30;  // above every energy the walk can meet

@@ -105,6 +105,17 @@ __device__ __forceinline__ int32_t wave_min(int32_t v)
     return min(min(a, b), min(c, d));
 }
 
+// Keeps every element of a chunk vector materialised at this point: the
+// walk updates the chunk energies once per state (Eq. incremental_update)
+// even where no test reads them, rather than letting the compiler fold
+// several flips into their net change.
+template <int MC>
+__device__ __forceinline__ void pin_vec(int32_t (&e)[MC])
+{
+#pragma unroll
+    for (int j = 0; j < MC; j++) asm("" : "+v"(e[j]));
+}
+
 __device__ __forceinline__ int64_t wave_sum64(int64_t v)
 {
 #pragma unroll
@@ -189,6 +200,7 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
     }
     for (int tab = 0; tab < 3; tab++) {
         const int c4 = tab == 0 ? 0 : (tab == 1 ? 1 : -1);
+        int32_t c2min = INT32_MAX;   // (thread 0)
         for (int o16 = 0; o16 < kPatterns; o16++) {
             const int o = tab == 0 ? o16 : kPatterns + o16;
             const int pat = (o ^ (o >> 1)) & (kPatterns - 1);
@@ -213,10 +225,13 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
                         if (((pat >> t) & 1) && ((pat >> u) & 1)) elow += T[(A - 1 - u) * n + (A - 1 - t)];
                 I.K[(3 + tab) * kPatterns + o16] = red[0];
                 I.K[tab * kPatterns + o16] = elow + red[0];
+                c2min = min(c2min, elow + red[0]);
             }
             __syncthreads();
         }
+        if (threadIdx.x == 0) I.K[kKC2Min + tab] = c2min;
     }
+    if (threadIdx.x == 0) I.K[kKC2Min + 3] = 0;
 }
 
 // ---------------------------------------------------------------- walk
@@ -567,7 +582,6 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
             for_each_tp(half, tab, [&](auto oc, int32_t tp) { TP[decltype(oc)::value] = tp; });
         };
         if constexpr (TIER == 1) build_thr();
-        else build_tp(0, 0);
 
         // A non-low prefix variable w flips (direction up: 0 -> 1); SLw[t] is
         // its coupling with the low variable A-1-t.
@@ -636,6 +650,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
             constexpr bool up = decltype(upc)::value;
 #pragma unroll
             for (int j = 0; j < MC; j++) E[j] = up ? E[j] + R[t][j] : E[j] - R[t][j];
+            pin_vec<MC>(E);
         };
         // Level-4 flip in the middle of super-block sb.
         auto middle_flip = [&](uint64_t sb) {
@@ -647,6 +662,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
 #pragma unroll
                 for (int j = 0; j < MC; j++) E[j] -= R[4][j];
             }
+            pin_vec<MC>(E);
             nonlow_flip(A - 5, up, S4, S4L);
             return up;
         };
@@ -677,6 +693,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
                     E[j] = up ? E[j] + r : E[j] - r;
                 }
             }
+            pin_vec<MC>(E);
             int32_t SLw[kLowLevels];
             static_for<0, kLowLevels>([&](auto tc) {
                 constexpr int tt = decltype(tc)::value;
@@ -715,30 +732,49 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
                     // per-step bound test, and the 15 low flips between them
                     // Every step's chunk energies stay observable through the
                     // (rarely taken) test, so each state gets its add.
-                    static_for<0, H16>([&](auto oc) {
+                    // exact test of step o2 (cold path)
+                    auto step_check = [&](auto oc) {
                         constexpr int o2 = decltype(oc)::value;
                         constexpr int o = h * H16 + o2;
-                        if (__builtin_expect(W0 <= TP[o2], 0)) {
+                        if (W0 <= TP[o2]) {
                             const int32_t thr = TP[o2] + kall[kbase + (3 + tab2) * kPatterns + o2];
                             if constexpr (TIER == 3)
                                 candidate3(tree_min<MC>(E), thr, (sb << kSuperLog) | uint64_t(o));
                             else
                                 candidate(tree_min<MC>(E), thr, (sb << kSuperLog) | uint64_t(o));
                         }
+                    };
+                    // the low flip after step o2 (none after the last step)
+                    auto step_flip = [&](auto oc) {
+                        constexpr int o2 = decltype(oc)::value;
+                        constexpr int o = h * H16 + o2;
                         if constexpr (o2 < H16 - 1) {
                             constexpr int t = cx_ctz(o + 1);
                             constexpr bool up = ((((o + 1) ^ ((o + 1) >> 1)) >> t) & 1) != 0;
                             low_flip(std::integral_constant<int, t>{},
                                      std::integral_constant<bool, up>{});
                         }
-                    });
+                    };
+                    // One scalar test for the half: an upper bound of its 16
+                    // thresholds tp(o) = best - Enl - hs(o) - C2(o), since
+                    // hs(o) >= sum_t min(0, H[t]) and C2(o) >= min_o C2.
+                    int32_t tb = best - Enl - kall[kbase + kKC2Min + tab2];
+                    static_for<0, kLowLevels>([&](auto tc) { tb -= min(0, H[decltype(tc)::value]); });
+                    if (__builtin_expect(W0 <= tb, 0)) {
+                        // exact per-step thresholds and tests
+                        build_tp(h, tab2);
+                        static_for<0, H16>([&](auto oc) {
+                            step_check(oc);
+                            step_flip(oc);
+                        });
+                    } else {
+                        static_for<0, H16>([&](auto oc) { step_flip(oc); });
+                    }
                     if constexpr (h == 0) {
                         tab2 = middle_flip(sb) ? 1 : 2;
-                        build_tp(1, tab2);
                     } else if (sb + 1 < sbEnd) {
                         boundary_flip(sb);
                         tab2 = 0;
-                        build_tp(0, 0);
                     }
                 });
             }
