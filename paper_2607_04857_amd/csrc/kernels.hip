@@ -105,6 +105,14 @@ __device__ __forceinline__ int32_t wave_min(int32_t v)
     return min(min(a, b), min(c, d));
 }
 
+// Global (address space 1) view of a table pointer: loads then take a
+// uniform base in SGPRs and a lane offset, instead of 64-bit flat addresses.
+using gint32 = __attribute__((address_space(1))) const int32_t;
+__device__ __forceinline__ const gint32 *to_global(const int32_t *p)
+{
+    return (const gint32 *)p;
+}
+
 // Keeps every element of a chunk vector materialised at this point: the
 // walk updates the chunk energies once per state (Eq. incremental_update)
 // even where no test reads them, rather than letting the compiler fold
@@ -427,9 +435,14 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
     static_assert(G >= kSuperLog && G <= kMaxVgprLevels, "VGPR-resident levels");
     constexpr int H16 = kPatterns;   // steps per half super-block
     const int lane = int(threadIdx.x);
+    const uint32_t ulane = threadIdx.x;
+    // row v of a lane-major [rows][MC*64] table: uniform base pointer
+    auto trow = [](const gint32 *t, int v) { return t + size_t(v) * (MC * kWave); };
 
     int cur = -1;
-    const int32_t *M = nullptr, *EB = nullptr, *S = nullptr;
+    // the tables, addressed as global memory (uniform base + lane offset +
+    // immediate), not through generic pointers
+    const gint32 *M = nullptr, *EB = nullptr, *S = nullptr;
     ItemRes *ires = nullptr;
     int kbase = 0;                // this instance's K table: kall[kbase ...] (scalar loads)
     int A = 0, L = 0;
@@ -460,9 +473,9 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
         if (lo != cur) {
             cur = lo;
             const Inst &I = insts[lo];
-            M = I.M;
-            EB = I.EB;
-            S = I.S;
+            M = to_global(I.M);
+            EB = to_global(I.EB);
+            S = to_global(I.S);
             kbase = I.kslot * kKTable;
             A = I.A;
             L = I.L;
@@ -474,9 +487,9 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
                 const bool have = t < A;
                 const int v = have ? A - 1 - t : 0;
 #pragma unroll
-                for (int j = 0; j < MC; j++) R[t][j] = have ? M[(v * MC + j) * kWave + lane] : 0;
+                for (int j = 0; j < MC; j++) R[t][j] = have ? trow(M, v)[j * kWave + ulane] : 0;
             });
-            S4 = S[(A - 5) * kWave + lane];
+            S4 = S[size_t(A - 5) * kWave + ulane];
             static_for<0, kLowLevels>([&](auto tc) {
                 constexpr int t = decltype(tc)::value;
                 S4L[t] = kall[kbase + kKBound + (A - 5) * 4 + t];
@@ -518,18 +531,18 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
 
         int32_t E[MC];
 #pragma unroll
-        for (int j = 0; j < MC; j++) E[j] = EB[j * kWave + lane];
+        for (int j = 0; j < MC; j++) E[j] = EB[j * kWave + ulane];
         for (int v = 0; v < A; v++) {
             if ((row0 >> (A - 1 - v)) & 1) {
 #pragma unroll
-                for (int j = 0; j < MC; j++) E[j] += M[(v * MC + j) * kWave + lane];
+                for (int j = 0; j < MC; j++) E[j] += trow(M, v)[j * kWave + ulane];
             }
         }
         // F: field of every prefix variable from the non-low ones (levels >= 4,
         // variables 0..A-5), plus its diagonal; one lane per variable.
         int32_t F = diagl;
         for (int w = 0; w <= A - 5; w++)
-            if ((row0 >> (A - 1 - w)) & 1) F += S[w * kWave + lane];
+            if ((row0 >> (A - 1 - w)) & 1) F += S[size_t(w) * kWave + ulane];
         // E_nl = energy of the non-low prefix bits = (sum_set F_w + T_ww) / 2
         const bool lbit = lane <= A - 5 && ((row0 >> (A - 1 - lane)) & 1);
         int32_t Enl = int32_t(wave_sum64(lbit ? int64_t(F) + diagl : 0) / 2);
@@ -689,7 +702,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
             if (!done) {
 #pragma unroll
                 for (int j = 0; j < MC; j++) {
-                    const int32_t r = M[(w * MC + j) * kWave + lane];
+                    const int32_t r = trow(M, w)[j * kWave + ulane];
                     E[j] = up ? E[j] + r : E[j] - r;
                 }
             }
@@ -699,7 +712,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
                 constexpr int tt = decltype(tc)::value;
                 SLw[tt] = kall[kbase + kKBound + w * 4 + tt];
             });
-            nonlow_flip(w, up, S[w * kWave + lane], SLw);
+            nonlow_flip(w, up, S[size_t(w) * kWave + ulane], SLw);
         };
 
         if constexpr (TIER == 1) {
