@@ -72,8 +72,13 @@ struct TopkWalk {
     uint64_t *listR;     // [waves][k] prefix rows of those chunks
     int32_t *listCount;  // [waves] entries used (written by every wave on exit)
     int32_t *gthr;       // shared bound, kNoEnergy before the walk
+    uint32_t *hist;      // [kTopkBins] keys entered into any list, by energy bin (zeroed)
+    int32_t *lowbin;     // lowest non-empty bin (kTopkBins before the walk)
+    int64_t hist_lo;     // energy of bin 0's lower edge (-sum|T|)
+    int hist_shift;      // bin = (E - hist_lo) >> hist_shift
     int k;
 };
+constexpr int kTopkBins = 16384;
 
 // One state of a top-k answer; the same layout as qubo_state_t.
 struct TopkState {
@@ -86,12 +91,15 @@ struct TopkState {
 struct TopkBufs {
     TopkWalk walk;
     int waves;           // lists in walk.listE (walked instances)
+    int32_t *candE;      // [waves * k] list entries <= the final bound, dense ...
+    uint64_t *candR;
+    int32_t *candN;      // [1] their number (zero before the finish)
     int32_t *chunkE;     // [k] the k smallest chunk keys ...
     uint64_t *chunkR;    // [k] ... and their prefix rows
     int32_t *chunkCount; // [1] chunks selected (min(k, chunks met))
     int32_t *stE;        // [k << B] (or [2^n] direct) candidate state energies
     uint64_t *stI;       // same, U_N rows
-    int32_t *segCount;   // [k] valid states per rescanned chunk ([1] direct)
+    int32_t *segCount;   // [k] states per rescanned chunk ([0] = 2^n direct)
     int32_t *selE;       // [k] the k smallest states, sorted by (E, index)
     uint64_t *selR;
     int32_t *selCount;   // [1]
@@ -128,7 +136,7 @@ bool walk_variant_exists(int mcols, int vgpr_levels);
 int walk_occupancy(int mcols, int vgpr_levels, int tier, int topk_k = 0);
 
 // LDS bytes of one tier-3 wave's list.
-constexpr int kTopkMetaWords = 9;   // 64-bit words of list scalars ahead of the entries
+constexpr int kTopkMetaWords = 13;  // 64-bit words of list scalars ahead of the entries
 inline size_t topk_lds_bytes(int k)
 {
     return size_t(kTopkMetaWords) * 8 + size_t(k) * (sizeof(uint64_t) + sizeof(int32_t));

@@ -277,14 +277,25 @@ constexpr int walk_waves_per_simd()
 // values outside the unrolled steps.)
 
 // ---- tier-3 list (top-k).  One wave per workgroup; the list lives in
-// dynamic LDS: 9 64-bit words of scalars, then k rows and k energies.  All
-// list state stays in LDS (not SGPRs) and the list code sits in functions
-// that are not inlined: only the rare candidate path touches it, and the
-// walk's registers stay those of tier 2.
+// dynamic LDS: kTopkMetaWords 64-bit words of scalars, then k rows and k
+// energies.  All list state stays in LDS (not SGPRs) and the list code sits
+// in functions that are not inlined: only the rare candidate path touches
+// it, and the walk's registers stay those of tier 2.
 //   M[0] entries used  M[1] slot of the largest key  M[2] its E (kNoEnergy
 //   until the list is full)  M[3] lowest shared bound seen  M[4] k
+//   M[5] histogram bin shift
 //   P[0] the largest key's row  P[1] gthr  P[2] listE  P[3] listR
-//   P[4] listCount   (M = words 0..3 as int32, P = words 4..8)
+//   P[4] listCount  P[5] hist  P[6] lowbin  P[7] hist_lo
+//   (M = words 0..3 as int32, P = words 4..12)
+//
+// Shared bound.  Every key that enters any wave's list is also counted in a
+// device-wide histogram by energy bin.  Keys entered belong to distinct
+// chunks (each chunk is walked once), so if the bins up to b hold at least k
+// of them, at least k chunks have a key <= the upper edge of bin b, which
+// therefore bounds the instance's k-th smallest chunk key: no chunk above it
+// can be among the k smallest.  Each insertion recomputes that edge and
+// lowers gthr; every wave's threshold is min(its own list's largest E when
+// full, gthr).
 extern __shared__ uint64_t tk_lds[];
 
 __device__ __forceinline__ int32_t *tk_M() { return reinterpret_cast<int32_t *>(tk_lds); }
@@ -306,11 +317,15 @@ __device__ __forceinline__ void tk_init(const TopkWalk &tk)
         M[2] = kNoEnergy;
         M[3] = kNoEnergy;
         M[4] = tk.k;
+        M[5] = tk.hist_shift;
         P[0] = 0;
         P[1] = reinterpret_cast<uint64_t>(tk.gthr);
         P[2] = reinterpret_cast<uint64_t>(tk.listE);
         P[3] = reinterpret_cast<uint64_t>(tk.listR);
         P[4] = reinterpret_cast<uint64_t>(tk.listCount);
+        P[5] = reinterpret_cast<uint64_t>(tk.hist);
+        P[6] = reinterpret_cast<uint64_t>(tk.lowbin);
+        P[7] = uint64_t(tk.hist_lo);
     }
     __syncthreads();
 }
@@ -371,6 +386,49 @@ __device__ int32_t tk_rescan(int k)
     return mE;
 }
 
+// Count key energy Ec in the shared histogram and lower gthr to the upper
+// edge of the first bin where the running count reaches k.
+__device__ void tk_count(int32_t Ec, int k)
+{
+    const uint64_t *P = tk_P();
+    uint32_t *hist = reinterpret_cast<uint32_t *>(sread64(P[5]));
+    int32_t *lowbin = reinterpret_cast<int32_t *>(sread64(P[6]));
+    const int64_t lo = int64_t(sread64(P[7]));
+    const int shift = sread(tk_M()[5]);
+    const int lane = int(threadIdx.x);
+    int b = int((int64_t(Ec) - lo) >> shift);
+    b = b < 0 ? 0 : (b >= kTopkBins ? kTopkBins - 1 : b);
+    if (lane == 0) {
+        atomicAdd(&hist[b], 1u);
+        atomicMin(lowbin, b);
+    }
+    __threadfence();
+    int base = sread(__hip_atomic_load(lowbin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    uint32_t cum = 0;
+    for (; base < kTopkBins; base += kWave) {
+        const int bin = base + lane;
+        uint32_t c = bin < kTopkBins
+                         ? __hip_atomic_load(&hist[bin], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                         : 0u;
+        // inclusive prefix sum over the wave
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t o = __shfl_up(c, off, kWave);
+            if (lane >= off) c += o;
+        }
+        const uint32_t total = uint32_t(__builtin_amdgcn_readlane(int32_t(c), kWave - 1));
+        if (cum + total >= uint32_t(k)) {
+            const uint64_t hit = __builtin_amdgcn_ballot_w64(cum + c >= uint32_t(k));
+            const int bstar = base + int(__builtin_ctzll(hit));
+            const int64_t edge = lo + (int64_t(bstar + 1) << shift) - 1;
+            const int32_t T = edge > int64_t(kNoEnergy) ? kNoEnergy : int32_t(edge);
+            if (lane == 0) atomicMin(tk_gthr(), T);
+            return;
+        }
+        cum += total;
+    }
+}
+
 // Offer chunk key (Ec, rc), Ec <= the current threshold: append while the
 // list has room, else replace the largest key if (Ec, rc) is smaller.
 // Returns the new threshold.
@@ -383,6 +441,7 @@ __device__ __noinline__ int32_t tk_insert(int32_t Ec, uint64_t rc)
     const int cnt = sread(M[0]);
     const int k = sread(M[4]);
     int32_t lkth = sread(M[2]);
+    bool entered = false;
     if (cnt < k) {
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -390,6 +449,7 @@ __device__ __noinline__ int32_t tk_insert(int32_t Ec, uint64_t rc)
             tk_R()[cnt] = rc;
             M[0] = cnt + 1;
         }
+        entered = true;
         if (cnt + 1 == k) lkth = tk_rescan(k);
     } else {
         const uint64_t lkR = sread64(tk_P()[0]);
@@ -400,9 +460,14 @@ __device__ __noinline__ int32_t tk_insert(int32_t Ec, uint64_t rc)
                 tk_E(k)[pos] = Ec;
                 tk_R()[pos] = rc;
             }
+            entered = true;
             lkth = tk_rescan(k);
         }
     }
+    if (entered) tk_count(Ec, k);
+    const int32_t g = sread(__hip_atomic_load(tk_gthr(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    __syncthreads();
+    if (threadIdx.x == 0) M[3] = min(M[3], g);
     __syncthreads();
     return min(lkth, sread(M[3]));
 }

@@ -18,7 +18,7 @@ struct JobOffsets {
     size_t insts = 0, counter = 0, res = 0, out = 0, K = 0;
     std::vector<size_t> T, Qf, M, EB, S;
     // top-k (k > 1, one instance)
-    size_t gthr = 0, listE = 0, listR = 0, listCount = 0, chunkE = 0, chunkR = 0, chunkCount = 0,
+    size_t gthr = 0, hist = 0, lowbin = 0, candN = 0, candE = 0, candR = 0, listE = 0, listR = 0, listCount = 0, chunkE = 0, chunkR = 0, chunkCount = 0,
            stE = 0, stI = 0, segCount = 0, selE = 0, selR = 0, selCount = 0, topk = 0;
 };
 
@@ -78,9 +78,15 @@ static JobOffsets compute_offsets(const Job &job, size_t *stage_bytes, size_t *b
         }
     }
     const size_t k = size_t(job.topk);
-    if (k > 1) {   // the shared top-k bound starts in the uploaded image
+    if (k > 1) {   // the shared top-k bound and histogram start in the uploaded image
         o.gthr = off;
         off = align_up(off + sizeof(int32_t), 256);
+        o.lowbin = off;
+        off = align_up(off + sizeof(int32_t), 256);
+        o.candN = off;
+        off = align_up(off + sizeof(int32_t), 256);
+        o.hist = off;
+        off = align_up(off + qk::kTopkBins * sizeof(uint32_t), 256);
     }
     *stage_bytes = off;
     o.counter = off;
@@ -112,6 +118,8 @@ static JobOffsets compute_offsets(const Job &job, size_t *stage_bytes, size_t *b
         put(&o.listE, W * k * sizeof(int32_t));
         put(&o.listR, W * k * sizeof(uint64_t));
         put(&o.listCount, W * sizeof(int32_t));
+        put(&o.candE, W * k * sizeof(int32_t));
+        put(&o.candR, W * k * sizeof(uint64_t));
         put(&o.chunkE, k * sizeof(int32_t));
         put(&o.chunkR, k * sizeof(uint64_t));
         put(&o.chunkCount, sizeof(int32_t));
@@ -234,15 +242,27 @@ qubo_status_t job_bind(Job *job, void *d_mem)
     }
     std::memcpy(job->stage.data() + o.insts, insts.data(), insts.size() * sizeof(qk::Inst));
     if (job->topk > 1) {
-        const int32_t none = qk::kNoEnergy;
+        const int32_t none = qk::kNoEnergy, nobin = qk::kTopkBins;
         std::memcpy(job->stage.data() + o.gthr, &none, sizeof(none));
+        std::memcpy(job->stage.data() + o.lowbin, &nobin, sizeof(nobin));
         qk::TopkBufs &t = job->tkb;
         t.walk.listE = reinterpret_cast<int32_t *>(base + o.listE);
         t.walk.listR = reinterpret_cast<uint64_t *>(base + o.listR);
         t.walk.listCount = reinterpret_cast<int32_t *>(base + o.listCount);
         t.walk.gthr = reinterpret_cast<int32_t *>(base + o.gthr);
+        t.walk.hist = reinterpret_cast<uint32_t *>(base + o.hist);
+        t.walk.lowbin = reinterpret_cast<int32_t *>(base + o.lowbin);
+        // bins of (E + sum|T|) over [0, 2 sum|T|]
+        const int64_t span = 2 * job->plans[0].sum_abs;
+        int shift = 0;
+        while ((span >> shift) >= qk::kTopkBins) shift++;
+        t.walk.hist_lo = -job->plans[0].sum_abs;
+        t.walk.hist_shift = shift;
         t.walk.k = job->topk;
         t.waves = job->groups.empty() ? 0 : job->groups[0].waves;
+        t.candE = reinterpret_cast<int32_t *>(base + o.candE);
+        t.candR = reinterpret_cast<uint64_t *>(base + o.candR);
+        t.candN = reinterpret_cast<int32_t *>(base + o.candN);
         t.chunkE = reinterpret_cast<int32_t *>(base + o.chunkE);
         t.chunkR = reinterpret_cast<uint64_t *>(base + o.chunkR);
         t.chunkCount = reinterpret_cast<int32_t *>(base + o.chunkCount);

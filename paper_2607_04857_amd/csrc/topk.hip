@@ -9,7 +9,8 @@
 // than it.  So:
 //   1. the tier-3 walk leaves per-wave lists of candidate chunk keys that
 //      together contain the k smallest chunks (kernels.hip);
-//   2. select the k smallest chunk keys of the lists;
+//   2. compact the list entries at or below the final shared bound, and
+//      select the k smallest chunk keys among them;
 //   3. rescan those chunks: every state's energy from the tables,
 //      E = E_p(row) + E_s(s) + x_p M_int[:, s] (Sec. II-C);
 //   4. select the k smallest (E, index) among them, sorted;
@@ -29,10 +30,10 @@ namespace {
 constexpr int kSelThreads = 1024;   // also the largest k
 
 struct SelArgs {
-    const int32_t *E;
+    const int32_t *E;          // dense candidates [0, *count * mult)
     const uint64_t *R;
-    const int32_t *segCount;   // valid entries at the head of each segment
-    uint32_t nseg, stride;     // segment s = entries [s*stride, s*stride + segCount[s])
+    const int32_t *count;
+    uint32_t mult;
     int k;
     int32_t *oE;               // [k] output, sorted by (E, R)
     uint64_t *oR;
@@ -46,15 +47,11 @@ __device__ __forceinline__ bool key_less(int32_t ea, uint64_t ra, int32_t eb, ui
     return ea < eb || (ea == eb && ra < rb);
 }
 
-// Visit every valid entry: f(E, R).
+// Visit every candidate: f(E, R).
 template <typename F>
-__device__ __forceinline__ void for_valid(const SelArgs &a, F &&f)
+__device__ __forceinline__ void for_valid(const SelArgs &a, uint32_t N, F &&f)
 {
-    const uint32_t N = a.nseg * a.stride;
-    for (uint32_t x = threadIdx.x; x < N; x += kSelThreads) {
-        const uint32_t seg = x / a.stride;
-        if (int32_t(x - seg * a.stride) < a.segCount[seg]) f(a.E[x], a.R[x]);
-    }
+    for (uint32_t x = threadIdx.x; x < N; x += kSelThreads) f(a.E[x], a.R[x]);
 }
 
 // Bin of the histogram where the running count reaches `need`.
@@ -86,9 +83,7 @@ __global__ __launch_bounds__(kSelThreads) void topk_select_kernel(SelArgs a)
     const uint32_t k = uint32_t(a.k);
 
     if (tid == 0) {
-        uint32_t t = 0;
-        for (uint32_t s = 0; s < a.nseg; s++) t += uint32_t(a.segCount[s]);
-        sh_total = t;
+        sh_total = uint32_t(*a.count) * a.mult;
         sh_pos = 0;
     }
     __syncthreads();
@@ -103,7 +98,7 @@ __global__ __launch_bounds__(kSelThreads) void topk_select_kernel(SelArgs a)
         for (int shift = 24; shift >= 0; shift -= 8) {
             for (uint32_t b = tid; b < 256; b += kSelThreads) hist[b] = 0;
             __syncthreads();
-            for_valid(a, [&](int32_t e, uint64_t) {
+            for_valid(a, total, [&](int32_t e, uint64_t) {
                 const uint32_t u = ukey(e);
                 if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 255u], 1u);
             });
@@ -122,7 +117,7 @@ __global__ __launch_bounds__(kSelThreads) void topk_select_kernel(SelArgs a)
             for (int shift = 56; shift >= 0; shift -= 8) {
                 for (uint32_t b = tid; b < 256; b += kSelThreads) hist[b] = 0;
                 __syncthreads();
-                for_valid(a, [&](int32_t e, uint64_t r) {
+                for_valid(a, total, [&](int32_t e, uint64_t r) {
                     if (ukey(e) == uk && (r & rmask) == rprefix)
                         atomicAdd(&hist[uint32_t(r >> shift) & 255u], 1u);
                 });
@@ -138,7 +133,7 @@ __global__ __launch_bounds__(kSelThreads) void topk_select_kernel(SelArgs a)
         }
     }
     // compaction into LDS (at most k entries)
-    for_valid(a, [&](int32_t e, uint64_t r) {
+    for_valid(a, total, [&](int32_t e, uint64_t r) {
         const uint32_t u = ukey(e);
         if (take_all || u < uk || (u == uk && (all_eq || r <= rk))) {
             const uint32_t p = atomicAdd(&sh_pos, 1u);
@@ -181,6 +176,39 @@ __global__ __launch_bounds__(kSelThreads) void topk_select_kernel(SelArgs a)
         a.oR[tid] = sR[tid];
     }
     if (tid == 0) *a.oCount = int32_t(cnt);
+}
+
+// The walk lists, compacted: entries with E <= *bound of every wave's list,
+// appended densely (one wave per list, wave-aggregated slots).
+__global__ __launch_bounds__(256) void topk_compact_kernel(const int32_t *__restrict__ E,
+                                                           const uint64_t *__restrict__ R,
+                                                           const int32_t *__restrict__ listCount,
+                                                           int nlists, int stride,
+                                                           const int32_t *__restrict__ bound,
+                                                           int32_t *__restrict__ oE,
+                                                           uint64_t *__restrict__ oR,
+                                                           int32_t *__restrict__ oN)
+{
+    const int lane = int(threadIdx.x) & (kWave - 1);
+    const int list = int(blockIdx.x) * (256 / kWave) + int(threadIdx.x) / kWave;
+    if (list >= nlists) return;
+    const int32_t bnd = *bound;
+    const int c = listCount[list];
+    for (int p0 = 0; p0 < c; p0 += kWave) {
+        const int p = p0 + lane;
+        const size_t x = size_t(list) * size_t(stride) + size_t(p);
+        const bool keep = p < c && E[x] <= bnd;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
+        if (!m) continue;
+        int base = 0;
+        if (lane == 0) base = atomicAdd(oN, int(__builtin_popcountll(m)));
+        base = __builtin_amdgcn_readfirstlane(base);
+        if (keep) {
+            const int rank = int(__builtin_popcountll(m & ((1ull << lane) - 1)));
+            oE[base + rank] = E[x];
+            oR[base + rank] = R[x];
+        }
+    }
 }
 
 // Step 3: block b rescans chunk rows[b] (if b < *rowCount).
@@ -329,15 +357,21 @@ hipError_t launch_topk_finish(const Inst *d_inst, const Inst &hI, const TopkBufs
         const uint32_t blocks = (N + 255) / 256;
         hipLaunchKernelGGL(topk_direct_kernel, dim3(blocks), dim3(256), 0, stream, d_inst, buf.stE,
                            buf.stI, buf.segCount);
-        st.nseg = 1;
-        st.stride = N;
+        st.count = buf.segCount;     // 2^n
+        st.mult = 1;
     } else {
+        // the lists' entries at or below the final shared bound, densely
+        const int lists_per_block = 256 / kWave;
+        const int blocks = (buf.waves + lists_per_block - 1) / lists_per_block;
+        if (blocks > 0)
+            hipLaunchKernelGGL(topk_compact_kernel, dim3(blocks), dim3(256), 0, stream,
+                               buf.walk.listE, buf.walk.listR, buf.walk.listCount, buf.waves, k,
+                               buf.walk.gthr, buf.candE, buf.candR, buf.candN);
         SelArgs ch{};
-        ch.E = buf.walk.listE;
-        ch.R = buf.walk.listR;
-        ch.segCount = buf.walk.listCount;
-        ch.nseg = uint32_t(buf.waves);
-        ch.stride = uint32_t(k);
+        ch.E = buf.candE;
+        ch.R = buf.candR;
+        ch.count = buf.candN;
+        ch.mult = 1;
         ch.k = k;
         ch.oE = buf.chunkE;
         ch.oR = buf.chunkR;
@@ -345,12 +379,11 @@ hipError_t launch_topk_finish(const Inst *d_inst, const Inst &hI, const TopkBufs
         hipLaunchKernelGGL(topk_select_kernel, dim3(1), dim3(kSelThreads), 0, stream, ch);
         hipLaunchKernelGGL(topk_rescan_kernel, dim3(k), dim3(256), 0, stream, d_inst, buf.chunkR,
                            buf.chunkCount, buf.stE, buf.stI, buf.segCount);
-        st.nseg = uint32_t(k);
-        st.stride = 1u << hI.B;
+        st.count = buf.chunkCount;   // rescanned chunks are the leading ones, full
+        st.mult = 1u << hI.B;
     }
     st.E = buf.stE;
     st.R = buf.stI;
-    st.segCount = buf.segCount;
     st.k = k;
     st.oE = buf.selE;
     st.oR = buf.selR;

@@ -110,3 +110,29 @@ def test_full_size_properties(orc):
     for (e, _), (se, _) in zip(pairs, ref):
         assert e <= se
     print(f"n=40 k=64: walk {res.kernel_ms:.1f} ms (k=1: {one.kernel_ms:.1f} ms)", flush=True)
+
+
+def test_stored_oracle_topk():
+    """The stored oracle answers (written by tests/golden/make_oracle_goldens.py
+    from oracle/ alone) include top-k lists up to n = 33."""
+    import json
+    import os
+    import paper_2607_04857_amd as q
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_results.json")))
+    checked = 0
+    for name, g in gold.items():
+        ref = g.get("topk") or []
+        if len(ref) < 2:
+            continue
+        Q = getattr(inputs, g["generator"])(**g["kwargs"])
+        if isinstance(Q, tuple):
+            Q = Q[0]
+        res, pairs = q.solve(Q, k=len(ref))
+        if g["dtype"] == "int32":
+            assert pairs == [(int(e), int(i)) for e, i in ref], name
+        else:
+            for (e, _), (re_, _) in zip(pairs, ref):
+                assert abs(e - re_) <= res.tol, name
+        checked += 1
+        print(f"{name}: top-{len(ref)} ok", flush=True)
+    assert checked >= 3
