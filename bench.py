@@ -65,7 +65,7 @@ def traffic_from_profile():
     return float(m_b.group(1))
 
 
-def cpu_baseline(Q, budget_s=12.0):
+def cpu_baseline(Q, budget_s=20.0):
     import oracle
     threads = min(16, os.cpu_count() or 1)
     n = Q.shape[0]
