@@ -54,6 +54,8 @@ struct Inst {
     uint64_t item_end;
     uint64_t item_local0;  // local index of the instance's item number item_begin
     uint64_t n_items;      // the instance's total items, 2^(A-L)
+    int32_t *gbest;        // best energy any wave has found for the instance
+                           // (kNoEnergy from the table build on)
 };
 
 struct ItemRes {

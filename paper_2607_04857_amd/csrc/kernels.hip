@@ -148,6 +148,7 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
     const Inst I = insts[blockIdx.y];
     if (blockIdx.x == 0 && blockIdx.y == 0)
         for (int c = int(threadIdx.x); c < n_counters; c += int(blockDim.x)) counters[c] = 0ull;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && I.gbest) *I.gbest = kNoEnergy;
     if (I.direct) return;
     const int n = I.n, A = I.A, B = I.B;
     const uint32_t NS = 1u << B;
@@ -517,6 +518,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
     int32_t S4L[kLowLevels];  // couplings of the level-4 variable with the low ones
     int32_t diagl = 0;       // T[l][l] on lane l < A
     int32_t CR[kPatterns];   // low-low coupling increments per pattern
+    int32_t *gbest = nullptr;     // the current instance's shared best
     int32_t best = kNoEnergy;     // tier 3: the current top-k threshold
     uint64_t bestRow = ~0ull;
 
@@ -585,6 +587,20 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
             });
             best = kNoEnergy;
             bestRow = ~0ull;
+            if constexpr (TIER != 3) gbest = I.gbest;
+        }
+
+        // Best energy found by any wave for this instance: a chunk can
+        // improve the final answer only if its key is at most that.  (A
+        // chunk tying it with an unknown row is still recorded: bestRow
+        // restarts at the largest row whenever the shared value lowers best.)
+        if constexpr (TIER != 3) {
+            const int32_t g0 = sread(__hip_atomic_load(gbest, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT));
+            if (g0 < best) {
+                best = g0;
+                bestRow = ~0ull;
+            }
         }
 
         // ---- item set-up: state g(i0) from scratch
@@ -697,6 +713,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
                     itemE = Ec;
                     itemRow = rc;
                     found = 1;
+                    if (lane == 0) atomicMin(gbest, Ec);
                     static_for<0, kPatterns>([&](auto pc) {
                         constexpr int p = decltype(pc)::value;
                         if constexpr (TIER == 1) THR[p] += d;

@@ -15,7 +15,7 @@ thread_local std::string g_last_error;
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct JobOffsets {
-    size_t insts = 0, counter = 0, res = 0, out = 0, K = 0;
+    size_t insts = 0, counter = 0, res = 0, out = 0, K = 0, gbest = 0;
     std::vector<size_t> T, Qf, M, EB, S;
     // top-k (k > 1, one instance)
     size_t gthr = 0, hist = 0, lowbin = 0, candN = 0, candE = 0, candR = 0, listE = 0, listR = 0, listCount = 0, chunkE = 0, chunkR = 0, chunkCount = 0,
@@ -107,6 +107,8 @@ static JobOffsets compute_offsets(const Job &job, size_t *stage_bytes, size_t *b
     off = align_up(off + size_t(job.total_items) * sizeof(qk::ItemRes), 256);
     o.out = off;
     off = align_up(off + ni * sizeof(qk::FinalRes), 256);
+    o.gbest = off;
+    off = align_up(off + ni * sizeof(int32_t), 256);
     if (k > 1) {
         const qplan::Plan &P = job.plans[0];
         const size_t W = job.groups.empty() ? 0 : size_t(job.groups[0].waves);
@@ -236,6 +238,7 @@ qubo_status_t job_bind(Job *job, void *d_mem)
         item += P.direct ? 0 : P.items;
         I.item_local0 = 0;
         I.n_items = P.direct ? 0 : P.items;
+        I.gbest = reinterpret_cast<int32_t *>(base + o.gbest) + i;
         const size_t nn = size_t(P.n) * P.n;
         std::memcpy(job->stage.data() + o.T[i], P.T.data(), nn * sizeof(int32_t));
         if (job->qf[i]) std::memcpy(job->stage.data() + o.Qf[i], job->qf[i], nn * sizeof(float));
