@@ -92,7 +92,14 @@ typedef struct {
  * defaults.  B: suffix bits in [6, 10] (0 = default 10); L: log2 Gray steps per
  * work item in [5, A] (0 = default); tier: 0 = default, 1 or 2 to force that
  * walk tier; waves_per_cu: resident walk waves per compute unit (0 = the
- * occupancy limit); vgpr_levels: see below. */
+ * occupancy limit); vgpr_levels: see below.
+ * item_first, item_count: walk only work items [item_first, item_first +
+ * item_count) of the plan (item_count 0 = all).  Work item c covers the prefix
+ * rows of Gray steps [c 2^L, (c+1) 2^L), which are the aligned block of rows
+ * [g(c) 2^L, (g(c)+1) 2^L) with g(c) = c ^ (c >> 1), i.e. the contiguous index
+ * range [g(c) 2^(L+B), (g(c)+1) 2^(L+B)); the result is the minimum (and top-k)
+ * over the chosen items' states.  For sampled checks at full size; not
+ * allowed for direct (n <= 14) plans or in batches. */
 typedef struct {
     int B;
     int L;
@@ -103,7 +110,9 @@ typedef struct {
                             (B = 10); fewer levels free VGPRs for a third/fourth
                             wave per SIMD, the higher rows being read from L2
                             when they flip                                    */
-    int reserved[3];
+    int item_first;
+    int item_count;
+    int reserved;
 } qubo_options_t;
 
 /* Solve one instance held in HOST memory.  k = 0 or 1: best state only

@@ -51,7 +51,8 @@ class _Result(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("B", ctypes.c_int), ("L", ctypes.c_int), ("tier", ctypes.c_int),
                 ("waves_per_cu", ctypes.c_int), ("vgpr_levels", ctypes.c_int),
-                ("reserved", ctypes.c_int * 3)]
+                ("item_first", ctypes.c_int), ("item_count", ctypes.c_int),
+                ("reserved", ctypes.c_int)]
 
 
 class _PlanInfo(ctypes.Structure):
@@ -178,21 +179,24 @@ def _as_q(Q):
     raise TypeError("Q must be int32 or float32")
 
 
-def _options(B=0, L=0, tier=0, waves_per_cu=0, vgpr_levels=0) -> _Options:
+def _options(B=0, L=0, tier=0, waves_per_cu=0, vgpr_levels=0, item_first=0,
+             item_count=0) -> _Options:
     o = _Options()
     o.B, o.L, o.tier, o.waves_per_cu = int(B), int(L), int(tier), int(waves_per_cu)
     o.vgpr_levels = int(vgpr_levels)
+    o.item_first, o.item_count = int(item_first), int(item_count)
     return o
 
 
 def solve(Q, k: int = 1, *, B: int = 0, L: int = 0, tier: int = 0, waves_per_cu: int = 0,
-          vgpr_levels: int = 0):
-    """Minimise E(x) for a host matrix.  k > 1 also returns the k smallest (E, index) pairs."""
+          vgpr_levels: int = 0, item_first: int = 0, item_count: int = 0):
+    """Minimise E(x) for a host matrix.  k > 1 also returns the k smallest (E, index) pairs.
+    item_first/item_count restrict the walk to those work items (see qubo_options_t)."""
     Qc, dt = _as_q(Q)
     n = Qc.shape[0]
     out = _Result()
     top = (_State * k)() if k > 1 else None
-    opt = _options(B, L, tier, waves_per_cu, vgpr_levels)
+    opt = _options(B, L, tier, waves_per_cu, vgpr_levels, item_first, item_count)
     _check(lib().qubo_solve_ex(Qc.ctypes.data, n, dt, int(k), ctypes.byref(opt),
                                ctypes.byref(out), top))
     res = _result(out, n)
@@ -338,13 +342,15 @@ class Server:
             pass
 
 
-def plan_info(Q, *, B: int = 0, L: int = 0, tier: int = 0, vgpr_levels: int = 0):
+def plan_info(Q, *, B: int = 0, L: int = 0, tier: int = 0, vgpr_levels: int = 0,
+              item_first: int = 0, item_count: int = 0):
     """Host-only plan of a solve (no GPU): split, items, scale; plus the folded T."""
     Qc, dt = _as_q(Q)
     n = Qc.shape[0]
     info = _PlanInfo()
     T = np.zeros((n, n), dtype=np.int32)
-    opt = _options(B, L, tier, vgpr_levels=vgpr_levels)
+    opt = _options(B, L, tier, vgpr_levels=vgpr_levels, item_first=item_first,
+                   item_count=item_count)
     _check(lib().qubo_plan_info(Qc.ctypes.data, n, dt, ctypes.byref(opt), ctypes.byref(info),
                                 T.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
     d = {f: getattr(info, f) for f, _ in _PlanInfo._fields_}

@@ -48,6 +48,10 @@ void batch_free(qubo_batch *b)
 qubo_status_t batch_build(qubo_batch *b, int count, const void *const *Q, const int *n,
                           const qubo_dtype_t *dtype, const qubo_options_t *opt)
 {
+    if (opt && (opt->item_first || opt->item_count)) {
+        qrt::set_error("item ranges are for single solves");
+        return QUBO_EINVAL;
+    }
     std::vector<qplan::Plan> plans(static_cast<size_t>(count));
     std::string msg;
     qrt::tune_autoload();

@@ -46,14 +46,15 @@ struct Inst {
     int32_t *S;
     int32_t *K;            // this instance's K table (kslot-th table of the K array)
     const float *Qf;
-    ItemRes *res;          // per-item results of this instance, by local item index
+    ItemRes *res;          // this launch's item results: item g of the launch
+                           // (item_begin <= g < item_end) writes res[g - item_begin]
     int n, A, B, L;
     int direct;            // 1: no walk, direct evaluation of all 2^n states
     int kslot;             // index of the K table in the launch's K array
     uint64_t item_begin;   // this launch's walk-item range [item_begin, item_end)
     uint64_t item_end;
-    uint64_t item_local0;  // local index of the instance's item number item_begin
-    uint64_t n_items;      // the instance's total items, 2^(A-L)
+    uint64_t item_local0;  // the instance's own item number of launch item item_begin
+    uint64_t n_items;      // item records the finish reduces (res[0 .. n_items))
     int32_t *gbest;        // best energy any wave has found for the instance
                            // (kNoEnergy from the table build on)
 };

@@ -880,7 +880,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
             r.E = found ? itemE : kNoEnergy;
             r.found = found;
             r.row = found ? itemRow : 0ull;
-            ires[qloc] = r;
+            ires[g - item_begin] = r;
         }
     }
     if constexpr (TIER == 3) tk_flush();

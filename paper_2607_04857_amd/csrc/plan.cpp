@@ -198,6 +198,10 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
     P.direct = n <= kDirectMaxN;
     if (!P.direct && n - B < kSuper) B = n - kSuper;  // the prefix must hold one super-block
     if (P.direct) {
+        if (opt && (opt->item_first || opt->item_count)) {
+            *msg = "item ranges need a walked plan (n > 14)";
+            return QUBO_EINVAL;
+        }
         P.A = 0;
         P.B = 0;
         P.mcols = 0;
@@ -243,6 +247,15 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
     }
     P.L = L;
     P.items = uint64_t(1) << (P.A - L);
+    if (opt && (opt->item_first || opt->item_count)) {
+        if (opt->item_first < 0 || opt->item_count < 1 ||
+            uint64_t(opt->item_first) + uint64_t(opt->item_count) > P.items) {
+            *msg = "item range must satisfy 0 <= item_first, 1 <= item_count, first + count <= items";
+            return QUBO_EINVAL;
+        }
+        P.item_first = uint64_t(opt->item_first);
+        P.item_count = uint64_t(opt->item_count);
+    }
     *out = std::move(P);
     return QUBO_OK;
 }

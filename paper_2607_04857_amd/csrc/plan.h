@@ -35,6 +35,8 @@ struct Plan {
     double eps_q = 0.0;    // per-state quantisation bound (fp32)
     int64_t sum_abs = 0;   // sum |T| over i <= j (of the int32 matrix solved)
     uint64_t items = 0;    // 2^(A - L) walk items (0 when direct)
+    uint64_t item_first = 0, item_count = 0;   // walk only these items (count 0: all)
+    uint64_t walk_items() const { return item_count ? item_count : items; }
     std::vector<int32_t> T;    // folded (and scaled) upper-triangular n x n
 };
 

@@ -170,9 +170,9 @@ qubo_status_t job_layout(Job *job, int waves_per_cu)
         }
         WalkGroup &g = job->groups.back();
         g.count = int(i) + 1 - g.first;
-        g.items += P.items;
+        g.items += P.walk_items();
         if (P.A > job->max_A) job->max_A = P.A;
-        job->total_items += P.items;
+        job->total_items += P.walk_items();
     }
     if (job->topk > 1 && (job->plans.size() != 1 || (!job->groups.empty() && job->groups[0].tier != 3))) {
         set_error("internal: top-k jobs hold one instance planned for tier 3");
@@ -214,7 +214,7 @@ qubo_status_t job_bind(Job *job, void *d_mem)
         uint64_t acc = 0;
         for (int k = g.first; k < g.first + g.count; k++) {
             group_base[size_t(k)] = acc;
-            acc += job->plans[size_t(k)].items;
+            acc += job->plans[size_t(k)].walk_items();
         }
     }
     for (size_t i = 0; i < job->plans.size(); i++) {
@@ -234,10 +234,10 @@ qubo_status_t job_bind(Job *job, void *d_mem)
         I.direct = P.direct ? 1 : 0;
         I.kslot = int(i);
         I.item_begin = group_base[i];
-        I.item_end = group_base[i] + (P.direct ? 0 : P.items);
-        item += P.direct ? 0 : P.items;
-        I.item_local0 = 0;
-        I.n_items = P.direct ? 0 : P.items;
+        I.item_end = group_base[i] + (P.direct ? 0 : P.walk_items());
+        item += P.direct ? 0 : P.walk_items();
+        I.item_local0 = P.item_first;
+        I.n_items = P.direct ? 0 : P.walk_items();
         I.gbest = reinterpret_cast<int32_t *>(base + o.gbest) + i;
         const size_t nn = size_t(P.n) * P.n;
         std::memcpy(job->stage.data() + o.T[i], P.T.data(), nn * sizeof(int32_t));

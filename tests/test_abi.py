@@ -144,3 +144,17 @@ def test_topk_argument_checks_need_no_gpu():
         with pytest.raises(q.QuboError) as ei:
             q.solve(Q, k=k)
         assert ei.value.status == -1
+
+
+def test_item_range_options_validated_on_host():
+    import paper_2607_04857_amd as q
+    Q = inputs.uniform_int(24, -100, 100, 5)
+    info = q.plan_info(Q)
+    ok = q.plan_info(Q, item_first=info["items"] - 2, item_count=2)
+    assert ok["items"] == info["items"]
+    for first, count in [(info["items"] - 1, 2), (-1, 1), (0, -3), (3, 0)]:
+        with pytest.raises(q.QuboError) as ei:
+            q.plan_info(Q, item_first=first, item_count=count)
+        assert ei.value.status == -1
+    with pytest.raises(q.QuboError):
+        q.plan_info(inputs.uniform_int(12, -100, 100, 5), item_first=0, item_count=1)

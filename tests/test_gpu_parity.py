@@ -136,3 +136,46 @@ def test_planted_n44(q, orc, tier):
     print("planted44", got.energy_i, got.index, istar, f"{got.kernel_ms:.1f} ms", flush=True)
     assert got.index == istar
     assert got.energy_i == orc.energy(Q, istar)
+
+
+def test_planted_n48_large(q, orc):
+    """Beyond the headline size: 2^48 states (about 5 s), entries U[-1000, 1000]
+    with a planted unique ground state, and its top-4 head."""
+    Q, xstar = inputs.planted(48, -1000, 1000, 9)
+    istar = orc.index_of(xstar)
+    got = q.solve(Q)
+    print("planted48", got.energy_i, got.index, istar, f"{got.kernel_ms:.1f} ms", flush=True)
+    assert (got.A, got.B) == (38, 10)
+    assert got.index == istar and got.energy_i == orc.energy(Q, istar)
+    res, pairs = q.solve(Q, k=4)
+    assert pairs[0] == (got.energy_i, istar)
+    # planted: E(x) >= E(x*) + Hamming(x, x*), so every other state is at least one higher
+    assert all(e >= got.energy_i + 1 for e, _ in pairs[1:])
+    assert all(e == orc.energy(Q, i) for e, i in pairs)
+    assert pairs == sorted(pairs)
+
+
+def _gray(c):
+    return c ^ (c >> 1)
+
+
+def test_headline_sampled_items(q, orc):
+    """The n = 44 headline instance in its own plan and kernel, checked on
+    sampled work items: item c covers the contiguous index range
+    [g(c) 2^(L+B), (g(c)+1) 2^(L+B)) of 2^24 states, which the oracle
+    evaluates exhaustively."""
+    Q = inputs.uniform_int(44, -10000, 10000, 4)
+    info = q.plan_info(Q)
+    L, B, items = info["L"], info["B"], info["items"]
+    assert (info["A"], B, L, items) == (34, 10, 14, 1 << 20)
+    span = 1 << (L + B)
+    rng = np.random.default_rng(44)
+    firsts = [0, items - 4] + [int(c) for c in rng.integers(0, items - 4, 3)]
+    for c0 in firsts:
+        got = q.solve(Q, item_first=c0, item_count=4)
+        exp = min(orc.solve_range(Q, _gray(c) * span, span, k=1)[0] for c in range(c0, c0 + 4))
+        print(f"items [{c0}, {c0 + 4}): {got.energy_i} @ {got.index} (oracle {exp})", flush=True)
+        assert (got.energy_i, got.index) == exp
+    c0 = firsts[-1]
+    res, pairs = q.solve(Q, k=16, item_first=c0, item_count=1)
+    assert pairs == [(int(e), int(i)) for e, i in orc.solve_range(Q, _gray(c0) * span, span, k=16)]
