@@ -53,6 +53,15 @@ def kernel_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+def kernel_name(r):
+    """Template instance of the walk kernel a plan runs (row cache "4" is
+    G = 6 with the rows of levels 3 and 4 in LDS)."""
+    mc = 2 ** (r.B - 6)
+    if r.vgpr_levels == 4:
+        return "walk_kernel<%d,6,%d,true>" % (mc, r.tier)
+    return "walk_kernel<%d,%d,%d>" % (mc, r.vgpr_levels, r.tier)
+
+
 def traffic_from_profile():
     """HBM bytes per walk launch from the committed PMC summary, if still valid."""
     if not os.path.exists(PMC_FILE):
@@ -241,7 +250,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                      "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS,
                      "traffic": traffic_from_profile(),
-                     "kernel": "walk_kernel<%d,%d,%d>" % (2 ** (r.B - 6), r.vgpr_levels, r.tier),
+                     "kernel": kernel_name(r),
                      "walk_ms": walk_ms},
         "paper_context": {"states_per_s": 7.42e12, "hardware": "NVIDIA H100 80GB",
                           "precision": "int16", "n": 44},

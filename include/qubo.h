@@ -106,10 +106,11 @@ typedef struct {
     int tier;
     int waves_per_cu;
     int vgpr_levels;     /* Gray levels whose M_int rows stay in VGPRs: 0 = default
-                            (6 for B = 10, else 12), 12, 8 (B = 9 or 10), 6 or 5
-                            (B = 10); fewer levels free VGPRs for a third/fourth
-                            wave per SIMD, the higher rows being read from L2
-                            when they flip                                    */
+                            (4 for B = 10, else 12), 12, 8 (B = 9 or 10), 6, 5
+                            or 4 (B = 10); fewer levels free VGPRs for a third
+                            or fourth wave per SIMD, the higher rows being read
+                            from L2 when they flip.  4 keeps levels 0-2 and 5
+                            in VGPRs and levels 3-4 in LDS (8 KB per wave)    */
     int item_first;
     int item_count;
     int reserved;
@@ -194,7 +195,8 @@ void qubo_server_destroy(qubo_server_t *srv);
  * independent `op` instructions (0: v_add_u32, 1: v_min3_i32, 2: v_add_u32
  * with one scalar add per two vector adds, 3: v_add_u32 with one never-taken
  * scalar compare-and-branch per 16 vector adds, 4: v_pk_add_u16, 5:
- * v_pk_min_i16) with waves_per_simd resident waves on every SIMD and reports
+ * v_pk_min_i16, 6: v_add_u32 with a register footprint that admits at most 3
+ * waves per SIMD) with waves_per_simd resident waves on every SIMD and reports
  * vector lane-operations per second (a packed instruction counts once per
  * lane) and the kernel time. */
 qubo_status_t qubo_probe_valu(int op, int waves_per_simd, int iters, double *lane_ops_per_s,

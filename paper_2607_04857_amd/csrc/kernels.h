@@ -140,7 +140,7 @@ int walk_occupancy(int mcols, int vgpr_levels, int tier, int topk_k = 0);
 
 // LDS bytes of one tier-3 wave's list.
 constexpr int kTopkMetaWords = 13;  // 64-bit words of list scalars ahead of the entries
-inline size_t topk_lds_bytes(int k)
+__host__ __device__ inline size_t topk_lds_bytes(int k)
 {
     return size_t(kTopkMetaWords) * 8 + size_t(k) * (sizeof(uint64_t) + sizeof(int32_t));
 }

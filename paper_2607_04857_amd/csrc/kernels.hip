@@ -269,13 +269,26 @@ __device__ __forceinline__ int32_t wave_min_bcast(int32_t v)
 // Resident waves per SIMD each variant is register-allocated for: the full
 // 12-level row cache fits 256 VGPRs (2 waves); the 8-level cache leaves room
 // for a third (MC=16) or a fourth (MC=8) wave.
-template <int MC, int G>
+// LR: the rows of Gray levels 3 and 4 live in LDS (2 x MC x 64 dwords per
+// wave) instead of VGPRs, which leaves room for a fourth wave per SIMD.
+template <int MC, int G, bool LR = false>
 constexpr int walk_waves_per_simd()
 {
-    return G >= 12 ? (MC >= 16 ? 2 : (MC >= 8 ? 3 : 4)) : (G <= 5 ? 4 : (MC >= 16 ? 3 : 4));
+    return LR ? 4 : (G >= 12 ? (MC >= 16 ? 2 : (MC >= 8 ? 3 : 4)) : (G <= 5 ? 4 : (MC >= 16 ? 3 : 4)));
 }
 // (G = 6 and 8 with MC = 16 target 3 waves, G = 5 four; 8 and 5 spill a few
 // values outside the unrolled steps.)
+
+// Bytes of dynamic LDS ahead of the LDS rows (the tier-3 list), 16-aligned.
+__host__ __device__ inline size_t lds_rows_offset(int tier, int k)
+{
+    return tier == 3 ? (topk_lds_bytes(k) + 15) & ~size_t(15) : 0;
+}
+template <int MC>
+constexpr size_t lds_rows_bytes()
+{
+    return size_t(2) * MC * kWave * sizeof(int32_t);
+}
 
 // ---- tier-3 list (top-k).  One wave per workgroup; the list lives in
 // dynamic LDS: kTopkMetaWords 64-bit words of scalars, then k rows and k
@@ -492,8 +505,8 @@ __device__ __noinline__ void tk_flush()
 
 // TIER 3: tier 2's bound test against a top-k threshold instead of the best
 //         energy: the wave keeps the k smallest chunk keys it has met in LDS.
-template <int MC, int G, int TIER>
-__global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_kernel(
+template <int MC, int G, int TIER, bool LR = false>
+__global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void walk_kernel(
     const Inst *__restrict__ insts, int n_inst, uint64_t total_items,
     unsigned long long *__restrict__ counter, const int32_t *__restrict__ kall, TopkWalk tk)
 {
@@ -504,6 +517,9 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
     const uint32_t ulane = threadIdx.x;
     // row v of a lane-major [rows][MC*64] table: uniform base pointer
     auto trow = [](const gint32 *t, int v) { return t + size_t(v) * (MC * kWave); };
+    // LR: rows of levels 3 and 4 after the (tier-3) list in dynamic LDS
+    int32_t *const ldsR = reinterpret_cast<int32_t *>(
+        reinterpret_cast<char *>(tk_lds) + lds_rows_offset(TIER, tk.k));
 
     int cur = -1;
     // the tables, addressed as global memory (uniform base + lane offset +
@@ -516,7 +532,8 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
     int32_t R[G][MC];        // M_int rows of Gray levels 0..G-1 (variable A-1-t)
     int32_t S4 = 0;          // couplings of the level-4 variable, one lane each
     int32_t S4L[kLowLevels];  // couplings of the level-4 variable with the low ones
-    int32_t diagl = 0;       // T[l][l] on lane l < A
+    const int32_t *Tm = nullptr;  // the instance's folded T (the diagonal is
+    int nT = 0;                   // re-read per item rather than held in a VGPR)
     int32_t CR[kPatterns];   // low-low coupling increments per pattern
     int32_t *gbest = nullptr;     // the current instance's shared best
     int32_t best = kNoEnergy;     // tier 3: the current top-k threshold
@@ -553,15 +570,24 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
                 constexpr int t = decltype(tc)::value;
                 const bool have = t < A;
                 const int v = have ? A - 1 - t : 0;
+                if constexpr (LR && (t == 3 || t == 4)) {
+                    // each lane writes and later reads only its own columns
 #pragma unroll
-                for (int j = 0; j < MC; j++) R[t][j] = have ? trow(M, v)[j * kWave + ulane] : 0;
+                    for (int j = 0; j < MC; j++)
+                        ldsR[(t - 3) * (MC * kWave) + j * kWave + lane] =
+                            have ? trow(M, v)[j * kWave + ulane] : 0;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < MC; j++) R[t][j] = have ? trow(M, v)[j * kWave + ulane] : 0;
+                }
             });
             S4 = S[size_t(A - 5) * kWave + ulane];
             static_for<0, kLowLevels>([&](auto tc) {
                 constexpr int t = decltype(tc)::value;
                 S4L[t] = kall[kbase + kKBound + (A - 5) * 4 + t];
             });
-            diagl = lane < A ? I.T[lane * I.n + lane] : 0;
+            Tm = I.T;
+            nT = I.n;
             // Sll(t,u): coupling of the low variables A-1-t and A-1-u
             int32_t Sll[kLowLevels][kLowLevels];
             static_for<0, kLowLevels>([&](auto tc) {
@@ -621,6 +647,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
         }
         // F: field of every prefix variable from the non-low ones (levels >= 4,
         // variables 0..A-5), plus its diagonal; one lane per variable.
+        const int32_t diagl = lane < A ? Tm[lane * nT + lane] : 0;   // T[l][l], lane l < A
         int32_t F = diagl;
         for (int w = 0; w <= A - 5; w++)
             if ((row0 >> (A - 1 - w)) & 1) F += S[size_t(w) * kWave + ulane];
@@ -743,19 +770,30 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
         auto low_flip = [&](auto tc, auto upc) {
             constexpr int t = decltype(tc)::value;
             constexpr bool up = decltype(upc)::value;
+            if constexpr (LR && t == 3) {
 #pragma unroll
-            for (int j = 0; j < MC; j++) E[j] = up ? E[j] + R[t][j] : E[j] - R[t][j];
+                for (int j = 0; j < MC; j++) {
+                    const int32_t r = ldsR[j * kWave + lane];
+                    E[j] = up ? E[j] + r : E[j] - r;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < MC; j++) E[j] = up ? E[j] + R[t][j] : E[j] - R[t][j];
+            }
             pin_vec<MC>(E);
         };
         // Level-4 flip in the middle of super-block sb.
         auto middle_flip = [&](uint64_t sb) {
             const bool up = (sb & 1) == 0;
+            int32_t R4[MC];
+#pragma unroll
+            for (int j = 0; j < MC; j++) R4[j] = LR ? ldsR[(MC * kWave) + j * kWave + lane] : R[4][j];
             if (up) {
 #pragma unroll
-                for (int j = 0; j < MC; j++) E[j] += R[4][j];
+                for (int j = 0; j < MC; j++) E[j] += R4[j];
             } else {
 #pragma unroll
-                for (int j = 0; j < MC; j++) E[j] -= R[4][j];
+                for (int j = 0; j < MC; j++) E[j] -= R4[j];
             }
             pin_vec<MC>(E);
             nonlow_flip(A - 5, up, S4, S4L);
@@ -782,10 +820,22 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G>())) void walk_ke
                 }
             });
             if (!done) {
+                // row from L2; the direction is wave-uniform, so branch on it
+                // rather than select +-r per element
+                // in halves of up to 8 columns: fewer registers in flight
+                constexpr int HC = MC > 8 ? 8 : MC;
 #pragma unroll
-                for (int j = 0; j < MC; j++) {
-                    const int32_t r = trow(M, w)[j * kWave + ulane];
-                    E[j] = up ? E[j] + r : E[j] - r;
+                for (int j0 = 0; j0 < MC; j0 += HC) {
+                    int32_t r[HC];
+#pragma unroll
+                    for (int j = 0; j < HC; j++) r[j] = trow(M, w)[(j0 + j) * kWave + ulane];
+                    if (up) {
+#pragma unroll
+                        for (int j = 0; j < HC; j++) E[j0 + j] += r[j];
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < HC; j++) E[j0 + j] -= r[j];
+                    }
                 }
             }
             pin_vec<MC>(E);
@@ -973,57 +1023,69 @@ hipError_t launch_tables(const Inst *d_insts, int n_inst, int max_A, unsigned lo
     return hipGetLastError();
 }
 
-template <int MC, int G>
+template <int MC, int G, bool LR = false>
+static size_t walk_lds_bytes(int tier, int k)
+{
+    return lds_rows_offset(tier, k) + (LR ? lds_rows_bytes<MC>() : 0);
+}
+
+template <int MC, int G, bool LR = false>
 static hipError_t launch_walk_g(int tier, const Inst *d_insts, int n_inst, uint64_t total_items,
                                 unsigned long long *d_counter, const int32_t *d_k, int waves,
                                 hipStream_t stream, const TopkWalk *tk)
 {
     TopkWalk none{};
     if (tier == 1) {
-        hipLaunchKernelGGL((walk_kernel<MC, G, 1>), dim3(waves), dim3(kWave), 0, stream, d_insts,
-                           n_inst, total_items, d_counter, d_k, none);
+        hipLaunchKernelGGL((walk_kernel<MC, G, 1, LR>), dim3(waves), dim3(kWave),
+                           (walk_lds_bytes<MC, G, LR>(1, 0)), stream, d_insts, n_inst, total_items,
+                           d_counter, d_k, none);
     } else if (tier == 2) {
-        hipLaunchKernelGGL((walk_kernel<MC, G, 2>), dim3(waves), dim3(kWave), 0, stream, d_insts,
-                           n_inst, total_items, d_counter, d_k, none);
+        hipLaunchKernelGGL((walk_kernel<MC, G, 2, LR>), dim3(waves), dim3(kWave),
+                           (walk_lds_bytes<MC, G, LR>(2, 0)), stream, d_insts, n_inst, total_items,
+                           d_counter, d_k, none);
     } else if (tier == 3) {
         if (!tk || tk->k < 2 || n_inst != 1) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((walk_kernel<MC, G, 3>), dim3(waves), dim3(kWave),
-                           topk_lds_bytes(tk->k), stream, d_insts, n_inst, total_items, d_counter,
-                           d_k, *tk);
+        hipLaunchKernelGGL((walk_kernel<MC, G, 3, LR>), dim3(waves), dim3(kWave),
+                           (walk_lds_bytes<MC, G, LR>(3, tk->k)), stream, d_insts, n_inst,
+                           total_items, d_counter, d_k, *tk);
     } else {
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <int MC, int G>
+template <int MC, int G, bool LR = false>
 static int occupancy_g(int tier, int topk_k)
 {
     int blocks = 0;
     hipError_t e;
     if (tier == 3)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, G, 3>, kWave,
-                                                         topk_lds_bytes(topk_k));
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, G, 3, LR>, kWave,
+                                                         walk_lds_bytes<MC, G, LR>(3, topk_k));
     else if (tier == 2)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, G, 2>, kWave, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, G, 2, LR>, kWave,
+                                                         walk_lds_bytes<MC, G, LR>(2, 0));
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, G, 1>, kWave, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, G, 1, LR>, kWave,
+                                                         walk_lds_bytes<MC, G, LR>(1, 0));
     if (e != hipSuccess || blocks < 1) return 1;
     return blocks;
 }
 
 // Variants built: every MC with G = 12; MC = 8 and 16 with G = 8; MC = 16
-// with G = 6 and 5.
+// with G = 6 and 5, and "4": G = 6 with levels 3 and 4 in LDS (levels 0-2
+// and 5 in VGPRs, four waves per SIMD).
 bool walk_variant_exists(int mcols, int vgpr_levels)
 {
     if (vgpr_levels == 12) return mcols == 1 || mcols == 2 || mcols == 4 || mcols == 8 || mcols == 16;
     if (vgpr_levels == 8) return mcols == 8 || mcols == 16;
-    if (vgpr_levels == 6 || vgpr_levels == 5) return mcols == 16;
+    if (vgpr_levels == 6 || vgpr_levels == 5 || vgpr_levels == 4) return mcols == 16;
     return false;
 }
 
 int walk_occupancy(int mcols, int vgpr_levels, int tier, int topk_k)
 {
+    if (vgpr_levels == 4) return occupancy_g<16, 6, true>(tier, topk_k);
     if (vgpr_levels == 5) return occupancy_g<16, 5>(tier, topk_k);
     if (vgpr_levels == 6) return occupancy_g<16, 6>(tier, topk_k);
     if (vgpr_levels == 8)
@@ -1042,8 +1104,9 @@ hipError_t launch_walk(int mcols, int vgpr_levels, int tier, const Inst *d_insts
                        int waves, hipStream_t stream, const TopkWalk *tk)
 {
 #define QK_ARGS tier, d_insts, n_inst, total_items, d_counter, d_k, waves, stream, tk
-    if (vgpr_levels == 6 || vgpr_levels == 5) {
+    if (vgpr_levels == 6 || vgpr_levels == 5 || vgpr_levels == 4) {
         if (mcols != 16) return hipErrorInvalidValue;
+        if (vgpr_levels == 4) return launch_walk_g<16, 6, true>(QK_ARGS);
         return vgpr_levels == 6 ? launch_walk_g<16, 6>(QK_ARGS) : launch_walk_g<16, 5>(QK_ARGS);
     }
     if (vgpr_levels == 8) {

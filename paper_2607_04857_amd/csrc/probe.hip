@@ -5,8 +5,11 @@
 // grid places waves_per_simd waves on every SIMD of the device.  Ops: 0
 // v_add_u32; 1 v_min3_i32; 2 v_add_u32 with one s_add_i32 per two vector adds;
 // 3 v_add_u32 with one never-taken s_cmp/s_cbranch per 16 vector adds; 4
-// v_pk_add_u16; 5 v_pk_min_i16.  Vector instructions x 64 lanes are counted
-// (a packed instruction is one lane-operation on two 16-bit halves).
+// v_pk_add_u16; 5 v_pk_min_i16; 6 v_add_u32 over 160 accumulators, whose
+// register footprint admits at most 3 waves per SIMD (the walk's occupancy:
+// with few registers the dispatcher may place 4 waves on some SIMDs and 2 on
+// others when 3 per SIMD are launched).  Vector instructions x 64 lanes are
+// counted (a packed instruction is one lane-operation on two 16-bit halves).
 #include <hip/hip_runtime.h>
 
 #include "runtime.h"
@@ -16,16 +19,19 @@ namespace {
 template <int OP>
 __global__ __launch_bounds__(64) void valu_probe_kernel(int iters, int32_t *__restrict__ out)
 {
-    int32_t a[16];
+    // accumulators; 256 vector instructions per iteration either way
+    constexpr int NA = OP == 6 ? 160 : 16;
+    constexpr int NR = OP == 6 ? 1 : 16;
+    int32_t a[NA];
 #pragma unroll
-    for (int k = 0; k < 16; k++) a[k] = int32_t(threadIdx.x) * 7 + k;
+    for (int k = 0; k < NA; k++) a[k] = int32_t(threadIdx.x) * 7 + k;
     const int32_t b = int32_t(blockIdx.x) | 1, c = int32_t(threadIdx.x) ^ 5;
     int32_t sc = int32_t(blockIdx.x);   // scalar work for OP 2 and 3 (wave-uniform)
     for (int it = 0; it < iters; it++) {
 #pragma unroll
-        for (int r = 0; r < 16; r++) {
+        for (int r = 0; r < NR; r++) {
 #pragma unroll
-            for (int k = 0; k < 16; k++) {
+            for (int k = 0; k < (OP == 6 ? 256 : 16); k++) {
                 if constexpr (OP == 1)
                     asm volatile("v_min3_i32 %0, %0, %1, %2" : "+v"(a[k]) : "v"(b), "v"(c));
                 else if constexpr (OP == 4)
@@ -33,7 +39,7 @@ __global__ __launch_bounds__(64) void valu_probe_kernel(int iters, int32_t *__re
                 else if constexpr (OP == 5)
                     asm volatile("v_pk_min_i16 %0, %0, %1" : "+v"(a[k]) : "v"(b));
                 else
-                    asm volatile("v_add_u32 %0, %1, %0" : "+v"(a[k]) : "v"(b));
+                    asm volatile("v_add_u32 %0, %1, %0" : "+v"(a[k % NA]) : "v"(b));
                 if constexpr (OP == 2)   // one scalar add per two vector adds
                     if (k % 2 == 1) asm volatile("s_add_i32 %0, %0, 3" : "+s"(sc) : : "scc");
             }
@@ -44,7 +50,7 @@ __global__ __launch_bounds__(64) void valu_probe_kernel(int iters, int32_t *__re
     if constexpr (OP == 2) a[0] ^= sc;
     int32_t x = 0;
 #pragma unroll
-    for (int k = 0; k < 16; k++) x ^= a[k];
+    for (int k = 0; k < NA; k++) x ^= a[k];
     out[blockIdx.x * 64 + threadIdx.x] = x;
 }
 
@@ -54,7 +60,7 @@ extern "C" qubo_status_t qubo_probe_valu(int op, int waves_per_simd, int iters,
                                          double *lane_ops_per_s, double *ms)
 {
     qrt::set_error("");
-    if (op < 0 || op > 5 || waves_per_simd < 1 || waves_per_simd > 8 || iters < 1) {
+    if (op < 0 || op > 6 || waves_per_simd < 1 || waves_per_simd > 8 || iters < 1) {
         qrt::set_error("bad probe arguments");
         return QUBO_EINVAL;
     }
@@ -87,8 +93,10 @@ extern "C" qubo_status_t qubo_probe_valu(int op, int waves_per_simd, int iters,
                 hipLaunchKernelGGL(valu_probe_kernel<3>, dim3(blocks), dim3(64), 0, s, iters, d_out);
             else if (op == 4)
                 hipLaunchKernelGGL(valu_probe_kernel<4>, dim3(blocks), dim3(64), 0, s, iters, d_out);
-            else
+            else if (op == 5)
                 hipLaunchKernelGGL(valu_probe_kernel<5>, dim3(blocks), dim3(64), 0, s, iters, d_out);
+            else
+                hipLaunchKernelGGL(valu_probe_kernel<6>, dim3(blocks), dim3(64), 0, s, iters, d_out);
             (void)hipEventRecord(e1, s);
         }
         if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess ||

@@ -11,8 +11,9 @@ from paper_2607_04857_amd import inputs
 pytestmark = pytest.mark.gpu
 
 # (B, vgpr_levels, tier): every built walk variant in both tiers, cycled over n
-VARIANTS = [(10, 6, 2), (10, 5, 1), (9, 8, 2), (8, 12, 1), (10, 8, 2), (7, 12, 2),
-            (10, 12, 1), (6, 12, 2), (9, 12, 1), (10, 6, 1), (10, 5, 2), (9, 8, 1)]
+VARIANTS = [(10, 4, 2), (10, 5, 1), (9, 8, 2), (8, 12, 1), (10, 8, 2), (7, 12, 2),
+            (10, 12, 1), (6, 12, 2), (9, 12, 1), (10, 6, 1), (10, 5, 2), (9, 8, 1),
+            (10, 4, 1), (10, 6, 2)]
 
 
 @pytest.fixture()

@@ -23,7 +23,7 @@ def _plan(q, n, **kw):
 
 def test_empty_table_gives_defaults(q):
     d = _plan(q, 30)
-    assert (d["B"], d["vgpr_levels"], d["tier"]) == (10, 6, 2)
+    assert (d["B"], d["vgpr_levels"], d["tier"]) == (10, 4, 2)
     assert q.tune_lookup(30) is None
 
 
