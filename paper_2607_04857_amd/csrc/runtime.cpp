@@ -468,7 +468,15 @@ qubo_status_t solve_host(const void *Q, int n, qubo_dtype_t dtype, int k, const 
     if (k > 1) {
         // the top-k walk keeps candidate lists (tier 3); the finish selects
         job.topk = k;
-        if (!job.plans[0].direct) job.plans[0].tier = 3;
+        qplan::Plan &P = job.plans[0];
+        if (!P.direct) {
+            P.tier = 3;
+            // The LDS row cache shares LDS with the list: when both no longer
+            // fit four waves per SIMD, the VGPR row cache (three waves) wins.
+            if (P.vgpr_levels == 4 && !(opt && opt->vgpr_levels) &&
+                qk::walk_occupancy(P.mcols, 4, 3, k) < 4 * 4)
+                P.vgpr_levels = 6;
+        }
     }
     st = solve_planned(job, stream, opt ? opt->waves_per_cu : 0, out, topk);
     if (st == QUBO_OK && k == 1 && topk) topk[0] = out->best;
