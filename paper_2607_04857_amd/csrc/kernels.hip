@@ -616,10 +616,11 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
             if constexpr (TIER != 3) gbest = I.gbest;
         }
 
-        // Best energy found by any wave for this instance: a chunk can
-        // improve the final answer only if its key is at most that.  (A
-        // chunk tying it with an unknown row is still recorded: bestRow
-        // restarts at the largest row whenever the shared value lowers best.)
+        // Best energy found by any wave for this instance (published at the
+        // end of each item): a chunk can improve the final answer only if its
+        // key is at most that.  (A chunk tying it with an unknown row is still
+        // recorded: bestRow restarts at the largest row whenever the shared
+        // value lowers best.)
         if constexpr (TIER != 3) {
             const int32_t g0 = sread(__hip_atomic_load(gbest, __ATOMIC_RELAXED,
                                                        __HIP_MEMORY_SCOPE_AGENT));
@@ -740,7 +741,6 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                     itemE = Ec;
                     itemRow = rc;
                     found = 1;
-                    if (lane == 0) atomicMin(gbest, Ec);
                     static_for<0, kPatterns>([&](auto pc) {
                         constexpr int p = decltype(pc)::value;
                         if constexpr (TIER == 1) THR[p] += d;
@@ -931,6 +931,9 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
             r.found = found;
             r.row = found ? itemRow : 0ull;
             ires[g - item_begin] = r;
+            // publish once per item: every wave starting an item of this
+            // instance at once would otherwise contend on one address
+            if (found) atomicMin(gbest, itemE);
         }
     }
     if constexpr (TIER == 3) tk_flush();

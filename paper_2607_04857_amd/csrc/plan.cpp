@@ -230,7 +230,9 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
     // per-item set-up, about A*MC adds plus the prefix fields, stays below
     // 0.3% of the item), the whole prefix range when it is smaller, and never
     // more than 2^20 items per instance.  A lone instance instead keeps at
-    // least 2^11 items (one per resident wavefront) down to 2^9-step items.
+    // least 2^13 items (two per resident wavefront) down to 2^9-step items,
+    // and at most 2^18 (longer items where there are plenty: fewer item
+    // records and set-ups; the autotuner measured this at n = 43 and 44).
     int L;
     if (opt && opt->L) {
         L = opt->L;
@@ -242,7 +244,8 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
         L = tuned.L;
     } else {
         L = P.A < 14 ? P.A : 14;
-        if (!many && P.A - L < 11) L = P.A - 11 < 9 ? 9 : P.A - 11;
+        if (!many && P.A - L < 13) L = P.A - 13 < 9 ? 9 : P.A - 13;
+        if (!many && P.A - L > 18) L = P.A - 18;
         if (L > P.A) L = P.A;
         if (P.A - L > 20) L = P.A - 20;
     }
