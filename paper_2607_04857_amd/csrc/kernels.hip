@@ -12,8 +12,11 @@
 //  * one wavefront owns all 2^B columns of its chunk: lane l holds columns
 //    s = j*64 + l (j < MC), i.e. E_sd lives in MC VGPRs per lane (column-wise
 //    split, Sec. III-C.2, at lane granularity);
-//  * the twelve most frequently flipped rows M_int[k] (Gray levels 0..11) sit
-//    in VGPRs; higher levels flip once per 4096 steps and are read from L2;
+//  * the rows M_int[k] of the most frequently flipped Gray levels stay on
+//    chip: by default levels 0-2 and 5 in VGPRs and 3-4 in LDS (8 KB per
+//    wave), which fits 128 VGPRs and so four waves per SIMD; other variants
+//    keep 5, 6, 8 or 12 levels in VGPRs; higher levels are read from L2 when
+//    they flip (level 6 once per 128 steps);
 //  * wavefronts take work items (2^L consecutive Gray steps of the prefix,
 //    the "straightforward" split of Sec. III-C.1 along the Gray index) from an
 //    atomic counter; the grid is persistent;
@@ -21,11 +24,14 @@
 //    over 32-step super-blocks in which the four lowest Gray levels follow a
 //    static pattern, so E_p of each of the 16 low patterns is tabulated in
 //    SGPRs and refreshed only when a higher prefix bit flips;
-//  * the per-state test "min over the chunk + E_p <= best" is a v_min3 tree
-//    per lane and one compare against an SGPR threshold; the rare hit is
-//    resolved with a DPP wave minimum.  Ties resolve to the lowest prefix row
-//    here and to the lowest suffix in the final rescan, giving the lowest
-//    U_N index overall.
+//  * the candidate test "min over the chunk + E_p <= best" is, by default
+//    (tier 2), a lower bound from one DPP wave minimum per super-block and a
+//    per-offset table, tested against a cheap upper bound of the thresholds
+//    once per 16 steps; exact per-step tests run only when that passes (tier
+//    1 does the exact v_min3 test at every step).  Each step still updates
+//    the chunk vector once (pinned, so the compiler cannot fold flips).  Ties
+//    resolve to the lowest prefix row here and to the lowest suffix in the
+//    final rescan, giving the lowest U_N index overall.
 #include <type_traits>
 #include <utility>
 
@@ -264,11 +270,12 @@ __device__ __forceinline__ int32_t wave_min_bcast(int32_t v)
 //         every Gray step.
 // TIER 2: an exact wave minimum W0 is taken once per 32-step super-block;
 //         at offset o the chunk minimum is at least W0 + D(o) (table K), so
-//         the step needs only the scalar test W0 <= THR - D(o); the exact
-//         minimum is formed only when that test passes.
+//         step o needs only the scalar test W0 <= THR - D(o); each 16-step
+//         half first tests W0 against an upper bound of its 16 thresholds, and
+//         builds and tests the exact ones only when that passes.
 // Resident waves per SIMD each variant is register-allocated for: the full
-// 12-level row cache fits 256 VGPRs (2 waves); the 8-level cache leaves room
-// for a third (MC=16) or a fourth (MC=8) wave.
+// 12-level row cache fits 256 VGPRs (2 waves); the 8- and 6-level caches
+// leave room for a third (MC=16) or a fourth (MC=8) wave.
 // LR: the rows of Gray levels 3 and 4 live in LDS (2 x MC x 64 dwords per
 // wave) instead of VGPRs, which leaves room for a fourth wave per SIMD.
 template <int MC, int G, bool LR = false>
