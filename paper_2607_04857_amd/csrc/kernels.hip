@@ -201,7 +201,11 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
     //   E_sd(o) - E_sd(0) = sum_{t<4} p_t(o) M[A-1-t] + [o >= 16] c4 M[A-5].
     // D = its minimum over all 2^B columns, a lower bound of how far the
     // chunk minimum can fall from its value at the super-block start.
-    __shared__ int32_t red[256];
+    // All 48 (table, offset) minima at once: per-thread minima over the
+    // thread's columns, wave minima by shuffles, one exchange through LDS.
+    constexpr int NQ = 3 * kPatterns;
+    __shared__ int32_t red[256 / kWave][NQ];
+    __shared__ int32_t c2s[NQ];
     int32_t mcol[4][5];   // M rows of levels 0..4 at this thread's columns
     for (int k = 0; k < 4; k++) {
         const uint32_t col = threadIdx.x + 256u * uint32_t(k);
@@ -213,40 +217,46 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
             mcol[k][t] = m;
         }
     }
-    for (int tab = 0; tab < 3; tab++) {
+    const int wl = int(threadIdx.x) % kWave, wv = int(threadIdx.x) / kWave;
+    for (int q = 0; q < NQ; q++) {
+        const int tab = q / kPatterns, o16 = q % kPatterns;
         const int c4 = tab == 0 ? 0 : (tab == 1 ? 1 : -1);
-        int32_t c2min = INT32_MAX;   // (thread 0)
-        for (int o16 = 0; o16 < kPatterns; o16++) {
-            const int o = tab == 0 ? o16 : kPatterns + o16;
-            const int pat = (o ^ (o >> 1)) & (kPatterns - 1);
-            int32_t mn = INT32_MAX;
-            for (int k = 0; k < 4; k++) {
-                if (threadIdx.x + 256u * uint32_t(k) >= NS) continue;
-                int32_t v = c4 * mcol[k][4];
-                for (int t = 0; t < 4; t++)
-                    if ((pat >> t) & 1) v += mcol[k][t];
-                mn = min(mn, v);
-            }
-            red[threadIdx.x] = mn;
-            __syncthreads();
-            for (int off = 128; off > 0; off >>= 1) {
-                if (int(threadIdx.x) < off) red[threadIdx.x] = min(red[threadIdx.x], red[threadIdx.x + off]);
-                __syncthreads();
-            }
-            if (threadIdx.x == 0) {
-                int32_t elow = 0;   // couplings among the set low variables
-                for (int t = 0; t < 4; t++)
-                    for (int u = t + 1; u < 4; u++)
-                        if (((pat >> t) & 1) && ((pat >> u) & 1)) elow += T[(A - 1 - u) * n + (A - 1 - t)];
-                I.K[(3 + tab) * kPatterns + o16] = red[0];
-                I.K[tab * kPatterns + o16] = elow + red[0];
-                c2min = min(c2min, elow + red[0]);
-            }
-            __syncthreads();
+        const int o = tab == 0 ? o16 : kPatterns + o16;
+        const int pat = (o ^ (o >> 1)) & (kPatterns - 1);
+        int32_t mn = INT32_MAX;
+        for (int k = 0; k < 4; k++) {
+            if (threadIdx.x + 256u * uint32_t(k) >= NS) continue;
+            int32_t v = c4 * mcol[k][4];
+            for (int t = 0; t < 4; t++)
+                if ((pat >> t) & 1) v += mcol[k][t];
+            mn = min(mn, v);
         }
-        if (threadIdx.x == 0) I.K[kKC2Min + tab] = c2min;
+#pragma unroll
+        for (int off = kWave / 2; off >= 1; off >>= 1) mn = min(mn, __shfl_xor(mn, off, kWave));
+        if (wl == 0) red[wv][q] = mn;
     }
-    if (threadIdx.x == 0) I.K[kKC2Min + 3] = 0;
+    __syncthreads();
+    if (int(threadIdx.x) < NQ) {
+        const int q = int(threadIdx.x), tab = q / kPatterns, o16 = q % kPatterns;
+        const int o = tab == 0 ? o16 : kPatterns + o16;
+        const int pat = (o ^ (o >> 1)) & (kPatterns - 1);
+        int32_t d = red[0][q];
+        for (int w = 1; w < 256 / kWave; w++) d = min(d, red[w][q]);
+        int32_t elow = 0;   // couplings among the set low variables
+        for (int t = 0; t < 4; t++)
+            for (int u = t + 1; u < 4; u++)
+                if (((pat >> t) & 1) && ((pat >> u) & 1)) elow += T[(A - 1 - u) * n + (A - 1 - t)];
+        I.K[(3 + tab) * kPatterns + o16] = d;
+        I.K[tab * kPatterns + o16] = elow + d;
+        c2s[q] = elow + d;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        int32_t m = INT32_MAX;
+        for (int o16 = 0; o16 < kPatterns; o16++) m = min(m, c2s[threadIdx.x * kPatterns + o16]);
+        I.K[kKC2Min + threadIdx.x] = m;
+    }
+    if (threadIdx.x == 3) I.K[kKC2Min + 3] = 0;
 }
 
 // ---------------------------------------------------------------- walk
