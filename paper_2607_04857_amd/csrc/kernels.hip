@@ -162,14 +162,28 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
     const uint32_t stride = gridDim.x * blockDim.x;
     const int32_t *T = I.T;
     // M_int[v][s] = sum over the set suffix bits t of s of T[v][A + t]
-    // (Sec. II-C; bit t of the suffix row is (s >> (B-1-t)) & 1).
+    // (Sec. II-C; bit t of the suffix row is (s >> (B-1-t)) & 1), as the sum
+    // of two partial sums built first in LDS: part[v][s & 31] over the five
+    // lowest bits of s and part[v][32 + (s >> 5)] over the others.
+    __shared__ int32_t part[kMaxPrefixRows][64];
+    for (uint32_t e = threadIdx.x; e < uint32_t(A) * 64u; e += blockDim.x) {
+        const int v = int(e / 64u), x = int(e % 64u);
+        int32_t acc = 0;
+        if (x < 32) {
+            for (int u = 0; u < 5; u++)
+                if ((x >> u) & 1) acc += T[v * n + A + B - 1 - u];
+        } else {
+            const int hi = x - 32;
+            for (int u = 0; u < B - 5; u++)
+                if ((hi >> u) & 1) acc += T[v * n + A + B - 6 - u];
+        }
+        part[v][x] = acc;
+    }
+    __syncthreads();
     for (uint32_t e = tid; e < uint32_t(A) * NS; e += stride) {
         const int v = int(e >> B);
         const uint32_t s = e & (NS - 1);
-        int32_t acc = 0;
-        for (int t = 0; t < B; t++)
-            if ((s >> (B - 1 - t)) & 1u) acc += T[v * n + A + t];
-        I.M[e] = acc;
+        I.M[e] = part[v][s & 31u] + part[v][32u + (s >> 5)];
     }
     // E_s(U_B)[s] = sum_{t <= u, both set} T[A+t][A+u] (Sec. III-A, step 2)
     for (uint32_t s = tid; s < NS; s += stride) {
@@ -1035,9 +1049,11 @@ __global__ __launch_bounds__(256) void finish_kernel(const Inst *__restrict__ in
 hipError_t launch_tables(const Inst *d_insts, int n_inst, int max_A, unsigned long long *d_counters,
                          int n_counters, hipStream_t stream)
 {
-    int bx = (max_A * 1024 + 255) / 256;
+    // a few blocks per instance: each builds the partial sums it needs, so
+    // more blocks mostly add scheduling work (4096-instance batches)
+    int bx = (max_A * 1024 + 4095) / 4096;
     if (bx < 1) bx = 1;
-    if (bx > 64) bx = 64;
+    if (bx > 8) bx = 8;
     hipLaunchKernelGGL(tables_kernel, dim3(bx, n_inst), dim3(256), 0, stream, d_insts, d_counters,
                        n_counters);
     return hipGetLastError();

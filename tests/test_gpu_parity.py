@@ -179,3 +179,28 @@ def test_headline_sampled_items(q, orc):
     c0 = firsts[-1]
     res, pairs = q.solve(Q, k=16, item_first=c0, item_count=1)
     assert pairs == [(int(e), int(i)) for e, i in orc.solve_range(Q, _gray(c0) * span, span, k=16)]
+
+
+def test_algebraic_invariances(q, orc):
+    """End to end through the walk (n = 26): relabelling the variables
+    permutes the argmin, E(cQ) = c E(Q) for an integer c > 0, and the
+    maximum of E(Q) is minus the minimum of E(-Q) (checked by the oracle)."""
+    n = 26
+    Q = inputs.uniform_int(n, -1000, 1000, 2600)
+    base = q.solve(Q)
+    assert (base.energy_i, base.index) == orc.solve(Q, k=1)[0]
+    x = np.array([(base.index >> (n - 1 - i)) & 1 for i in range(n)])
+    perm = np.random.default_rng(26).permutation(n)
+    Qp = np.ascontiguousarray(Q[np.ix_(perm, perm)])          # variable i' = perm[i]
+    rp = q.solve(Qp)
+    xp = np.array([(rp.index >> (n - 1 - i)) & 1 for i in range(n)])
+    assert rp.energy_i == base.energy_i
+    assert orc.energy(Q, orc.index_of(xp[np.argsort(perm)])) == base.energy_i
+    if len({e for e, _ in orc.solve(Q, k=2)}) == 2:                # unique minimum
+        assert np.array_equal(xp, x[perm])
+    r3 = q.solve(3 * Q)
+    assert (r3.energy_i, r3.index) == (3 * base.energy_i, base.index)
+    rneg = q.solve(-Q)
+    worst = orc.solve(-Q, k=1)[0]
+    assert (rneg.energy_i, rneg.index) == worst
+    assert orc.energy(Q, rneg.index) == -rneg.energy_i
