@@ -147,6 +147,58 @@ __device__ __forceinline__ void lexmin(int64_t &bE, uint64_t &bI, int64_t e, uin
 
 // ---------------------------------------------------------------- tables
 
+// Greedy single-flip descent from two starts per wave (the all-zero state
+// for wave 0's first start, hashed states otherwise), lowering the
+// instance's shared best to the energy of the local minima found.  Any
+// state's energy is a valid threshold for the walk (the state's own chunk
+// still passes it), and a local minimum of a dense QUBO is usually close to
+// the global one, so walk waves start with a near-final threshold.  Lane l
+// holds variable l (n <= 60 < 64) and its field f_l = T_ll + sum of the
+// couplings with the set variables: flipping l changes E by +-f_l.
+__device__ void seed_best(const Inst &I, int wave)
+{
+    const int n = I.n, lane = int(threadIdx.x) % kWave;
+    const int32_t *T = I.T;
+    int32_t bestE = kNoEnergy;
+    for (int rep = 0; rep < 2; rep++) {
+        const uint32_t start = uint32_t(wave) * 2u + uint32_t(rep);
+        uint32_t h = start * 0x9E3779B9u + uint32_t(lane) * 0x85EBCA6Bu;
+        h ^= h >> 15;
+        h *= 0xC2B2AE35u;
+        h ^= h >> 13;
+        int x = (start != 0 && lane < n) ? int(h & 1u) : 0;
+        uint64_t xm = __builtin_amdgcn_ballot_w64(x != 0);
+        int32_t f = 0, own = 0;   // field; sum of row l over the set j >= l
+        if (lane < n) {
+            f = T[lane * n + lane];
+            own = x ? T[lane * n + lane] : 0;
+            for (int j = 0; j < n; j++) {
+                if (j == lane || !((xm >> j) & 1)) continue;
+                const int32_t c = j < lane ? T[j * n + lane] : T[lane * n + j];
+                f += c;
+                if (x && j > lane) own += c;
+            }
+        }
+        int32_t E = int32_t(wave_sum64(own));
+        for (int it = 0; it < 4 * n; it++) {
+            const int32_t gain = lane < n ? (x ? -f : f) : INT32_MAX;
+            // smallest gain, lowest lane on ties
+            int64_t key = int64_t(gain) * 256 + lane;
+#pragma unroll
+            for (int off = kWave / 2; off >= 1; off >>= 1) key = min(key, __shfl_xor(key, off, kWave));
+            const int32_t g = int32_t(key >> 8);
+            if (g >= 0) break;
+            const int k = int(key & 0xFF);
+            const int32_t sgn = __shfl(x, k, kWave) ? -1 : 1;   // 1 -> 0 subtracts couplings
+            E += g;
+            if (lane == k) x ^= 1;
+            else if (lane < n) f += sgn * (k < lane ? T[k * n + lane] : T[lane * n + k]);
+        }
+        bestE = min(bestE, E);
+    }
+    if (lane == 0) atomicMin(I.gbest, bestE);
+}
+
 __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ insts,
                                                      unsigned long long *__restrict__ counters,
                                                      int n_counters)
@@ -154,7 +206,10 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
     const Inst I = insts[blockIdx.y];
     if (blockIdx.x == 0 && blockIdx.y == 0)
         for (int c = int(threadIdx.x); c < n_counters; c += int(blockDim.x)) counters[c] = 0ull;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && I.gbest) *I.gbest = kNoEnergy;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && I.gbest) {
+        atomicExch(I.gbest, kNoEnergy);
+        __threadfence();
+    }
     if (I.direct) return;
     const int n = I.n, A = I.A, B = I.B;
     const uint32_t NS = 1u << B;
@@ -203,6 +258,11 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
         I.S[e] = v;
     }
     if (blockIdx.x != 0) return;
+    __syncthreads();
+    // (only when the walk covers every state: a restricted item range must
+    // not start from an energy found outside it)
+    if (I.gbest && I.item_local0 == 0 && I.n_items == (uint64_t(1) << (A - I.L)))
+        seed_best(I, int(threadIdx.x) / kWave);
     for (uint32_t e = threadIdx.x; e < uint32_t(A) * 4u; e += blockDim.x) {
         const int w = int(e / 4), t = int(e % 4), l = A - 1 - t;
         int32_t v = 0;
