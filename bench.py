@@ -19,7 +19,8 @@ roofline         = the walk kernel (dominant kernel) against the int32 VALU
 cpu_baseline     = the CPU oracle (direct evaluation) timed on this host over a
                    bounded contiguous index range of the same instance.
 batched          = 4096 instances, n ~ U{20..34}, int32 U[-100,100] (seed 5):
-                   aggregate states/s of one graph replay.
+                   aggregate states/s of one graph replay; batched_fp32 the
+                   same with float32 N(0,1) entries (seed 6).
 topk             = the k = 1024 lowest-energy states of a dense n = 40 int32
                    instance (U[-10000,10000], seed 3): walk (tier 3) and
                    end-to-end time.
@@ -92,9 +93,10 @@ def cpu_baseline(Q, budget_s=20.0):
                       f"[{first}, {first + count})) of the n={n} instance, {dt:.1f} s"}
 
 
-def batched(q, steps=2):
+def batched(q, steps=2, kind="int"):
     from paper_2607_04857_amd import inputs
-    Qs = inputs.batch(4096, 20, 34, seed=5, kind="int", lo=-100, hi=100)
+    seed = 5 if kind == "int" else 6
+    Qs = inputs.batch(4096, 20, 34, seed=seed, kind=kind, lo=-100, hi=100)
     b = q.Batch(Qs)
     b.run()                                   # warm-up replay
     t0 = time.perf_counter()
@@ -103,7 +105,8 @@ def batched(q, steps=2):
     dt = (time.perf_counter() - t0) / steps
     states, kms = b.stats()
     b.close()
-    return {"workload": "4096 dense QUBOs, n~U{20..34}, int32 U[-100,100], seed 5",
+    what = "int32 U[-100,100], seed 5" if kind == "int" else "float32 N(0,1), seed 6"
+    return {"workload": f"4096 dense QUBOs, n~U{{20..34}}, {what}",
             "states_per_s": states / dt, "ms_per_replay": dt * 1e3,
             "states": states, "graph_ms": kms}
 
@@ -211,6 +214,7 @@ def main():
         out = {}
         if not args.no_batch:
             out["batched"] = batched(q)
+            out["batched_fp32"] = batched(q, kind="fp32")
         if not args.no_serve:
             out["serving"] = serving(q)
         print(json.dumps(out), flush=True)
@@ -260,6 +264,7 @@ def main():
     line["roofline"]["frac_of_probe"] = achieved / probe
     if not args.no_batch:
         line["batched"] = batched(q)
+        line["batched_fp32"] = batched(q, kind="fp32")
     if not args.no_topk:
         line["topk"] = topk(q, torch)
     if not args.no_serve:

@@ -191,6 +191,54 @@ qubo_status_t qubo_server_info(qubo_server_t *srv, size_t *mem_in_use, size_t *m
 /* Stops accepting work, finishes every submitted request, frees the server. */
 void qubo_server_destroy(qubo_server_t *srv);
 
+/* ------------------------------------------------------- long solves
+ * Very large n (a walk of minutes to hours) in bounded slices with a
+ * resumable checkpoint.  The search space splits into independent segments
+ * whose minima reduce to the global one (the map-reduce scheme of Sec.
+ * III-C, which Sec. IV-C applies beyond the kernel's size limit).  Here a
+ * segment is a run of the plan's work items (see qubo_options_t): the solve
+ * walks items [next_item, next_item + items_per_slice) per slice, folds each
+ * slice's (E, index) into the running lexicographic minimum and then
+ * rewrites the checkpoint file at `path` (a sibling "<path>.tmp" is written
+ * and renamed over it, so the file is always whole).  If `path` already
+ * holds a checkpoint, the solve resumes after its last finished slice.
+ *
+ * Q, n, dtype: as qubo_solve.  opt (may be NULL): plan overrides as for
+ * qubo_solve_ex; item_first / item_count must be 0.  A resumed solve keeps
+ * the plan recorded in the checkpoint; an override that contradicts it is
+ * QUBO_EINVAL.  items_per_slice: work items per slice (0 = all remaining
+ * items in one slice; n <= 14 plans are always one slice).  max_slices: stop
+ * after this many slices in this call (0 = run to the end).
+ * Returns QUBO_OK with *out = the final result once every item is done
+ * (states = 2^n; kernel_ms = walk time summed over all slices of all calls;
+ * total_ms = this call), QUBO_EAGAIN when max_slices slices ran and items
+ * remain (*out untouched: read progress with qubo_checkpoint_info), and
+ * QUBO_EINVAL for a checkpoint that is malformed, belongs to another input
+ * (n, dtype or the FNV-1a hash of Q differ) or cannot be written.  The
+ * result equals qubo_solve's for the same input and plan.  Calls that share
+ * one path at the same time race. */
+typedef struct {
+    int n;
+    qubo_dtype_t dtype;
+    int A, B, L, tier, vgpr_levels;   /* plan of every slice (B = 0: direct)   */
+    uint64_t q_hash;      /* FNV-1a 64 of n, dtype and the n*n input words     */
+    uint64_t items;       /* work items of the plan (1 for a direct plan)      */
+    uint64_t next_item;   /* items [0, next_item) are finished                 */
+    int found;            /* 1 once best holds a state (next_item > 0)         */
+    qubo_state_t best;    /* lexicographic minimum over the finished items     */
+    int p;                /* fixed-point exponent (float32 input)              */
+    double tol;           /* as qubo_result_t.tol                              */
+    double walk_ms;       /* walk-kernel time summed over finished slices      */
+} qubo_checkpoint_t;
+
+qubo_status_t qubo_solve_checkpointed(const void *Q, int n, qubo_dtype_t dtype,
+                                      const qubo_options_t *opt, uint64_t items_per_slice,
+                                      int max_slices, const char *path, qubo_result_t *out);
+
+/* Read a checkpoint written by qubo_solve_checkpointed (host only, never
+ * touches the GPU).  QUBO_EINVAL if the file is missing or malformed. */
+qubo_status_t qubo_checkpoint_info(const char *path, qubo_checkpoint_t *info);
+
 /* Measurement: int32 VALU throughput of this device.  Runs wave64 streams of
  * independent `op` instructions (0: v_add_u32, 1: v_min3_i32, 2: v_add_u32
  * with one scalar add per two vector adds, 3: v_add_u32 with one never-taken

@@ -62,6 +62,15 @@ class _PlanInfo(ctypes.Structure):
                 ("items", ctypes.c_uint64)]
 
 
+class _Checkpoint(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("dtype", ctypes.c_int), ("A", ctypes.c_int),
+                ("B", ctypes.c_int), ("L", ctypes.c_int), ("tier", ctypes.c_int),
+                ("vgpr_levels", ctypes.c_int), ("q_hash", ctypes.c_uint64),
+                ("items", ctypes.c_uint64), ("next_item", ctypes.c_uint64), ("found", ctypes.c_int),
+                ("best", _State), ("p", ctypes.c_int), ("tol", ctypes.c_double),
+                ("walk_ms", ctypes.c_double)]
+
+
 class _TuneEntry(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("dtype", ctypes.c_int), ("B", ctypes.c_int),
                 ("L", ctypes.c_int), ("tier", ctypes.c_int), ("vgpr_levels", ctypes.c_int),
@@ -96,6 +105,9 @@ _SIGS = {
     "qubo_server_destroy": (None, [_VP]),
     "qubo_plan_info": (_I, [_VP, _I, _I, ctypes.POINTER(_Options), ctypes.POINTER(_PlanInfo),
                             ctypes.POINTER(ctypes.c_int32)]),
+    "qubo_solve_checkpointed": (_I, [_VP, _I, _I, ctypes.POINTER(_Options), ctypes.c_uint64, _I,
+                                     ctypes.c_char_p, ctypes.POINTER(_Result)]),
+    "qubo_checkpoint_info": (_I, [ctypes.c_char_p, ctypes.POINTER(_Checkpoint)]),
     "qubo_probe_valu": (_I, [_I, _I, _I, ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(ctypes.c_double)]),
     "qubo_autotune": (_I, [_I, _I, _I, _I, ctypes.c_char_p, ctypes.POINTER(_TuneEntry), _I,
@@ -355,6 +367,35 @@ def plan_info(Q, *, B: int = 0, L: int = 0, tier: int = 0, vgpr_levels: int = 0,
                                 T.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
     d = {f: getattr(info, f) for f, _ in _PlanInfo._fields_}
     d["T"] = T
+    return d
+
+
+def solve_checkpointed(Q, path: str, *, items_per_slice: int = 0, max_slices: int = 0,
+                       B: int = 0, L: int = 0, tier: int = 0, waves_per_cu: int = 0,
+                       vgpr_levels: int = 0) -> Optional[Result]:
+    """Solve in slices of work items with a resumable checkpoint at ``path``
+    (see ``qubo_solve_checkpointed``).  Returns the result when every item is
+    done, None when ``max_slices`` slices ran and items remain."""
+    Qc, dt = _as_q(Q)
+    n = Qc.shape[0]
+    out = _Result()
+    opt = _options(B, L, tier, waves_per_cu, vgpr_levels)
+    st = lib().qubo_solve_checkpointed(Qc.ctypes.data, n, dt, ctypes.byref(opt),
+                                       int(items_per_slice), int(max_slices), path.encode(),
+                                       ctypes.byref(out))
+    if st == -6:
+        return None
+    _check(st)
+    return _result(out, n)
+
+
+def checkpoint_info(path: str) -> dict:
+    """Progress recorded in a checkpoint file (host only)."""
+    c = _Checkpoint()
+    _check(lib().qubo_checkpoint_info(path.encode(), ctypes.byref(c)))
+    d = {f: getattr(c, f) for f, _ in _Checkpoint._fields_ if f != "best"}
+    d["dtype"] = "fp32" if c.dtype == QUBO_FP32 else "int32"
+    d["best"] = (c.best.energy_i, c.best.energy, c.best.index)
     return d
 
 

@@ -46,3 +46,56 @@ def test_solve_batch_function(orc):
     Qs = [inputs.uniform_int(n, -1000, 1000, 500 + n) for n in (16, 18, 20)]
     for Q, r in zip(Qs, q.solve_batch(Qs)):
         assert (r.energy_i, r.index) == orc.solve(Q, k=1)[0]
+
+
+def _flip_check(orc, Q, r):
+    """Every single flip of the returned state is no better (and no lower-index tie)."""
+    n = Q.shape[0]
+    is_int = Q.dtype == np.int32
+    E = orc.energy(Q, r.index)
+    if is_int:
+        assert E == r.energy_i, (n, r, E)
+    else:
+        assert abs(E - r.energy) <= 1e-9 * float(np.abs(Q.astype(np.float64)).sum()) + 1e-12
+    for i in range(n):
+        j = r.index ^ (1 << (n - 1 - i))
+        Ej = orc.energy(Q, j)
+        if is_int:
+            assert Ej > E or (Ej == E and j > r.index), (n, i, E, Ej)
+        else:
+            assert Ej >= r.energy - r.tol, (n, i, r.energy, Ej, r.tol)
+
+
+@pytest.mark.parametrize("kind,seed", [("int", 5), ("fp32", 6)])
+def test_batch_full_config_sampled(orc, kind, seed):
+    """The 4096-instance batch (n ~ U{20..34}) exactly as the benchmark replays it.
+
+    Every instance: the returned energy is the oracle's energy of the returned
+    state, and no single flip improves it.  A seeded sample of the instances
+    the oracle solves in seconds: (E*, index) equal to the oracle's.
+    """
+    import paper_2607_04857_amd as q
+    Qs = inputs.batch(4096, 20, 34, seed=seed, kind=kind)
+    b = q.Batch(Qs)
+    b.run()
+    b.run()
+    res = b.results()
+    states, _ = b.stats()
+    b.close()
+    assert states == sum(2.0 ** Q.shape[0] for Q in Qs)
+    for Q, r in zip(Qs, res):
+        _flip_check(orc, Q, r)
+    print(f"{kind}: all {len(Qs)} instances self-consistent and flip-stable", flush=True)
+    rng = np.random.default_rng(100 + seed)
+    small = [i for i, Q in enumerate(Qs) if Q.shape[0] <= 26]
+    big = [i for i, Q in enumerate(Qs) if Q.shape[0] == 29]
+    pick = list(rng.choice(small, size=20, replace=False)) + [int(rng.choice(big))]
+    for i in pick:
+        Q, r = Qs[i], res[i]
+        E, idx = orc.solve(Q, k=1)[0]
+        if kind == "int":
+            assert (r.energy_i, r.index) == (E, idx), (i, Q.shape[0], r, E, idx)
+        else:
+            assert abs(r.energy - E) <= r.tol, (i, r, E)
+            assert r.index == idx or r.energy <= E + r.tol
+    print(f"{kind}: {len(pick)} sampled instances equal the oracle", flush=True)
