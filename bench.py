@@ -55,11 +55,11 @@ def kernel_hash():
 
 
 def kernel_name(r):
-    """Template instance of the walk kernel a plan runs (row cache "4" is
-    G = 6 with the rows of levels 3 and 4 in LDS)."""
+    """Template instance of the walk kernel a plan runs (row caches "4" and
+    "3" are G = 6 and G = 5 with the rows of levels 3 and 4 in LDS)."""
     mc = 2 ** (r.B - 6)
-    if r.vgpr_levels == 4:
-        return "walk_kernel<%d,6,%d,true>" % (mc, r.tier)
+    if r.vgpr_levels in (3, 4):
+        return "walk_kernel<%d,%d,%d,true>" % (mc, r.vgpr_levels + 2, r.tier)
     return "walk_kernel<%d,%d,%d>" % (mc, r.vgpr_levels, r.tier)
 
 

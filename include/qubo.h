@@ -106,11 +106,13 @@ typedef struct {
     int tier;
     int waves_per_cu;
     int vgpr_levels;     /* Gray levels whose M_int rows stay in VGPRs: 0 = default
-                            (4 for B = 10, else 12), 12, 8 (B = 9 or 10), 6, 5
-                            or 4 (B = 10); fewer levels free VGPRs for a third
+                            (4 for B = 10, else 12), 12, 8 (B = 9 or 10), 6, 5,
+                            4 or 3 (B = 10); fewer levels free VGPRs for a third
                             or fourth wave per SIMD, the higher rows being read
                             from L2 when they flip.  4 keeps levels 0-2 and 5
-                            in VGPRs and levels 3-4 in LDS (8 KB per wave)    */
+                            in VGPRs and levels 3-4 in LDS (8 KB per wave); 3
+                            keeps levels 0-2 in VGPRs, levels 3-4 in LDS and
+                            reads every level from 5 up from L2              */
     int item_first;
     int item_count;
     int reserved;

@@ -235,10 +235,14 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
         part[v][x] = acc;
     }
     __syncthreads();
+    // rows A..2A-1 hold -M_int: a flip whose direction is known only at
+    // run time then adds one row or the other, without a branch
     for (uint32_t e = tid; e < uint32_t(A) * NS; e += stride) {
         const int v = int(e >> B);
         const uint32_t s = e & (NS - 1);
-        I.M[e] = part[v][s & 31u] + part[v][32u + (s >> 5)];
+        const int32_t m = part[v][s & 31u] + part[v][32u + (s >> 5)];
+        I.M[e] = m;
+        I.M[uint32_t(A) * NS + e] = -m;
     }
     // E_s(U_B)[s] = sum_{t <= u, both set} T[A+t][A+u] (Sec. III-A, step 2)
     for (uint32_t s = tid; s < NS; s += stride) {
@@ -256,6 +260,7 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
         int32_t v = 0;
         if (l < A && l != w) v = (l < w) ? T[l * n + w] : T[w * n + l];
         I.S[e] = v;
+        I.S[uint32_t(A) * kWave + e] = -v;   // negated rows, as for M_int
     }
     if (blockIdx.x != 0) return;
     __syncthreads();
@@ -797,16 +802,12 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
         if constexpr (TIER == 1) build_thr();
 
         // A non-low prefix variable w flips (direction up: 0 -> 1); SLw[t] is
-        // its coupling with the low variable A-1-t.
-        auto nonlow_flip = [&](int w, bool up, int32_t Scol, const int32_t *SLw) {
+        // its coupling with the low variable A-1-t; Sd is its coupling
+        // column with the sign of the flip applied.
+        auto nonlow_flip = [&](int w, bool up, int32_t Sd, const int32_t *SLw) {
             const int32_t Fw = __builtin_amdgcn_readlane(F, w);
-            if (up) {
-                Enl += Fw;
-                F += Scol;
-            } else {
-                Enl -= Fw;
-                F -= Scol;
-            }
+            Enl = up ? Enl + Fw : Enl - Fw;
+            F += Sd;
             static_for<0, kLowLevels>([&](auto tc) {
                 constexpr int t = decltype(tc)::value;
                 H[t] = up ? H[t] + SLw[t] : H[t] - SLw[t];
@@ -887,7 +888,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                 for (int j = 0; j < MC; j++) E[j] -= R4[j];
             }
             pin_vec<MC>(E);
-            nonlow_flip(A - 5, up, S4, S4L);
+            nonlow_flip(A - 5, up, up ? S4 : -S4, S4L);
             return up;
         };
         // Flip entering super-block sb + 1 (Gray level >= 5).
@@ -910,24 +911,12 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                     done = true;
                 }
             });
+            // signed row (M_int or its negation) for levels read from L2:
+            // one code path whatever the direction
+            const int ws = up ? w : w + A;
             if (!done) {
-                // row from L2; the direction is wave-uniform, so branch on it
-                // rather than select +-r per element
-                // in halves of up to 8 columns: fewer registers in flight
-                constexpr int HC = MC > 8 ? 8 : MC;
 #pragma unroll
-                for (int j0 = 0; j0 < MC; j0 += HC) {
-                    int32_t r[HC];
-#pragma unroll
-                    for (int j = 0; j < HC; j++) r[j] = trow(M, w)[(j0 + j) * kWave + ulane];
-                    if (up) {
-#pragma unroll
-                        for (int j = 0; j < HC; j++) E[j0 + j] += r[j];
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < HC; j++) E[j0 + j] -= r[j];
-                    }
-                }
+                for (int j = 0; j < MC; j++) E[j] += trow(M, ws)[j * kWave + ulane];
             }
             pin_vec<MC>(E);
             int32_t SLw[kLowLevels];
@@ -935,7 +924,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                 constexpr int tt = decltype(tc)::value;
                 SLw[tt] = kall[kbase + kKBound + w * 4 + tt];
             });
-            nonlow_flip(w, up, S[size_t(w) * kWave + ulane], SLw);
+            nonlow_flip(w, up, S[size_t(ws) * kWave + ulane], SLw);
         };
 
         if constexpr (TIER == 1) {
@@ -960,7 +949,10 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                 });
             }
         } else {
-            for (uint64_t sb = sb0; sb < sbEnd; sb++) {
+            // 32-bit trip count: a 64-bit compare would take the vector unit
+            const uint32_t nsb = uint32_t(sbEnd - sb0);
+            for (uint32_t ks = 0; ks < nsb; ks++) {
+                const uint64_t sb = sb0 + ks;
                 W0 = wave_min_bcast(tree_min<MC>(E));
                 static_for<0, 2>([&](auto hc) {
                     constexpr int h = decltype(hc)::value;
@@ -1008,7 +1000,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                     }
                     if constexpr (h == 0) {
                         tab2 = middle_flip(sb) ? 1 : 2;
-                    } else if (sb + 1 < sbEnd) {
+                    } else if (ks + 1 < nsb) {
                         boundary_flip(sb);
                         tab2 = 0;
                     }
@@ -1169,19 +1161,23 @@ static int occupancy_g(int tier, int topk_k)
 }
 
 // Variants built: every MC with G = 12; MC = 8 and 16 with G = 8; MC = 16
-// with G = 6 and 5, and "4": G = 6 with levels 3 and 4 in LDS (levels 0-2
-// and 5 in VGPRs, four waves per SIMD).
+// with G = 6 and 5, "4": G = 6 with levels 3 and 4 in LDS (levels 0-2 and 5
+// in VGPRs, four waves per SIMD), and "3": G = 5 with levels 3 and 4 in LDS
+// (levels 0-2 in VGPRs; every flip of level 5 or above reads its signed row
+// from L2, so the flip into the next super-block takes one code path).
 bool walk_variant_exists(int mcols, int vgpr_levels)
 {
     if (vgpr_levels == 12) return mcols == 1 || mcols == 2 || mcols == 4 || mcols == 8 || mcols == 16;
     if (vgpr_levels == 8) return mcols == 8 || mcols == 16;
-    if (vgpr_levels == 6 || vgpr_levels == 5 || vgpr_levels == 4) return mcols == 16;
+    if (vgpr_levels == 6 || vgpr_levels == 5 || vgpr_levels == 4 || vgpr_levels == 3)
+        return mcols == 16;
     return false;
 }
 
 int walk_occupancy(int mcols, int vgpr_levels, int tier, int topk_k)
 {
     if (vgpr_levels == 4) return occupancy_g<16, 6, true>(tier, topk_k);
+    if (vgpr_levels == 3) return occupancy_g<16, 5, true>(tier, topk_k);
     if (vgpr_levels == 5) return occupancy_g<16, 5>(tier, topk_k);
     if (vgpr_levels == 6) return occupancy_g<16, 6>(tier, topk_k);
     if (vgpr_levels == 8)
@@ -1200,9 +1196,10 @@ hipError_t launch_walk(int mcols, int vgpr_levels, int tier, const Inst *d_insts
                        int waves, hipStream_t stream, const TopkWalk *tk)
 {
 #define QK_ARGS tier, d_insts, n_inst, total_items, d_counter, d_k, waves, stream, tk
-    if (vgpr_levels == 6 || vgpr_levels == 5 || vgpr_levels == 4) {
+    if (vgpr_levels == 6 || vgpr_levels == 5 || vgpr_levels == 4 || vgpr_levels == 3) {
         if (mcols != 16) return hipErrorInvalidValue;
         if (vgpr_levels == 4) return launch_walk_g<16, 6, true>(QK_ARGS);
+        if (vgpr_levels == 3) return launch_walk_g<16, 5, true>(QK_ARGS);
         return vgpr_levels == 6 ? launch_walk_g<16, 6>(QK_ARGS) : launch_walk_g<16, 5>(QK_ARGS);
     }
     if (vgpr_levels == 8) {

@@ -26,7 +26,7 @@ bool variant_built(int mcols, int G)
 {
     if (G == 12) return mcols == 1 || mcols == 2 || mcols == 4 || mcols == 8 || mcols == 16;
     if (G == 8) return mcols == 8 || mcols == 16;
-    if (G == 6 || G == 5 || G == 4) return mcols == 16;
+    if (G == 6 || G == 5 || G == 4 || G == 3) return mcols == 16;
     return false;
 }
 
@@ -191,8 +191,8 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
     const int tier = (opt && opt->tier) ? opt->tier : (use_tune ? tuned.tier : kDefaultTier);
     int vgpr_levels = (opt && opt->vgpr_levels) ? opt->vgpr_levels : (use_tune ? tuned.vgpr_levels : 0);
     if (vgpr_levels != 0 && vgpr_levels != 12 && vgpr_levels != 8 && vgpr_levels != 6 &&
-        vgpr_levels != 5 && vgpr_levels != 4) {
-        *msg = "option vgpr_levels must be 0, 4, 5, 6, 8 or 12";
+        vgpr_levels != 5 && vgpr_levels != 4 && vgpr_levels != 3) {
+        *msg = "option vgpr_levels must be 0, 3, 4, 5, 6, 8 or 12";
         return QUBO_EINVAL;
     }
     P.direct = n <= kDirectMaxN;
@@ -221,7 +221,7 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
     // suffixes.
     if (vgpr_levels == 0) vgpr_levels = P.mcols == 16 ? 4 : 12;
     if ((vgpr_levels == 8 && P.mcols < 8) || (vgpr_levels <= 6 && vgpr_levels && P.mcols != 16)) {
-        *msg = "vgpr_levels 8 needs B = 9 or 10, vgpr_levels 4, 5 and 6 need B = 10";
+        *msg = "vgpr_levels 8 needs B = 9 or 10, vgpr_levels 3, 4, 5 and 6 need B = 10";
         return QUBO_EINVAL;
     }
     P.vgpr_levels = vgpr_levels;

@@ -94,12 +94,13 @@ static JobOffsets compute_offsets(const Job &job, size_t *stage_bytes, size_t *b
     for (size_t i = 0; i < ni; i++) {
         const qplan::Plan &P = job.plans[i];
         const size_t A = P.direct ? 0 : size_t(P.A), NS = P.direct ? 0 : (size_t(1) << P.B);
+        // M_int and the prefix couplings, each followed by its negation
         o.M.push_back(off);
-        off = align_up(off + A * NS * sizeof(int32_t), 256);
+        off = align_up(off + 2 * A * NS * sizeof(int32_t), 256);
         o.EB.push_back(off);
         off = align_up(off + NS * sizeof(int32_t), 256);
         o.S.push_back(off);
-        off = align_up(off + A * qk::kWave * sizeof(int32_t), 256);
+        off = align_up(off + 2 * A * qk::kWave * sizeof(int32_t), 256);
     }
     o.K = off;
     off = align_up(off + ni * qk::kKTable * sizeof(int32_t), 256);
@@ -473,8 +474,8 @@ qubo_status_t solve_host(const void *Q, int n, qubo_dtype_t dtype, int k, const 
             P.tier = 3;
             // The LDS row cache shares LDS with the list: when both no longer
             // fit four waves per SIMD, the VGPR row cache (three waves) wins.
-            if (P.vgpr_levels == 4 && !(opt && opt->vgpr_levels) &&
-                qk::walk_occupancy(P.mcols, 4, 3, k) < 4 * 4)
+            if ((P.vgpr_levels == 4 || P.vgpr_levels == 3) && !(opt && opt->vgpr_levels) &&
+                qk::walk_occupancy(P.mcols, P.vgpr_levels, 3, k) < 4 * 4)
                 P.vgpr_levels = 6;
         }
     }

@@ -387,7 +387,7 @@ struct Candidate {
 // work-item sizes around the default.
 qubo_status_t candidates(const void *Q, int n, qubo_dtype_t dtype, std::vector<Candidate> *out)
 {
-    static const int kCaches[] = {12, 8, 6, 5, 4};
+    static const int kCaches[] = {12, 8, 6, 5, 4, 3};
     for (int B = 6; B <= 10; B++) {
         if (n - B < qplan::kSuper) continue;
         const int mcols = (1 << B) / qplan::kWave;

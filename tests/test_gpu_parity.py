@@ -56,7 +56,7 @@ def test_split_invariance(q, orc, B, L, tier):
 
 
 @pytest.mark.parametrize("tier", TIERS)
-@pytest.mark.parametrize("B,G", [(9, 8), (10, 8), (10, 6), (10, 5), (10, 4)])
+@pytest.mark.parametrize("B,G", [(9, 8), (10, 8), (10, 6), (10, 5), (10, 4), (10, 3)])
 @pytest.mark.parametrize("L", [5, 9])
 def test_vgpr_levels(q, orc, B, G, L, tier):
     Q = inputs.uniform_int(23, -500, 500, 78)

@@ -36,7 +36,7 @@ def test_walk_sizes(orc, n, k):
 
 
 @pytest.mark.parametrize("B,G", [(6, 12), (7, 12), (8, 12), (9, 12), (9, 8), (10, 12), (10, 8),
-                                 (10, 6), (10, 5), (10, 4)])
+                                 (10, 6), (10, 5), (10, 4), (10, 3)])
 def test_every_walk_variant(orc, B, G):
     import paper_2607_04857_amd as q
     Q = inputs.uniform_int(22, -500, 500, 1200 + B * 16 + G)
