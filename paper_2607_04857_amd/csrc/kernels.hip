@@ -357,11 +357,13 @@ __device__ __forceinline__ int32_t wave_min_bcast(int32_t v)
 
 // TIER 1: the chunk minimum (v_min3 tree) is compared with the threshold at
 //         every Gray step.
-// TIER 2: an exact wave minimum W0 is taken once per 32-step super-block;
-//         at offset o the chunk minimum is at least W0 + D(o) (table K), so
-//         step o needs only the scalar test W0 <= THR - D(o); each 16-step
-//         half first tests W0 against an upper bound of its 16 thresholds, and
-//         builds and tests the exact ones only when that passes.
+// TIER 2: each lane takes its chunk minimum lm0 once per 32-step
+//         super-block; at offset o the chunk minimum is at least
+//         W0 + D(o) (table K), W0 the wave minimum of lm0, so step o needs
+//         only the scalar test W0 <= THR - D(o).  Each 16-step half first
+//         tests lm0 against an upper bound of its 16 thresholds (one vector
+//         compare); only when a lane passes are W0 and the exact thresholds
+//         formed and tested.
 // Resident waves per SIMD each variant is register-allocated for: the full
 // 12-level row cache fits 256 VGPRs (2 waves); the 8- and 6-level caches
 // leave room for a third (MC=16) or a fourth (MC=8) wave.
@@ -818,6 +820,8 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
         uint64_t itemRow = 0;
         int found = 0;
         int32_t W0 = 0;    // TIER 2: exact wave minimum at the super-block start
+                           // (taken on the cold path only)
+        int32_t lm0 = 0;   // TIER 2: this lane's chunk minimum at the super-block start
         int tab2 = 0;      // TIER 2: K table of the current half
 
         // Candidate test at Gray step i with chunk minimum lm and threshold thr.
@@ -953,7 +957,10 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
             const uint32_t nsb = uint32_t(sbEnd - sb0);
             for (uint32_t ks = 0; ks < nsb; ks++) {
                 const uint64_t sb = sb0 + ks;
-                W0 = wave_min_bcast(tree_min<MC>(E));
+                // (tier 3, short of registers for its lists, keeps the
+                // wave minimum instead of the lane minimum)
+                if constexpr (TIER == 3) W0 = wave_min_bcast(tree_min<MC>(E));
+                else lm0 = tree_min<MC>(E);
                 static_for<0, 2>([&](auto hc) {
                     constexpr int h = decltype(hc)::value;
                     // the 16 steps of half h, with (CHECK) or without the
@@ -988,7 +995,13 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                     // hs(o) >= sum_t min(0, H[t]) and C2(o) >= min_o C2.
                     int32_t tb = best - Enl - kall[kbase + kKC2Min + tab2];
                     static_for<0, kLowLevels>([&](auto tc) { tb -= min(0, H[decltype(tc)::value]); });
-                    if (__builtin_expect(W0 <= tb, 0)) {
+                    // any lane at or below the bound (the wave minimum W0 is
+                    // formed only then)
+                    bool cold;
+                    if constexpr (TIER == 3) cold = W0 <= tb;
+                    else cold = __builtin_amdgcn_ballot_w64(lm0 <= tb) != 0;
+                    if (__builtin_expect(cold, 0)) {
+                        if constexpr (TIER != 3) W0 = wave_min_bcast(lm0);
                         // exact per-step thresholds and tests
                         build_tp(h, tab2);
                         static_for<0, H16>([&](auto oc) {
