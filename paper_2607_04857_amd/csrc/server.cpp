@@ -386,7 +386,10 @@ qubo_status_t server_init(qubo_server *s, size_t budget, int max_slots)
     qubo_status_t st = qrt::device_info(&di);
     if (st != QUBO_OK) return st;
     s->cus = di.cus;
-    s->tick_items = uint64_t(di.cus) * uint64_t(qk::walk_occupancy(16, 6, 2)) * 2;
+    // two items per resident wave of the default walk variant (B = 10, LDS
+    // row cache): every wave of a tick then gets the same share, so the
+    // tick ends without a half-idle tail
+    s->tick_items = uint64_t(di.cus) * uint64_t(qk::walk_occupancy(16, 4, 2)) * 2;
     QRT_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "hipStreamCreate");
     QRT_HIP(hipMalloc(&s->d_karena, size_t(max_slots) * qk::kKTable * sizeof(int32_t)), "hipMalloc");
     // one item counter per walk variant launched in a tick
