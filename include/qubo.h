@@ -271,17 +271,26 @@ qubo_status_t qubo_plan_info(const void *Q, int n, qubo_dtype_t dtype,
  * suffix width B (columns per lane), the row-cache depth vgpr_levels, the
  * bound tier and the work-item size L.  The paper tuned its kernel by hand
  * on its GPU (Sec. IV); here the library times every plan it can run and
- * keeps the fastest per (n, dtype) in a process-wide table that the planner
- * consults whenever the caller's options override none of B, L, tier and
- * vgpr_levels (all zero or opt == NULL).  Batches and the server use the
- * tuned B / vgpr_levels / tier but their own L.  The table starts empty
+ * keeps the fastest per (scope, n, dtype) in a process-wide table that the
+ * planner consults whenever the caller's options override none of B, L, tier
+ * and vgpr_levels (all zero or opt == NULL).  Two scopes: QUBO_TUNE_SINGLE
+ * entries (qubo_autotune) serve lone solves, whose speed depends on spreading
+ * one instance over the GPU; QUBO_TUNE_BATCH entries (qubo_autotune_batch)
+ * serve instances of batches and the server, where many instances fill the
+ * GPU (their L is always the batch item size).  The table starts empty
  * (built-in defaults) unless QUBO_TUNE_CACHE names a cache file, which is
  * then loaded at the first solve, batch or server submission. */
+#define QUBO_TUNE_SINGLE 0
+#define QUBO_TUNE_BATCH 1
 typedef struct {
     int n;                 /* variables, 15..60                                  */
     qubo_dtype_t dtype;
-    int B, L, tier, vgpr_levels;   /* L = 0: the planner's default item size   */
-    double walk_ms;        /* measured walk time of this plan (informational)   */
+    int B, L, tier, vgpr_levels;   /* L = 0: the planner's default item size
+                                      (always 0 for QUBO_TUNE_BATCH)          */
+    double walk_ms;        /* measured time of this plan (informational): the
+                              walk kernel for single entries, one batch replay
+                              for batch entries                              */
+    int scope;             /* QUBO_TUNE_SINGLE or QUBO_TUNE_BATCH               */
 } qubo_tune_entry_t;
 
 /* Time every runnable plan for each n in [n_min, n_max] (15 <= n_min <= n_max
@@ -297,6 +306,22 @@ qubo_status_t qubo_autotune(int n_min, int n_max, qubo_dtype_t dtype, int reps,
                             const char *cache_path, qubo_tune_entry_t *out,
                             int out_cap, int *out_count);
 
+/* The batch-scope counterpart of qubo_autotune: for each n in [n_min, n_max]
+ * (15 <= n_min <= n_max <= 44) it times every runnable (B, vgpr_levels, tier)
+ * on a batch of m = min(4096, max(1, 2^(39-n))) copies of the synthetic
+ * instance -- enough work to fill the GPU, as in the batch and server
+ * workloads -- by the event time of one graph replay, each candidate once and
+ * the four fastest `reps` more times.  The built-in plan is kept unless a
+ * candidate is at least 5% faster (each extra kernel variant in a batch adds
+ * a persistent launch and its tail, which a per-n timing does not see).
+ * Every instance of every candidate must return the same (E*, index*)
+ * (QUBO_EINTERNAL otherwise).  Winners go into the table with scope
+ * QUBO_TUNE_BATCH and, with cache_path, into that file, as for
+ * qubo_autotune. */
+qubo_status_t qubo_autotune_batch(int n_min, int n_max, qubo_dtype_t dtype, int reps,
+                                  const char *cache_path, qubo_tune_entry_t *out,
+                                  int out_cap, int *out_count);
+
 /* Load a cache file into the process table.  device_key: the key the file
  * must carry; NULL = this device's key (qubo_device_key).  A file made on
  * another device, malformed JSON or an entry naming a plan this build cannot
@@ -311,8 +336,9 @@ qubo_status_t qubo_tune_save(const char *path, const char *device_key);
  * qubo_tune_load; nothing is stored if any entry is invalid). */
 qubo_status_t qubo_tune_set(const qubo_tune_entry_t *entries, int count);
 
-/* 1 and *out filled (out may be NULL) if the table holds (n, dtype), else 0. */
-int qubo_tune_lookup(int n, qubo_dtype_t dtype, qubo_tune_entry_t *out);
+/* 1 and *out filled (out may be NULL) if the table holds (scope, n, dtype),
+ * else 0. */
+int qubo_tune_lookup(int n, qubo_dtype_t dtype, int scope, qubo_tune_entry_t *out);
 
 /* Empty the process table (built-in defaults again). */
 void qubo_tune_clear(void);

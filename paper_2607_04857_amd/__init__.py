@@ -74,7 +74,7 @@ class _Checkpoint(ctypes.Structure):
 class _TuneEntry(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("dtype", ctypes.c_int), ("B", ctypes.c_int),
                 ("L", ctypes.c_int), ("tier", ctypes.c_int), ("vgpr_levels", ctypes.c_int),
-                ("walk_ms", ctypes.c_double)]
+                ("walk_ms", ctypes.c_double), ("scope", ctypes.c_int)]
 
 
 # name -> (restype, argtypes); mirrors include/qubo.h
@@ -112,10 +112,12 @@ _SIGS = {
                              ctypes.POINTER(ctypes.c_double)]),
     "qubo_autotune": (_I, [_I, _I, _I, _I, ctypes.c_char_p, ctypes.POINTER(_TuneEntry), _I,
                            ctypes.POINTER(_I)]),
+    "qubo_autotune_batch": (_I, [_I, _I, _I, _I, ctypes.c_char_p, ctypes.POINTER(_TuneEntry), _I,
+                                 ctypes.POINTER(_I)]),
     "qubo_tune_load": (_I, [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(_I)]),
     "qubo_tune_save": (_I, [ctypes.c_char_p, ctypes.c_char_p]),
     "qubo_tune_set": (_I, [ctypes.POINTER(_TuneEntry), _I]),
-    "qubo_tune_lookup": (_I, [_I, _I, ctypes.POINTER(_TuneEntry)]),
+    "qubo_tune_lookup": (_I, [_I, _I, _I, ctypes.POINTER(_TuneEntry)]),
     "qubo_tune_clear": (None, []),
     "qubo_device_key": (_I, [ctypes.c_char_p, _I]),
     "qubo_last_error": (ctypes.c_char_p, []),
@@ -417,21 +419,26 @@ def probe_valu(op: str = "add", waves_per_simd: int = 4, iters: int = 4096):
 _DTYPES = {"int32": QUBO_INT32, "fp32": QUBO_FP32}
 
 
+_SCOPES = {"single": 0, "batch": 1}
+
+
 def _entry_dict(e: _TuneEntry) -> dict:
     return {"n": e.n, "dtype": "fp32" if e.dtype == QUBO_FP32 else "int32", "B": e.B, "L": e.L,
-            "tier": e.tier, "vgpr_levels": e.vgpr_levels, "walk_ms": e.walk_ms}
+            "tier": e.tier, "vgpr_levels": e.vgpr_levels, "walk_ms": e.walk_ms,
+            "scope": "batch" if e.scope == 1 else "single"}
 
 
 def autotune(n_min: int, n_max: int, dtype: str = "int32", reps: int = 2,
-             cache_path: Optional[str] = None) -> List[dict]:
+             cache_path: Optional[str] = None, batch: bool = False) -> List[dict]:
     """Time every runnable walk plan for n in [n_min, n_max] and install the
-    fastest per n (see ``qubo_autotune``); returns the winners."""
+    fastest per n (see ``qubo_autotune``; batch=True: ``qubo_autotune_batch``,
+    the plans of instances inside batches and the server); returns the winners."""
     cap = n_max - n_min + 1
     out = (_TuneEntry * max(cap, 1))()
     cnt = ctypes.c_int()
-    _check(lib().qubo_autotune(int(n_min), int(n_max), _DTYPES[dtype], int(reps),
-                               cache_path.encode() if cache_path else None, out, cap,
-                               ctypes.byref(cnt)))
+    fn = lib().qubo_autotune_batch if batch else lib().qubo_autotune
+    _check(fn(int(n_min), int(n_max), _DTYPES[dtype], int(reps),
+              cache_path.encode() if cache_path else None, out, cap, ctypes.byref(cnt)))
     return [_entry_dict(out[k]) for k in range(min(cnt.value, cap))]
 
 
@@ -452,13 +459,13 @@ def tune_set(entries: Sequence[dict]):
     for k, e in enumerate(entries):
         arr[k] = _TuneEntry(int(e["n"]), _DTYPES[e.get("dtype", "int32")], int(e["B"]),
                             int(e.get("L", 0)), int(e["tier"]), int(e["vgpr_levels"]),
-                            float(e.get("walk_ms", 0.0)))
+                            float(e.get("walk_ms", 0.0)), _SCOPES[e.get("scope", "single")])
     _check(lib().qubo_tune_set(arr, len(entries)))
 
 
-def tune_lookup(n: int, dtype: str = "int32") -> Optional[dict]:
+def tune_lookup(n: int, dtype: str = "int32", scope: str = "single") -> Optional[dict]:
     e = _TuneEntry()
-    if lib().qubo_tune_lookup(int(n), _DTYPES[dtype], ctypes.byref(e)):
+    if lib().qubo_tune_lookup(int(n), _DTYPES[dtype], _SCOPES[scope], ctypes.byref(e)):
         return _entry_dict(e)
     return None
 

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <utility>
 
 namespace qplan {
@@ -20,7 +21,7 @@ constexpr int kMaxB = 10;          // 16 columns per lane (VGPR budget)
 constexpr int kDefaultTier = 2;
 
 std::mutex g_tune_mu;
-std::map<std::pair<int, int>, TuneEntry> g_tune;   // (n, dtype) -> entry
+std::map<std::tuple<int, int, int>, TuneEntry> g_tune;   // (scope, n, dtype) -> entry
 
 bool variant_built(int mcols, int G)
 {
@@ -35,13 +36,13 @@ bool variant_built(int mcols, int G)
 void tune_put(const TuneEntry &e)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[{e.n, int(e.dtype)}] = e;
+    g_tune[std::make_tuple(e.scope, e.n, int(e.dtype))] = e;
 }
 
-bool tune_get(int n, qubo_dtype_t dtype, TuneEntry *out)
+bool tune_get(int n, qubo_dtype_t dtype, int scope, TuneEntry *out)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find({n, int(dtype)});
+    auto it = g_tune.find(std::make_tuple(scope, n, int(dtype)));
     if (it == g_tune.end()) return false;
     *out = it->second;
     return true;
@@ -77,6 +78,14 @@ bool tune_valid(const TuneEntry &e, std::string *msg)
     }
     if (e.tier != 1 && e.tier != 2) {
         *msg = "tuning entry tier must be 1 or 2";
+        return false;
+    }
+    if (e.scope != kScopeSingle && e.scope != kScopeBatch) {
+        *msg = "tuning entry scope must be single (0) or batch (1)";
+        return false;
+    }
+    if (e.scope == kScopeBatch && e.L != 0) {
+        *msg = "batch tuning entries keep the batch item size (L = 0)";
         return false;
     }
     if (!variant_built((1 << e.B) / kWave, e.vgpr_levels)) {
@@ -177,7 +186,8 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
     // A tuned choice applies when the caller overrides none of the walk knobs.
     TuneEntry tuned;
     const bool overridden = opt && (opt->B || opt->L || opt->tier || opt->vgpr_levels);
-    const bool use_tune = !overridden && n > kDirectMaxN && tune_get(n, dtype, &tuned);
+    const bool use_tune = !overridden && n > kDirectMaxN &&
+                          tune_get(n, dtype, many ? kScopeBatch : kScopeSingle, &tuned);
 
     int B = (opt && opt->B) ? opt->B : (use_tune ? tuned.B : kDefaultB);
     if (opt && opt->B && (opt->B < kMinB || opt->B > kMaxB)) {

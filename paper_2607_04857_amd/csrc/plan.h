@@ -41,17 +41,26 @@ struct Plan {
 };
 
 // One tuned walk choice for instances of n variables and a dtype.
+// Scope of an entry: the plan of a lone solve (its latency: every item of
+// one instance spread over the GPU), or the plan of an instance inside a
+// batch or the server (throughput: the GPU filled by many instances).
+constexpr int kScopeSingle = 0;
+constexpr int kScopeBatch = 1;
+
 struct TuneEntry {
     int n = 0;
     qubo_dtype_t dtype = QUBO_INT32;
     int B = 0, L = 0, tier = 0, vgpr_levels = 0;
     double walk_ms = 0.0;      // measured walk time of the chosen plan
+    int scope = kScopeSingle;
 };
 
-// Process-wide tuning table (thread-safe).  make_plan consults it when the
-// caller overrides none of B, L, tier and vgpr_levels.
+// Process-wide tuning table (thread-safe), keyed by (scope, n, dtype).
+// make_plan consults it when the caller overrides none of B, L, tier and
+// vgpr_levels: the single scope for lone solves, the batch scope for
+// instances of batches and the server.
 void tune_put(const TuneEntry &e);
-bool tune_get(int n, qubo_dtype_t dtype, TuneEntry *out);
+bool tune_get(int n, qubo_dtype_t dtype, int scope, TuneEntry *out);
 void tune_clear();
 std::vector<TuneEntry> tune_all();
 

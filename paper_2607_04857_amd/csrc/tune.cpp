@@ -10,10 +10,18 @@
 // fastest, and let the planner use it.  Every candidate must return the same
 // (E*, index*) -- plan invariance is checked on every tuning run.
 //
+// Two scopes: lone solves are timed by their walk kernel; instances of
+// batches and the server by the replay of a batch that fills the GPU, since
+// the best plan for one instance spread over the whole GPU (more, smaller
+// items: narrower suffixes at small n) is not the best one for many
+// instances sharing it.
+//
 // Cache file: a JSON object
 //   {"format": "qubo-tune-1", "device": "<arch>/<CUs>cu",
 //    "entries": [{"n": .., "dtype": "int32"|"fp32", "B": .., "L": ..,
-//                 "tier": .., "vgpr_levels": .., "walk_ms": ..}, ...]}
+//                 "tier": .., "vgpr_levels": .., "walk_ms": ..,
+//                 "scope": "single"|"batch"}, ...]}
+// (an entry without "scope" is a single-solve entry).
 #include <algorithm>
 #include <cctype>
 #include <cmath>
@@ -252,6 +260,12 @@ bool parse_cache(const std::string &text, const std::string &device_key,
             return false;
         const JVal *ms = o.get("walk_ms");
         e.walk_ms = (ms && ms->kind == JVal::Num) ? ms->num : 0.0;
+        const JVal *sc = o.get("scope");
+        if (sc && (sc->kind != JVal::Str || (sc->str != "single" && sc->str != "batch"))) {
+            *msg = "entry field 'scope' must be \"single\" or \"batch\"";
+            return false;
+        }
+        e.scope = (sc && sc->str == "batch") ? qplan::kScopeBatch : qplan::kScopeSingle;
         if (!qplan::tune_valid(e, msg)) {
             *msg = "n=" + std::to_string(e.n) + ": " + *msg;
             return false;
@@ -267,12 +281,12 @@ std::string format_cache(const std::vector<qplan::TuneEntry> &entries, const std
     o << "{\"format\": \"" << kFormat << "\", \"device\": \"" << key << "\", \"entries\": [";
     for (size_t k = 0; k < entries.size(); k++) {
         const qplan::TuneEntry &e = entries[k];
-        char buf[256];
+        char buf[320];
         std::snprintf(buf, sizeof(buf),
                       "%s\n  {\"n\": %d, \"dtype\": \"%s\", \"B\": %d, \"L\": %d, \"tier\": %d, "
-                      "\"vgpr_levels\": %d, \"walk_ms\": %.17g}",
+                      "\"vgpr_levels\": %d, \"walk_ms\": %.17g, \"scope\": \"%s\"}",
                       k ? "," : "", e.n, dtype_name(e.dtype), e.B, e.L, e.tier, e.vgpr_levels,
-                      e.walk_ms);
+                      e.walk_ms, e.scope == qplan::kScopeBatch ? "batch" : "single");
         o << buf;
     }
     o << "\n]}\n";
@@ -489,6 +503,130 @@ qubo_status_t tune_one(int n, qubo_dtype_t dtype, int reps, hipStream_t stream,
     return QUBO_OK;
 }
 
+// Batch scope: m copies of the tuning instance of n in one batch, timed by
+// a graph replay (2^39 states where 4096 copies reach that: the walk then
+// dominates the replay, as it does in real batches).
+int batch_copies(int n) { return n >= 39 ? 1 : std::min(4096, 1 << (39 - n)); }
+
+// A batch-scope winner must beat the built-in plan by this margin: every
+// extra kernel variant in a batch is one more persistent launch with its own
+// tail, which a per-n timing does not see (measured: per-n winners 2-5%
+// ahead at n = 20-28 made a mixed 4096-instance batch up to 1% slower).
+constexpr double kBatchMargin = 0.95;
+
+qubo_status_t time_batch(const std::vector<const void *> &ptrs, const std::vector<int> &ns,
+                         const std::vector<qubo_dtype_t> &dts, const qubo_options_t &o, int runs,
+                         double *ms, qubo_result_t *first, qubo_result_t *last)
+{
+    qubo_batch_t *b = nullptr;
+    qubo_status_t st = qubo_batch_create(int(ptrs.size()), ptrs.data(), ns.data(), dts.data(), &o, &b);
+    if (st != QUBO_OK) return st;
+    *ms = 1e300;
+    for (int r = 0; r < runs && st == QUBO_OK; r++) {
+        st = qubo_batch_run(b, nullptr);
+        double states = 0, kms = 0;
+        if (st == QUBO_OK) st = qubo_batch_stats(b, &states, &kms);
+        if (st == QUBO_OK && r > 0) *ms = std::min(*ms, kms);   // run 0 warms up
+    }
+    std::vector<qubo_result_t> res(ptrs.size());
+    if (st == QUBO_OK) st = qubo_batch_results(b, res.data());
+    if (st == QUBO_OK) {
+        *first = res.front();
+        *last = res.back();
+    }
+    const std::string keep = qrt::last_error_cstr();
+    qubo_batch_destroy(b);
+    qrt::set_error(keep);
+    return st;
+}
+
+qubo_status_t tune_batch_one(int n, qubo_dtype_t dtype, int reps, qplan::TuneEntry *winner)
+{
+    const std::vector<uint32_t> q = tuning_instance(n, dtype);
+    const int m = batch_copies(n);
+    const std::vector<const void *> ptrs(size_t(m), q.data());
+    const std::vector<int> ns(size_t(m), n);
+    const std::vector<qubo_dtype_t> dts(size_t(m), dtype);
+    // (B, row cache, tier) as for a lone solve; L stays the batch default
+    std::vector<Candidate> cands, all;
+    qubo_status_t st = candidates(q.data(), n, dtype, &all);
+    if (st != QUBO_OK) return st;
+    for (const Candidate &c : all) {
+        bool dup = false;
+        for (const Candidate &d : cands)
+            dup |= d.opt.B == c.opt.B && d.opt.tier == c.opt.tier && d.opt.vgpr_levels == c.opt.vgpr_levels;
+        if (dup) continue;
+        Candidate k = c;
+        k.opt.L = 0;
+        cands.push_back(k);
+    }
+    if (cands.empty()) {
+        qrt::set_error("no walk plan for n = " + std::to_string(n));
+        return QUBO_EINVAL;
+    }
+    qubo_result_t ref{}, r0{}, r1{};
+    bool have_ref = false;
+    auto check = [&](const qubo_options_t &o) {
+        if (!have_ref) {
+            ref = r0;
+            have_ref = true;
+        }
+        for (const qubo_result_t *x : {&r0, &r1})
+            if (x->best.energy_i != ref.best.energy_i || x->best.index != ref.best.index) {
+                char buf[200];
+                std::snprintf(buf, sizeof(buf),
+                              "plan invariance violated in a batch at n=%d: B=%d tier=%d "
+                              "vgpr_levels=%d gave (%lld, %llu), expected (%lld, %llu)",
+                              n, o.B, o.tier, o.vgpr_levels, (long long)x->best.energy_i,
+                              (unsigned long long)x->best.index, (long long)ref.best.energy_i,
+                              (unsigned long long)ref.best.index);
+                qrt::set_error(buf);
+                return false;
+            }
+        return true;
+    };
+    for (Candidate &c : cands) {
+        double ms = 0;
+        if ((st = time_batch(ptrs, ns, dts, c.opt, 2, &ms, &r0, &r1)) != QUBO_OK) return st;
+        if (!check(c.opt)) return QUBO_EINTERNAL;
+        c.best_ms = ms;
+    }
+    std::stable_sort(cands.begin(), cands.end(),
+                     [](const Candidate &a, const Candidate &b) { return a.best_ms < b.best_ms; });
+    const size_t top = std::min<size_t>(4, cands.size());
+    if (reps > 0)
+        for (size_t k = 0; k < top; k++) {
+            double ms = 0;
+            if ((st = time_batch(ptrs, ns, dts, cands[k].opt, reps + 1, &ms, &r0, &r1)) != QUBO_OK)
+                return st;
+            if (!check(cands[k].opt)) return QUBO_EINTERNAL;
+            cands[k].best_ms = std::min(cands[k].best_ms, ms);
+        }
+    std::stable_sort(cands.begin(), cands.begin() + long(top),
+                     [](const Candidate &a, const Candidate &b) { return a.best_ms < b.best_ms; });
+    const Candidate *wp = &cands[0];
+    // the built-in plan (tier 2 given explicitly: the table is bypassed)
+    qplan::Plan D;
+    std::string msg;
+    qubo_options_t dopt{};
+    dopt.tier = 2;
+    if (qplan::make_plan(q.data(), n, dtype, &dopt, &D, &msg, true) == QUBO_OK && !D.direct)
+        for (const Candidate &c : cands)
+            if (c.opt.B == D.B && c.opt.tier == D.tier && c.opt.vgpr_levels == D.vgpr_levels &&
+                wp->best_ms >= kBatchMargin * c.best_ms)
+                wp = &c;
+    const Candidate &w = *wp;
+    winner->n = n;
+    winner->dtype = dtype;
+    winner->B = w.opt.B;
+    winner->L = 0;
+    winner->tier = w.opt.tier;
+    winner->vgpr_levels = w.opt.vgpr_levels;
+    winner->walk_ms = w.best_ms;
+    winner->scope = qplan::kScopeBatch;
+    return QUBO_OK;
+}
+
 void to_abi(const qplan::TuneEntry &e, qubo_tune_entry_t *o)
 {
     o->n = e.n;
@@ -498,6 +636,7 @@ void to_abi(const qplan::TuneEntry &e, qubo_tune_entry_t *o)
     o->tier = e.tier;
     o->vgpr_levels = e.vgpr_levels;
     o->walk_ms = e.walk_ms;
+    o->scope = e.scope;
 }
 
 std::once_flag g_autoload_once;
@@ -566,6 +705,7 @@ qubo_status_t qubo_tune_set(const qubo_tune_entry_t *entries, int count)
             e.tier = entries[k].tier;
             e.vgpr_levels = entries[k].vgpr_levels;
             e.walk_ms = entries[k].walk_ms;
+            e.scope = entries[k].scope;
             std::string msg;
             if (!qplan::tune_valid(e, &msg)) {
                 qrt::set_error("entry " + std::to_string(k) + ": " + msg);
@@ -580,10 +720,10 @@ qubo_status_t qubo_tune_set(const qubo_tune_entry_t *entries, int count)
     }
 }
 
-int qubo_tune_lookup(int n, qubo_dtype_t dtype, qubo_tune_entry_t *out)
+int qubo_tune_lookup(int n, qubo_dtype_t dtype, int scope, qubo_tune_entry_t *out)
 {
     qplan::TuneEntry e;
-    if (!qplan::tune_get(n, dtype, &e)) return 0;
+    if (!qplan::tune_get(n, dtype, scope, &e)) return 0;
     if (out) to_abi(e, out);
     return 1;
 }
@@ -646,55 +786,88 @@ qubo_status_t qubo_tune_save(const char *path, const char *device_key)
     }
 }
 
+}  // extern "C"
+
+namespace {
+
+qubo_status_t autotune_range(bool batch, int n_min, int n_max, qubo_dtype_t dtype, int reps,
+                             const char *cache_path, qubo_tune_entry_t *out, int out_cap,
+                             int *out_count)
+{
+    const int hi = batch ? 44 : 48;
+    if (n_min < qplan::kDirectMaxN + 1 || n_max > hi || n_min > n_max) {
+        qrt::set_error("autotune range must satisfy 15 <= n_min <= n_max <= " + std::to_string(hi));
+        return QUBO_EINVAL;
+    }
+    if (dtype != QUBO_INT32 && dtype != QUBO_FP32) {
+        qrt::set_error("unknown dtype");
+        return QUBO_EINVAL;
+    }
+    if (reps < 0 || reps > 100 || out_cap < 0 || (out_cap > 0 && !out)) {
+        qrt::set_error("bad reps or output buffer");
+        return QUBO_EINVAL;
+    }
+    qubo_status_t st;
+    hipStream_t stream = qrt::thread_stream(&st);
+    if (st != QUBO_OK) return st;
+    std::string key;
+    if ((st = current_device_key(&key)) != QUBO_OK) return st;
+    std::vector<qplan::TuneEntry> won;
+    for (int n = n_min; n <= n_max; n++) {
+        qplan::TuneEntry e;
+        st = batch ? tune_batch_one(n, dtype, reps, &e) : tune_one(n, dtype, reps, stream, &e);
+        if (st != QUBO_OK) return st;
+        won.push_back(e);
+    }
+    if (cache_path) {
+        // merge with what the file already holds for this device
+        std::string text, msg;
+        if (read_file(cache_path, &text, &msg)) {
+            std::vector<qplan::TuneEntry> old;
+            if (parse_cache(text, key, &old, &msg))
+                for (const auto &e : old) qplan::tune_put(e);
+        }
+    }
+    for (const auto &e : won) qplan::tune_put(e);
+    if (cache_path) {
+        std::string msg;
+        if (!write_file(cache_path, format_cache(qplan::tune_all(), key), &msg)) {
+            qrt::set_error(msg);
+            return QUBO_EINVAL;
+        }
+    }
+    for (int k = 0; k < out_cap && k < int(won.size()); k++) to_abi(won[size_t(k)], &out[k]);
+    if (out_count) *out_count = int(won.size());
+    return QUBO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 qubo_status_t qubo_autotune(int n_min, int n_max, qubo_dtype_t dtype, int reps,
                             const char *cache_path, qubo_tune_entry_t *out, int out_cap,
                             int *out_count)
 {
     try {
         qrt::set_error("");
-        if (n_min < qplan::kDirectMaxN + 1 || n_max > 48 || n_min > n_max) {
-            qrt::set_error("autotune range must satisfy 15 <= n_min <= n_max <= 48");
-            return QUBO_EINVAL;
-        }
-        if (dtype != QUBO_INT32 && dtype != QUBO_FP32) {
-            qrt::set_error("unknown dtype");
-            return QUBO_EINVAL;
-        }
-        if (reps < 0 || reps > 100 || out_cap < 0 || (out_cap > 0 && !out)) {
-            qrt::set_error("bad reps or output buffer");
-            return QUBO_EINVAL;
-        }
-        qubo_status_t st;
-        hipStream_t stream = qrt::thread_stream(&st);
-        if (st != QUBO_OK) return st;
-        std::string key;
-        if ((st = current_device_key(&key)) != QUBO_OK) return st;
-        std::vector<qplan::TuneEntry> won;
-        for (int n = n_min; n <= n_max; n++) {
-            qplan::TuneEntry e;
-            if ((st = tune_one(n, dtype, reps, stream, &e)) != QUBO_OK) return st;
-            won.push_back(e);
-        }
-        if (cache_path) {
-            // merge with what the file already holds for this device
-            std::string text, msg;
-            if (read_file(cache_path, &text, &msg)) {
-                std::vector<qplan::TuneEntry> old;
-                if (parse_cache(text, key, &old, &msg))
-                    for (const auto &e : old) qplan::tune_put(e);
-            }
-        }
-        for (const auto &e : won) qplan::tune_put(e);
-        if (cache_path) {
-            std::string msg;
-            if (!write_file(cache_path, format_cache(qplan::tune_all(), key), &msg)) {
-                qrt::set_error(msg);
-                return QUBO_EINVAL;
-            }
-        }
-        for (int k = 0; k < out_cap && k < int(won.size()); k++) to_abi(won[size_t(k)], &out[k]);
-        if (out_count) *out_count = int(won.size());
-        return QUBO_OK;
+        return autotune_range(false, n_min, n_max, dtype, reps, cache_path, out, out_cap, out_count);
+    } catch (const std::bad_alloc &) {
+        qrt::set_error("host allocation failed");
+        return QUBO_ENOMEM;
+    } catch (...) {
+        qrt::set_error("unexpected exception");
+        return QUBO_EINTERNAL;
+    }
+}
+
+qubo_status_t qubo_autotune_batch(int n_min, int n_max, qubo_dtype_t dtype, int reps,
+                                  const char *cache_path, qubo_tune_entry_t *out, int out_cap,
+                                  int *out_count)
+{
+    try {
+        qrt::set_error("");
+        return autotune_range(true, n_min, n_max, dtype, reps, cache_path, out, out_cap, out_count);
     } catch (const std::bad_alloc &) {
         qrt::set_error("host allocation failed");
         return QUBO_ENOMEM;

@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 # (B, vgpr_levels, tier): every built walk variant in both tiers, cycled over n
 VARIANTS = [(10, 4, 2), (10, 5, 1), (9, 8, 2), (8, 12, 1), (10, 8, 2), (7, 12, 2),
             (10, 12, 1), (6, 12, 2), (9, 12, 1), (10, 6, 1), (10, 5, 2), (9, 8, 1),
-            (10, 4, 1), (10, 6, 2)]
+            (10, 4, 1), (10, 6, 2), (10, 3, 2), (10, 3, 1)]
 
 
 @pytest.fixture()
@@ -24,9 +24,10 @@ def q():
     q.tune_clear()
 
 
-def _table(ns, dtype="int32"):
+def _table(ns, dtype="int32", scope="batch"):
     return [{"n": n, "dtype": dtype, "B": VARIANTS[k % len(VARIANTS)][0], "L": 0,
-             "tier": VARIANTS[k % len(VARIANTS)][2], "vgpr_levels": VARIANTS[k % len(VARIANTS)][1]}
+             "tier": VARIANTS[k % len(VARIANTS)][2], "vgpr_levels": VARIANTS[k % len(VARIANTS)][1],
+             "scope": scope}
             for k, n in enumerate(ns)]
 
 
@@ -76,7 +77,7 @@ def test_batch_with_mixed_variants(q, orc):
         for Q, r in zip(Qs, res):
             n = Q.shape[0]
             if n > 14:
-                e = q.tune_lookup(n, "fp32" if Q.dtype == np.float32 else "int32")
+                e = q.tune_lookup(n, "fp32" if Q.dtype == np.float32 else "int32", "batch")
                 assert (r.B, r.tier, r.vgpr_levels) == (e["B"], e["tier"], e["vgpr_levels"])
             _check(orc, Q, r)
         print(f"mixed-variant batch replay {rep}: {len(res)} ok", flush=True)
@@ -93,8 +94,46 @@ def test_server_with_mixed_variants(q, orc):
     for Q, t in zip(Qs, tickets):
         r = srv.wait(t, timeout_ms=60000)
         assert r is not None
-        e = q.tune_lookup(Q.shape[0], "fp32" if Q.dtype == np.float32 else "int32")
+        e = q.tune_lookup(Q.shape[0], "fp32" if Q.dtype == np.float32 else "int32", "batch")
         assert (r.B, r.tier, r.vgpr_levels) == (e["B"], e["tier"], e["vgpr_levels"])
         _check(orc, Q, r)
     srv.close()
     print(f"mixed-variant server: {len(Qs)} ok", flush=True)
+
+
+def test_single_scope_entries_do_not_steer_batches(q, orc):
+    """A lone-solve entry leaves batch instances on the built-in plan and vice versa."""
+    q.tune_set([{"n": 22, "B": 7, "L": 0, "tier": 1, "vgpr_levels": 12, "scope": "single"},
+                {"n": 23, "B": 8, "L": 0, "tier": 1, "vgpr_levels": 12, "scope": "batch"}])
+    Q22, Q23 = inputs.uniform_int(22, -100, 100, 901), inputs.uniform_int(23, -100, 100, 902)
+    lone22, lone23 = q.solve(Q22), q.solve(Q23)
+    assert (lone22.B, lone22.tier) == (7, 1)
+    assert (lone23.B, lone23.vgpr_levels) == (10, 4)
+    b = q.Batch([Q22, Q23])
+    b.run()
+    r22, r23 = b.results()
+    b.close()
+    assert (r22.B, r22.vgpr_levels) == (10, 4)
+    assert (r23.B, r23.tier) == (8, 1)
+    for Q, r in ((Q22, r22), (Q23, r23), (Q22, lone22), (Q23, lone23)):
+        _check(orc, Q, r)
+
+
+def test_batch_autotune(q, orc, tmp_path):
+    path = str(tmp_path / "tune.json")
+    won = q.autotune(20, 21, "int32", reps=0, cache_path=path, batch=True)
+    assert [(e["n"], e["scope"], e["L"]) for e in won] == [(20, "batch", 0), (21, "batch", 0)]
+    doc = json.load(open(path))
+    assert sorted((x["n"], x["scope"]) for x in doc["entries"]) == [(20, "batch"), (21, "batch")]
+    q.tune_clear()
+    assert q.tune_load(path) == 2
+    assert q.tune_lookup(20) is None
+    Qs = [inputs.uniform_int(n, -100, 100, 950 + n) for n in (20, 21, 20)]
+    b = q.Batch(Qs)
+    b.run()
+    for Q, r in zip(Qs, b.results()):
+        e = q.tune_lookup(Q.shape[0], "int32", "batch")
+        assert (r.B, r.tier, r.vgpr_levels) == (e["B"], e["tier"], e["vgpr_levels"])
+        _check(orc, Q, r)
+    b.close()
+    print(f"batch-tuned: {won}", flush=True)

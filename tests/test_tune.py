@@ -87,7 +87,7 @@ def test_save_load_roundtrip(q, tmp_path):
     q.tune_clear()
     assert q.tune_load(path, KEY) == 2
     assert q.tune_lookup(20) == {"n": 20, "dtype": "int32", "B": 7, "L": 9, "tier": 1,
-                                 "vgpr_levels": 12, "walk_ms": 0.25}
+                                 "vgpr_levels": 12, "walk_ms": 0.25, "scope": "single"}
     e = q.tune_lookup(33, "fp32")
     assert (e["B"], e["vgpr_levels"], e["tier"]) == (10, 5, 2)
     assert q.tune_lookup(33, "int32") is None
@@ -149,3 +149,36 @@ def test_autotune_argument_checks(q):
         with pytest.raises(q.QuboError) as ei:
             q.autotune(*args)
         assert ei.value.status == -1
+
+
+def test_scopes_are_separate_tables(q, tmp_path):
+    q.tune_set([{"n": 30, "B": 8, "L": 0, "tier": 1, "vgpr_levels": 12, "scope": "batch"}])
+    assert q.tune_lookup(30) is None                       # single scope untouched
+    assert q.tune_lookup(30, "int32", "batch")["B"] == 8
+    assert _plan(q, 30)["B"] == 10                         # lone-solve plans ignore batch entries
+    q.tune_set([{"n": 30, "B": 9, "L": 11, "tier": 2, "vgpr_levels": 8}])
+    assert _plan(q, 30)["B"] == 9
+    assert q.tune_lookup(30, "int32", "batch")["B"] == 8
+    path = str(tmp_path / "tune.json")
+    q.tune_save(path, KEY)
+    doc = json.load(open(path))
+    assert sorted((e["scope"], e["B"]) for e in doc["entries"]) == [("batch", 8), ("single", 9)]
+    q.tune_clear()
+    assert q.tune_load(path, KEY) == 2
+    assert q.tune_lookup(30)["B"] == 9 and q.tune_lookup(30, "int32", "batch")["B"] == 8
+
+
+def test_batch_entries_keep_the_batch_item_size(q):
+    with pytest.raises(q.QuboError):
+        q.tune_set([{"n": 30, "B": 8, "L": 12, "tier": 1, "vgpr_levels": 12, "scope": "batch"}])
+    assert q.tune_lookup(30, "int32", "batch") is None
+
+
+def test_unknown_scope_in_cache_rejected(q, tmp_path):
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"format": "qubo-tune-1", "device": KEY, "entries": [
+        {"n": 30, "dtype": "int32", "B": 8, "L": 0, "tier": 1, "vgpr_levels": 12,
+         "scope": "both"}]}))
+    with pytest.raises(q.QuboError) as ei:
+        q.tune_load(str(path), KEY)
+    assert "scope" in ei.value.message
