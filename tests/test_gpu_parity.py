@@ -181,6 +181,47 @@ def test_headline_sampled_items(q, orc):
     assert pairs == [(int(e), int(i)) for e, i in orc.solve_range(Q, _gray(c0) * span, span, k=16)]
 
 
+def _gray_inverse(g):
+    c = 0
+    while g:
+        c ^= g
+        g >>= 1
+    return c
+
+
+@pytest.mark.parametrize("n,lo", [(54, -1000), (50, -10000)])
+def test_large_n_sampled_items(q, orc, n, lo):
+    """n = 54 and 50 in their own plans (A = n - 10 prefix bits, the smallest
+    items the planner allows: 2^(A-20) Gray steps, one wave each).  A planted
+    instance is solved on the work item that holds its ground state, which
+    the solve must return, and on a neighbouring item, whose answer must be
+    a state of that item's index block with the oracle's energy, above the
+    ground state, and with no single flip inside the block improving it (or
+    tying it at a lower index)."""
+    Q, xstar = inputs.planted(n, lo, -lo, 60 + n)
+    istar = orc.index_of(xstar)
+    L = n - 10 - 20
+    info = q.plan_info(Q, L=L)
+    B, items = info["B"], info["items"]
+    assert (info["A"], B, info["L"], items) == (n - 10, 10, L, 1 << 20)
+    span = 1 << (L + B)
+    c = _gray_inverse(istar >> (L + B))
+    assert _gray(c) == istar >> (L + B)
+    got = q.solve(Q, L=L, item_first=c, item_count=1)
+    print(f"n={n} item {c}: {got.energy_i} @ {got.index} (planted {istar}) "
+          f"{got.kernel_ms:.1f} ms", flush=True)
+    assert got.index == istar and got.energy_i == orc.energy(Q, istar)
+    c2 = c + 1 if c + 1 < items else c - 1
+    r = q.solve(Q, L=L, item_first=c2, item_count=1)
+    base = _gray(c2) * span
+    assert base <= r.index < base + span
+    assert r.energy_i == orc.energy(Q, r.index) and r.energy_i > got.energy_i
+    for b in range(L + B):                                # flips that stay in the block
+        j = r.index ^ (1 << b)
+        ej = orc.energy(Q, j)
+        assert ej > r.energy_i or (ej == r.energy_i and j > r.index), (b, ej)
+
+
 def test_algebraic_invariances(q, orc):
     """End to end through the walk (n = 26): relabelling the variables
     permutes the argmin, E(cQ) = c E(Q) for an integer c > 0, and the
