@@ -217,7 +217,14 @@ qubo_status_t enqueue_tick(qubo_server *s, TickBuf &t, bool *launched)
         return a->job.plans[0].items - a->next_item < b->job.plans[0].items - b->next_item;
     });
     std::vector<uint64_t> share(walkers.size(), 0);
-    uint64_t budget = s->tick_items, total = 0;
+    // Under a backlog of more than four ticks' work the tick doubles, and
+    // past sixteen it quadruples: fewer tick boundaries (each costs a drain
+    // of the walk grid and a finish launch), at no cost in latency since
+    // requests queue anyway.
+    uint64_t backlog = 0;
+    for (Request *r : walkers) backlog += r->job.plans[0].items - r->next_item;
+    const uint64_t scale = backlog > 16 * s->tick_items ? 4 : (backlog > 4 * s->tick_items ? 2 : 1);
+    uint64_t budget = scale * s->tick_items, total = 0;
     for (size_t k = 0; k < walkers.size(); k++) {
         Request *r = walkers[k];
         const uint64_t left = r->job.plans[0].items - r->next_item;
