@@ -209,9 +209,9 @@ def main():
         print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for {args.gpus}); the solve "
-              "shards by Gray-index range across GPUs with one 8-byte MIN reduction, which is "
-              "not built here.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the solve would shard "
+              "by Gray-index range across GPUs with one MIN reduction of an (energy, row) "
+              "pair, which is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch

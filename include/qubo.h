@@ -324,7 +324,7 @@ qubo_status_t qubo_autotune_batch(int n_min, int n_max, qubo_dtype_t dtype, int 
 
 /* Load a cache file into the process table.  device_key: the key the file
  * must carry; NULL = this device's key (qubo_device_key).  A file made on
- * another device, malformed JSON or an entry naming a plan this build cannot
+ * another device, malformed JSON or an entry naming a plan the library's kernels cannot
  * run is rejected as a whole with QUBO_EINVAL.  *loaded = entries read. */
 qubo_status_t qubo_tune_load(const char *path, const char *device_key, int *loaded);
 

@@ -64,7 +64,7 @@ bool tune_get(int n, qubo_dtype_t dtype, int scope, TuneEntry *out);
 void tune_clear();
 std::vector<TuneEntry> tune_all();
 
-// Check that a tuning entry describes a plan this build can run.
+// Check that a tuning entry describes a plan whose kernel variant the library compiles.
 bool tune_valid(const TuneEntry &e, std::string *msg);
 
 // Build a plan from a host Q.  Returns QUBO_OK or an error with msg set.

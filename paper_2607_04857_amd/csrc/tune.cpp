@@ -6,7 +6,7 @@
 // trades VGPRs for resident waves), the bound tier and the work-item size L.
 // The paper reports reaching its kernel's speed by extensive experimentation
 // on its GPU (Sec. IV); here that experimentation is a function: time every
-// plan this build can run on a synthetic instance of each n, keep the
+// plan the library's kernels can run on a synthetic instance of each n, keep the
 // fastest, and let the planner use it.  Every candidate must return the same
 // (E*, index*) -- plan invariance is checked on every tuning run.
 //
@@ -397,7 +397,7 @@ struct Candidate {
     double best_ms = 1e300;
 };
 
-// Every plan this build can run for n: suffix widths, row caches, tiers and
+// Every plan the library's kernels can run for n: suffix widths, row caches, tiers and
 // work-item sizes around the default.
 qubo_status_t candidates(const void *Q, int n, qubo_dtype_t dtype, std::vector<Candidate> *out)
 {
