@@ -36,6 +36,7 @@ constexpr int kKBound = kKC2Min + 4;     // bound constants at the head of a K t
 constexpr int kKTable = kKBound + 4 * kWave;  // + SL[w][t], t < 4: ints per K table
 constexpr int kMaxVgprLevels = 12;    // at most Gray levels 0..11 keep their M_int row in VGPRs
 constexpr int32_t kNoEnergy = 1 << 30;  // above every energy the walk can meet
+constexpr int kMaxVars = 60;          // largest n the planner accepts
 constexpr int kMaxPrefixRows = 60 - 6;   // A = n - B <= 60 - 6
 
 struct ItemRes;

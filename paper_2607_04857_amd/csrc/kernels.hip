@@ -1064,14 +1064,24 @@ __global__ __launch_bounds__(256) void finish_kernel(const Inst *__restrict__ in
 {
     __shared__ int64_t sE[256];
     __shared__ uint64_t sI[256];
+    // T (and the caller's float32 Q) staged in LDS: every energy below reads
+    // O(n^2) entries, and the float64 rescore runs on one thread in a fixed
+    // order, where global-memory latency would dominate
+    __shared__ int32_t sT[kMaxVars * kMaxVars];
+    __shared__ float sQ[kMaxVars * kMaxVars];
     const Inst I = insts[blockIdx.x];
     const int n = I.n;
+    for (int e = int(threadIdx.x); e < n * n; e += int(blockDim.x)) {
+        sT[e] = I.T[e];
+        if (I.Qf) sQ[e] = I.Qf[e];
+    }
+    __syncthreads();
     int64_t bE = INT64_MAX;
     uint64_t bI = ~0ull;
     int32_t status = 0;
     if (I.direct) {
         const uint64_t N = 1ull << n;
-        for (uint64_t r = threadIdx.x; r < N; r += blockDim.x) lexmin(bE, bI, energy_int(I.T, n, r), r);
+        for (uint64_t r = threadIdx.x; r < N; r += blockDim.x) lexmin(bE, bI, energy_int(sT, n, r), r);
         block_lexmin(bE, bI, sE, sI);
     } else {
         for (uint64_t k = threadIdx.x; k < I.n_items; k += blockDim.x) {
@@ -1091,7 +1101,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const Inst *__restrict__ in
             const uint32_t NS = 1u << I.B;
             for (uint32_t s = threadIdx.x; s < NS; s += blockDim.x) {
                 const uint64_t idx = (rowstar << I.B) | s;
-                const int64_t e = energy_int(I.T, n, idx);
+                const int64_t e = energy_int(sT, n, idx);
                 if (e == Estar) lexmin(bE, bI, e, idx);
             }
             block_lexmin(bE, bI, sE, sI);
@@ -1102,7 +1112,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const Inst *__restrict__ in
         FinalRes o;
         o.E = bE;
         o.index = bI;
-        o.E64 = (I.Qf && status == 0) ? energy_f64(I.Qf, n, bI) : double(bE);
+        o.E64 = (I.Qf && status == 0) ? energy_f64(sQ, n, bI) : double(bE);
         o.status = status;
         o.pad = 0;
         out[blockIdx.x] = o;

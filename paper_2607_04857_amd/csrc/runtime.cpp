@@ -7,6 +7,8 @@
 #include <algorithm>
 #include <mutex>
 
+static_assert(qk::kMaxVars == qplan::kMaxN, "finish kernel LDS sized for the largest n");
+
 namespace qrt {
 
 namespace {

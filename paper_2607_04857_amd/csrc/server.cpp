@@ -74,6 +74,7 @@ struct qubo_server {
     uint64_t tick_items = 0;      // work items per tick (two per resident wave)
     hipStream_t stream = nullptr;
     int32_t *d_karena = nullptr;  // max_slots K tables
+    qk::Inst *d_setup = nullptr;  // descriptors of the requests admitted in one round
     unsigned long long *d_counter = nullptr;
     std::vector<int> free_kslots;
     TickBuf ticks[2];
@@ -185,7 +186,24 @@ qubo_status_t setup_request(qubo_server *s, Request *r)
     QRT_HIP(hipMemcpyAsync(r->d_mem, r->job.stage.data(), r->job.stage_bytes, hipMemcpyHostToDevice,
                            s->stream),
             "hipMemcpyAsync H2D");
-    QRT_HIP(qk::launch_tables(r->job.d_insts, 1, r->job.max_A, nullptr, 0, s->stream), "tables kernel");
+    return QUBO_OK;
+}
+
+// One table-build launch for every request admitted in a round: their
+// descriptors are gathered device-to-device into one array, so the builds
+// run side by side instead of one small launch after another.
+qubo_status_t build_tables(qubo_server *s, const std::vector<Request *> &adm)
+{
+    if (adm.empty()) return QUBO_OK;
+    int max_A = 0;
+    for (size_t k = 0; k < adm.size(); k++) {
+        QRT_HIP(hipMemcpyAsync(s->d_setup + k, adm[k]->job.d_insts, sizeof(qk::Inst),
+                               hipMemcpyDeviceToDevice, s->stream),
+                "hipMemcpyAsync descriptor");
+        max_A = std::max(max_A, adm[k]->job.max_A);
+    }
+    QRT_HIP(qk::launch_tables(s->d_setup, int(adm.size()), max_A, nullptr, 0, s->stream),
+            "tables kernel");
     return QUBO_OK;
 }
 
@@ -327,6 +345,10 @@ void scheduler(qubo_server *s)
                 return;
             }
         }
+        if (build_tables(s, adm) != QUBO_OK) {
+            fail_all(s, qrt::last_error_cstr());
+            return;
+        }
         TickBuf &t = s->ticks[s->cur];
         if (t.inflight) {
             // the buffer's previous tick was enqueued two ticks ago
@@ -379,6 +401,7 @@ void server_free(qubo_server *s)
         delete kv.second;
     }
     if (s->d_karena) (void)hipFree(s->d_karena);
+    if (s->d_setup) (void)hipFree(s->d_setup);
     if (s->d_counter) (void)hipFree(s->d_counter);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
@@ -399,6 +422,7 @@ qubo_status_t server_init(qubo_server *s, size_t budget, int max_slots)
     s->tick_items = uint64_t(di.cus) * uint64_t(qk::walk_occupancy(16, 4, 2)) * 2;
     QRT_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "hipStreamCreate");
     QRT_HIP(hipMalloc(&s->d_karena, size_t(max_slots) * qk::kKTable * sizeof(int32_t)), "hipMalloc");
+    QRT_HIP(hipMalloc(&s->d_setup, size_t(max_slots) * sizeof(qk::Inst)), "hipMalloc");
     // one item counter per walk variant launched in a tick
     QRT_HIP(hipMalloc(&s->d_counter, kMaxTickLaunches * sizeof(unsigned long long)), "hipMalloc");
     for (int k = max_slots - 1; k >= 0; k--) s->free_kslots.push_back(k);
