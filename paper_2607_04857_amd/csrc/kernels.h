@@ -104,7 +104,7 @@ struct TopkBufs {
     int32_t *chunkCount; // [1] chunks selected (min(k, chunks met))
     int32_t *stE;        // [k << B] (or [2^n] direct) candidate state energies
     uint64_t *stI;       // same, U_N rows
-    int32_t *segCount;   // [k] states per rescanned chunk ([0] = 2^n direct)
+    int32_t *segCount;   // [0]: states kept by the rescan (2^n when direct)
     int32_t *selE;       // [k] the k smallest states, sorted by (E, index)
     uint64_t *selR;
     int32_t *selCount;   // [1]

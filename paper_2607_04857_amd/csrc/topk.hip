@@ -12,7 +12,9 @@
 //   2. compact the list entries at or below the final shared bound, and
 //      select the k smallest chunk keys among them;
 //   3. rescan those chunks: every state's energy from the tables,
-//      E = E_p(row) + E_s(s) + x_p M_int[:, s] (Sec. II-C);
+//      E = E_p(row) + E_s(s) + x_p M_int[:, s] (Sec. II-C), keeping the
+//      states at or below the largest selected chunk key (the k chunk minima
+//      are k states at or below it, so the k-th smallest energy is too);
 //   4. select the k smallest (E, index) among them, sorted;
 //   5. verify each energy from T, rescore fp32 instances in float64 and sort
 //      those by (E64, index).
@@ -38,6 +40,7 @@ struct SelArgs {
     int32_t *oE;               // [k] output, sorted by (E, R)
     uint64_t *oR;
     int32_t *oCount;
+    int32_t *clear;            // set to 0 when done (a later kernel's counter), or null
 };
 
 __device__ __forceinline__ uint32_t ukey(int32_t e) { return uint32_t(e) ^ 0x80000000u; }
@@ -175,7 +178,10 @@ __global__ __launch_bounds__(kSelThreads) void topk_select_kernel(SelArgs a)
         a.oE[tid] = sE[tid];
         a.oR[tid] = sR[tid];
     }
-    if (tid == 0) *a.oCount = int32_t(cnt);
+    if (tid == 0) {
+        *a.oCount = int32_t(cnt);
+        if (a.clear) *a.clear = 0;
+    }
 }
 
 // The walk lists, compacted: entries with E <= *bound of every wave's list,
@@ -211,23 +217,26 @@ __global__ __launch_bounds__(256) void topk_compact_kernel(const int32_t *__rest
     }
 }
 
-// Step 3: block b rescans chunk rows[b] (if b < *rowCount).
+// Step 3: block b rescans chunk rows[b] (if b < *rowCount) and appends its
+// states with E <= the largest selected chunk key to (stE, stI), densely
+// (wave-aggregated slots counted in *stCount, zeroed by the chunk select).
 __global__ __launch_bounds__(256) void topk_rescan_kernel(const Inst *__restrict__ inst,
                                                           const uint64_t *__restrict__ rows,
+                                                          const int32_t *__restrict__ rowE,
                                                           const int32_t *__restrict__ rowCount,
                                                           int32_t *__restrict__ stE,
                                                           uint64_t *__restrict__ stI,
-                                                          int32_t *__restrict__ segCount)
+                                                          int32_t *__restrict__ stCount)
 {
     __shared__ int64_t red[256];
     const Inst I = *inst;
     const int n = I.n, A = I.A, B = I.B;
     const uint32_t NS = 1u << B;
     const uint32_t b = blockIdx.x;
-    if (int32_t(b) >= *rowCount) {
-        if (threadIdx.x == 0) segCount[b] = 0;
-        return;
-    }
+    const int32_t rc = *rowCount;
+    if (int32_t(b) >= rc) return;
+    const int32_t bound = rowE[rc - 1];   // rows are sorted by (key, row)
+    const int lane = int(threadIdx.x) & (kWave - 1);
     const uint64_t row = rows[b];
     // E_p(row) = sum over set prefix bits i <= j of T[i][j]; prefix variable
     // v is bit A-1-v of the U_A row.
@@ -244,14 +253,23 @@ __global__ __launch_bounds__(256) void topk_rescan_kernel(const Inst *__restrict
         __syncthreads();
     }
     const int32_t Ep = int32_t(red[0]);
+    // NS is a multiple of 64: every lane of a wave that enters runs each pass
     for (uint32_t s = threadIdx.x; s < NS; s += blockDim.x) {
         int32_t e = Ep + I.EB[s];
         for (int v = 0; v < A; v++)
             if ((row >> (A - 1 - v)) & 1) e += I.M[uint32_t(v) * NS + s];
-        stE[size_t(b) * NS + s] = e;
-        stI[size_t(b) * NS + s] = (row << B) | s;
+        const bool keep = e <= bound;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
+        if (!m) continue;
+        int base = 0;
+        if (lane == 0) base = atomicAdd(stCount, int(__builtin_popcountll(m)));
+        base = __builtin_amdgcn_readfirstlane(base);
+        if (keep) {
+            const int p = base + int(__builtin_popcountll(m & ((1ull << lane) - 1)));
+            stE[p] = e;
+            stI[p] = (row << B) | s;
+        }
     }
-    if (threadIdx.x == 0) segCount[b] = int32_t(NS);
 }
 
 // Step 3 for direct instances: every state.
@@ -376,11 +394,12 @@ hipError_t launch_topk_finish(const Inst *d_inst, const Inst &hI, const TopkBufs
         ch.oE = buf.chunkE;
         ch.oR = buf.chunkR;
         ch.oCount = buf.chunkCount;
+        ch.clear = buf.segCount;     // [0]: the rescan's state counter
         hipLaunchKernelGGL(topk_select_kernel, dim3(1), dim3(kSelThreads), 0, stream, ch);
         hipLaunchKernelGGL(topk_rescan_kernel, dim3(k), dim3(256), 0, stream, d_inst, buf.chunkR,
-                           buf.chunkCount, buf.stE, buf.stI, buf.segCount);
-        st.count = buf.chunkCount;   // rescanned chunks are the leading ones, full
-        st.mult = 1u << hI.B;
+                           buf.chunkE, buf.chunkCount, buf.stE, buf.stI, buf.segCount);
+        st.count = buf.segCount;     // states kept by the rescan, densely
+        st.mult = 1;
     }
     st.E = buf.stE;
     st.R = buf.stI;
