@@ -246,7 +246,8 @@ qubo_status_t qubo_checkpoint_info(const char *path, qubo_checkpoint_t *info);
  * with one scalar add per two vector adds, 3: v_add_u32 with one never-taken
  * scalar compare-and-branch per 16 vector adds, 4: v_pk_add_u16, 5:
  * v_pk_min_i16, 6: v_add_u32 with a register footprint that admits at most 3
- * waves per SIMD) with waves_per_simd resident waves on every SIMD and reports
+ * waves per SIMD, 7: v_add_f32) with waves_per_simd resident waves on every
+ * SIMD and reports
  * vector lane-operations per second (a packed instruction counts once per
  * lane) and the kernel time. */
 qubo_status_t qubo_probe_valu(int op, int waves_per_simd, int iters, double *lane_ops_per_s,

@@ -407,10 +407,11 @@ def probe_valu(op: str = "add", waves_per_simd: int = 4, iters: int = 4096):
     op: 'add', 'min3', 'add+salu' (a scalar add per two vector adds),
     'add+branch' (a never-taken compare/branch per 16 vector adds), 'pk_add16'
     'pk_min16' (packed 16-bit pairs; one lane-op covers two values) or 'add_3w'
-    (adds with a register footprint that admits at most 3 waves per SIMD)."""
+    (adds with a register footprint that admits at most 3 waves per SIMD) or
+    'add_f32' (scalar float32 adds)."""
     rate, ms = ctypes.c_double(), ctypes.c_double()
     ops = {"add": 0, "min3": 1, "add+salu": 2, "add+branch": 3, "pk_add16": 4, "pk_min16": 5,
-           "add_3w": 6}
+           "add_3w": 6, "add_f32": 7}
     _check(lib().qubo_probe_valu(ops[op], int(waves_per_simd), int(iters),
                                  ctypes.byref(rate), ctypes.byref(ms)))
     return rate.value, ms.value

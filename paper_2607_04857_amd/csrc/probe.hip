@@ -8,8 +8,9 @@
 // v_pk_add_u16; 5 v_pk_min_i16; 6 v_add_u32 over 160 accumulators, whose
 // register footprint admits at most 3 waves per SIMD (the walk's occupancy:
 // with few registers the dispatcher may place 4 waves on some SIMDs and 2 on
-// others when 3 per SIMD are launched).  Vector instructions x 64 lanes are
-// counted (a packed instruction is one lane-operation on two 16-bit halves).
+// others when 3 per SIMD are launched); 7 v_add_f32 (scalar float32, the
+// add a float walk would use).  Vector instructions x 64 lanes are counted
+// (a packed instruction is one lane-operation on two 16-bit halves).
 #include <hip/hip_runtime.h>
 
 #include "runtime.h"
@@ -24,8 +25,10 @@ __global__ __launch_bounds__(64) void valu_probe_kernel(int iters, int32_t *__re
     constexpr int NR = OP == 6 ? 1 : 16;
     int32_t a[NA];
 #pragma unroll
-    for (int k = 0; k < NA; k++) a[k] = int32_t(threadIdx.x) * 7 + k;
-    const int32_t b = int32_t(blockIdx.x) | 1, c = int32_t(threadIdx.x) ^ 5;
+    for (int k = 0; k < NA; k++)
+        a[k] = OP == 7 ? __float_as_int(float(k)) : int32_t(threadIdx.x) * 7 + k;
+    const int32_t b = OP == 7 ? __float_as_int(1.0f) : (int32_t(blockIdx.x) | 1);
+    const int32_t c = int32_t(threadIdx.x) ^ 5;
     int32_t sc = int32_t(blockIdx.x);   // scalar work for OP 2 and 3 (wave-uniform)
     for (int it = 0; it < iters; it++) {
 #pragma unroll
@@ -38,6 +41,8 @@ __global__ __launch_bounds__(64) void valu_probe_kernel(int iters, int32_t *__re
                     asm volatile("v_pk_add_u16 %0, %0, %1" : "+v"(a[k]) : "v"(b));
                 else if constexpr (OP == 5)
                     asm volatile("v_pk_min_i16 %0, %0, %1" : "+v"(a[k]) : "v"(b));
+                else if constexpr (OP == 7)
+                    asm volatile("v_add_f32 %0, %1, %0" : "+v"(a[k]) : "v"(b));
                 else
                     asm volatile("v_add_u32 %0, %1, %0" : "+v"(a[k % NA]) : "v"(b));
                 if constexpr (OP == 2)   // one scalar add per two vector adds
@@ -60,7 +65,7 @@ extern "C" qubo_status_t qubo_probe_valu(int op, int waves_per_simd, int iters,
                                          double *lane_ops_per_s, double *ms)
 {
     qrt::set_error("");
-    if (op < 0 || op > 6 || waves_per_simd < 1 || waves_per_simd > 8 || iters < 1) {
+    if (op < 0 || op > 7 || waves_per_simd < 1 || waves_per_simd > 8 || iters < 1) {
         qrt::set_error("bad probe arguments");
         return QUBO_EINVAL;
     }
@@ -95,8 +100,10 @@ extern "C" qubo_status_t qubo_probe_valu(int op, int waves_per_simd, int iters,
                 hipLaunchKernelGGL(valu_probe_kernel<4>, dim3(blocks), dim3(64), 0, s, iters, d_out);
             else if (op == 5)
                 hipLaunchKernelGGL(valu_probe_kernel<5>, dim3(blocks), dim3(64), 0, s, iters, d_out);
-            else
+            else if (op == 6)
                 hipLaunchKernelGGL(valu_probe_kernel<6>, dim3(blocks), dim3(64), 0, s, iters, d_out);
+            else
+                hipLaunchKernelGGL(valu_probe_kernel<7>, dim3(blocks), dim3(64), 0, s, iters, d_out);
             (void)hipEventRecord(e1, s);
         }
         if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess ||
