@@ -158,3 +158,18 @@ def test_item_range_options_validated_on_host():
         assert ei.value.status == -1
     with pytest.raises(q.QuboError):
         q.plan_info(inputs.uniform_int(12, -100, 100, 5), item_first=0, item_count=1)
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/qubo.h is a C ABI: it compiles as C99 with warnings as errors."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use_header.c"
+    src.write_text('#include "qubo.h"\n'
+                   "int main(void) { qubo_result_t r; qubo_checkpoint_t c; qubo_tune_entry_t e;\n"
+                   "  (void)r; (void)c; (void)e; return (int)sizeof(qubo_options_t) == 32 ? 0 : 1; }\n")
+    subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-fsyntax-only",
+                    "-I", os.path.join(ROOT, "include"), str(src)], check=True)
