@@ -61,3 +61,24 @@ def test_planted_n46_in_slices(tmp_path, orc):
     r = q.solve_checkpointed(Q, f, items_per_slice=items // 4)
     print(f"planted n=46: index {r.index} expected {idx}, E {r.energy_i}", flush=True)
     assert r.index == idx and r.energy_i == orc.energy(Q, idx)
+
+
+def test_resume_keeps_the_recorded_plan(tmp_path):
+    """A tuning entry installed between two calls does not change the plan of
+    a solve already in progress: the resumed slices run the recorded one."""
+    import paper_2607_04857_amd as q
+    Q = inputs.uniform_int(36, -1000, 1000, 36)
+    whole = q.solve(Q)
+    f = str(tmp_path / "n36.ckpt")
+    items = q.plan_info(Q)["items"]
+    q.tune_clear()
+    try:
+        assert q.solve_checkpointed(Q, f, items_per_slice=items // 4, max_slices=2) is None
+        q.tune_set([{"n": 36, "B": 8, "L": 0, "tier": 1, "vgpr_levels": 12}])
+        assert q.plan_info(Q)["B"] == 8                    # a fresh solve would use it
+        r = q.solve_checkpointed(Q, f, items_per_slice=items // 4)
+    finally:
+        q.tune_clear()
+    d = q.checkpoint_info(f)
+    assert (r.B, d["B"], d["items"]) == (whole.B, whole.B, items)
+    assert (r.energy_i, r.index) == (whole.energy_i, whole.index)
