@@ -474,11 +474,12 @@ qubo_status_t solve_host(const void *Q, int n, qubo_dtype_t dtype, int k, const 
         qplan::Plan &P = job.plans[0];
         if (!P.direct) {
             P.tier = 3;
-            // The LDS row cache shares LDS with the list: when both no longer
-            // fit four waves per SIMD, the VGPR row cache (three waves) wins.
-            if ((P.vgpr_levels == 4 || P.vgpr_levels == 3) && !(opt && opt->vgpr_levels) &&
-                qk::walk_occupancy(P.mcols, P.vgpr_levels, 3, k) < 4 * 4)
-                P.vgpr_levels = 6;
+            // The LDS row cache shares LDS with the list.  While both fit four
+            // waves per SIMD the variant with levels 0-2 in VGPRs is the
+            // fastest top-k walk (its registers leave room for the list
+            // code); beyond that the VGPR row cache (three waves) wins.
+            if ((P.vgpr_levels == 4 || P.vgpr_levels == 3) && !(opt && opt->vgpr_levels))
+                P.vgpr_levels = qk::walk_occupancy(P.mcols, 3, 3, k) >= 4 * 4 ? 3 : 6;
         }
     }
     st = solve_planned(job, stream, opt ? opt->waves_per_cu : 0, out, topk);
