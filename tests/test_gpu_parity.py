@@ -163,14 +163,15 @@ def test_headline_sampled_items(q, orc):
     """The n = 44 headline instance in its own plan and kernel, checked on
     sampled work items: item c covers the contiguous index range
     [g(c) 2^(L+B), (g(c)+1) 2^(L+B)) of 2^26 states, which the oracle
-    evaluates exhaustively."""
+    evaluates exhaustively: the first and last pairs of items and ten random
+    pairs (2^31 states in all)."""
     Q = inputs.uniform_int(44, -10000, 10000, 4)
     info = q.plan_info(Q)
     L, B, items = info["L"], info["B"], info["items"]
     assert (info["A"], B, L, items) == (34, 10, 16, 1 << 18)
     span = 1 << (L + B)
     rng = np.random.default_rng(44)
-    firsts = [0, items - 2] + [int(c) for c in rng.integers(0, items - 2, 3)]
+    firsts = [0, items - 2] + [int(c) for c in rng.integers(0, items - 2, 10)]
     for c0 in firsts:
         got = q.solve(Q, item_first=c0, item_count=2)
         exp = min(orc.solve_range(Q, _gray(c) * span, span, k=1)[0] for c in range(c0, c0 + 2))
