@@ -1084,7 +1084,20 @@ __global__ __launch_bounds__(256) void finish_kernel(const Inst *__restrict__ in
         for (uint64_t r = threadIdx.x; r < N; r += blockDim.x) lexmin(bE, bI, energy_int(sT, n, r), r);
         block_lexmin(bE, bI, sE, sI);
     } else {
-        for (uint64_t k = threadIdx.x; k < I.n_items; k += blockDim.x) {
+        // eight independent record loads in flight per thread: the loop is
+        // bound by memory latency, not by the comparisons
+        constexpr int U = 8;
+        const uint64_t bd = blockDim.x;
+        uint64_t k = threadIdx.x;
+        for (; k + (U - 1) * bd < I.n_items; k += U * bd) {
+            ItemRes r[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) r[u] = I.res[k + u * bd];
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                if (r[u].found) lexmin(bE, bI, r[u].E, r[u].row);
+        }
+        for (; k < I.n_items; k += bd) {
             const ItemRes r = I.res[k];
             if (r.found) lexmin(bE, bI, r.E, r.row);
         }
