@@ -182,13 +182,10 @@ __device__ void seed_best(const Inst &I, int wave)
         int32_t E = int32_t(wave_sum64(own));
         for (int it = 0; it < 4 * n; it++) {
             const int32_t gain = lane < n ? (x ? -f : f) : INT32_MAX;
-            // smallest gain, lowest lane on ties
-            int64_t key = int64_t(gain) * 256 + lane;
-#pragma unroll
-            for (int off = kWave / 2; off >= 1; off >>= 1) key = min(key, __shfl_xor(key, off, kWave));
-            const int32_t g = int32_t(key >> 8);
+            // smallest gain (DPP minimum), lowest lane on ties
+            const int32_t g = wave_min(gain);
             if (g >= 0) break;
-            const int k = int(key & 0xFF);
+            const int k = int(__builtin_ctzll(__builtin_amdgcn_ballot_w64(gain == g)));
             const int32_t sgn = __shfl(x, k, kWave) ? -1 : 1;   // 1 -> 0 subtracts couplings
             E += g;
             if (lane == k) x ^= 1;
@@ -288,13 +285,8 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
     int32_t mcol[4][5];   // M rows of levels 0..4 at this thread's columns
     for (int k = 0; k < 4; k++) {
         const uint32_t col = threadIdx.x + 256u * uint32_t(k);
-        for (int t = 0; t < 5; t++) {
-            int32_t m = 0;
-            if (col < NS)
-                for (int b = 0; b < B; b++)
-                    if ((col >> (B - 1 - b)) & 1u) m += T[(A - 1 - t) * n + A + b];
-            mcol[k][t] = m;
-        }
+        for (int t = 0; t < 5; t++)   // from this block's partial-sum tables
+            mcol[k][t] = col < NS ? part[A - 1 - t][col & 31u] + part[A - 1 - t][32u + (col >> 5)] : 0;
     }
     const int wl = int(threadIdx.x) % kWave, wv = int(threadIdx.x) / kWave;
     for (int q = 0; q < NQ; q++) {
@@ -310,8 +302,7 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
                 if ((pat >> t) & 1) v += mcol[k][t];
             mn = min(mn, v);
         }
-#pragma unroll
-        for (int off = kWave / 2; off >= 1; off >>= 1) mn = min(mn, __shfl_xor(mn, off, kWave));
+        mn = wave_min(mn);
         if (wl == 0) red[wv][q] = mn;
     }
     __syncthreads();
