@@ -1050,11 +1050,13 @@ __device__ void block_lexmin(int64_t &bE, uint64_t &bI, int64_t *sE, uint64_t *s
     __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void finish_kernel(const Inst *__restrict__ insts,
-                                                     FinalRes *__restrict__ out)
+constexpr int kFinishThreads = 1024;   // the record reduction is latency-bound: many loads in flight
+
+__global__ __launch_bounds__(kFinishThreads) void finish_kernel(const Inst *__restrict__ insts,
+                                                                FinalRes *__restrict__ out)
 {
-    __shared__ int64_t sE[256];
-    __shared__ uint64_t sI[256];
+    __shared__ int64_t sE[kFinishThreads];
+    __shared__ uint64_t sI[kFinishThreads];
     // T (and the caller's float32 Q) staged in LDS: every energy below reads
     // O(n^2) entries, and the float64 rescore runs on one thread in a fixed
     // order, where global-memory latency would dominate
@@ -1248,7 +1250,7 @@ hipError_t launch_walk(int mcols, int vgpr_levels, int tier, const Inst *d_insts
 
 hipError_t launch_finish(const Inst *d_insts, int n_inst, FinalRes *d_out, hipStream_t stream)
 {
-    hipLaunchKernelGGL(finish_kernel, dim3(n_inst), dim3(256), 0, stream, d_insts, d_out);
+    hipLaunchKernelGGL(finish_kernel, dim3(n_inst), dim3(kFinishThreads), 0, stream, d_insts, d_out);
     return hipGetLastError();
 }
 
