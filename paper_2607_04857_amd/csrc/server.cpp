@@ -37,6 +37,7 @@ using Clock = std::chrono::steady_clock;
 // Walk launches per tick are one per distinct walk kernel variant among the
 // active requests; this bounds the number of built variants (B x cache x tier).
 constexpr int kMaxTickLaunches = 32;
+constexpr int kServeL = 12;         // log2 Gray steps per work item of a served request
 
 enum class RState { Queued, Active, Done, Failed };
 
@@ -235,13 +236,14 @@ qubo_status_t enqueue_tick(qubo_server *s, TickBuf &t, bool *launched)
         return a->job.plans[0].items - a->next_item < b->job.plans[0].items - b->next_item;
     });
     std::vector<uint64_t> share(walkers.size(), 0);
-    // Under a backlog of more than four ticks' work the tick doubles, and
-    // past sixteen it quadruples: fewer tick boundaries (each costs a drain
-    // of the walk grid and a finish launch), at no cost in latency since
-    // requests queue anyway.
+    // Under a backlog the tick grows: doubled past four ticks' work, and
+    // doubled again for every further factor of two, up to 16x: fewer tick
+    // boundaries (each costs a drain of the walk grid and a finish launch),
+    // at no cost in latency since requests queue anyway.
     uint64_t backlog = 0;
     for (Request *r : walkers) backlog += r->job.plans[0].items - r->next_item;
-    const uint64_t scale = backlog > 16 * s->tick_items ? 4 : (backlog > 4 * s->tick_items ? 2 : 1);
+    uint64_t scale = 1;
+    while (scale < 16 && backlog > 4 * scale * s->tick_items) scale *= 2;
     uint64_t budget = scale * s->tick_items, total = 0;
     for (size_t k = 0; k < walkers.size(); k++) {
         Request *r = walkers[k];
@@ -489,6 +491,15 @@ qubo_status_t qubo_server_submit(qubo_server_t *s, const void *Q, int n, qubo_dt
             delete r;
             qrt::set_error(msg);
             return st;
+        }
+        // Served requests walk 2^12-step items (a quarter of a batch's): a
+        // tick then lasts about a millisecond at light load, which sets the
+        // latency of a request that arrives while one runs; under a backlog
+        // the ticks grow instead (enqueue_tick).
+        qplan::Plan &P = r->job.plans[0];
+        if (!P.direct && P.L > kServeL) {
+            P.L = kServeL;
+            P.items = uint64_t(1) << (P.A - P.L);
         }
         if (dtype == QUBO_FP32) {
             const float *q = static_cast<const float *>(Q);
