@@ -17,6 +17,9 @@ What it computes (see ``qubo_oracle.c`` for the C side):
 * ``solve_range(Q, first, count, k)`` -- the same over an index range.
 * ``gray_solve(Q)`` (O2) -- the textbook O(N 2^N) Gray-code brute force with
   local fields (Sec. I-D), best pair only.
+* ``gray_solve_range(Q, i0, i1)`` -- the same walk over the Gray indices
+  [i0, i1), i.e. the states i ^ (i >> 1), so that a long walk can be split
+  into shards and resumed.
 
 int32 input is summed exactly in int64; fp32 input is converted exactly to
 float64 and summed in float64.
@@ -40,7 +43,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC", "-pthread",
+            ["gcc", "-O3", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC", "-pthread",
              _SRC, "-o", tmp])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -65,8 +68,11 @@ def _load():
     lib.oracle_solve_f.argtypes = [i32, c_f32p, u64, u64, i32, i32, c_f64p, c_u64p]
     lib.oracle_gray_i.argtypes = [i32, c_i32p, i32, c_i64p, c_u64p]
     lib.oracle_gray_f.argtypes = [i32, c_f32p, i32, c_f64p, c_u64p]
+    lib.oracle_gray_range_i.argtypes = [i32, c_i32p, u64, u64, i32, c_i64p, c_u64p]
+    lib.oracle_gray_range_f.argtypes = [i32, c_f32p, u64, u64, i32, c_f64p, c_u64p]
     for f in (lib.oracle_energy_i, lib.oracle_energy_f, lib.oracle_solve_i,
-              lib.oracle_solve_f, lib.oracle_gray_i, lib.oracle_gray_f):
+              lib.oracle_solve_f, lib.oracle_gray_i, lib.oracle_gray_f,
+              lib.oracle_gray_range_i, lib.oracle_gray_range_f):
         f.restype = ctypes.c_int
     lib.oracle_default_threads.argtypes = []
     lib.oracle_default_threads.restype = ctypes.c_int
@@ -154,6 +160,25 @@ def gray_solve(Q, threads: int = 0):
                                ctypes.byref(idx))
     if rc != 0:
         raise ValueError(f"oracle_gray failed ({rc})")
+    return (int(E.value) if is_int else float(E.value), int(idx.value))
+
+
+def gray_solve_range(Q, i0: int, i1: int, threads: int = 0):
+    """Best (E, index) pair over the states of Gray indices [i0, i1) (O2 shard)."""
+    lib = _load()
+    Qc, is_int = _prep(Q)
+    n = Qc.shape[0]
+    idx = ctypes.c_uint64()
+    if is_int:
+        E = ctypes.c_int64()
+        rc = lib.oracle_gray_range_i(n, _ptr(Qc, ctypes.c_int32), int(i0), int(i1), int(threads),
+                                     ctypes.byref(E), ctypes.byref(idx))
+    else:
+        E = ctypes.c_double()
+        rc = lib.oracle_gray_range_f(n, _ptr(Qc, ctypes.c_float), int(i0), int(i1), int(threads),
+                                     ctypes.byref(E), ctypes.byref(idx))
+    if rc != 0:
+        raise ValueError(f"oracle_gray_range failed ({rc})")
     return (int(E.value) if is_int else float(E.value), int(idx.value))
 
 

@@ -231,12 +231,21 @@ int oracle_solve_f(int n, const float *Q, uint64_t first, uint64_t count, int k,
 }
 
 /* ------------------------------------------------------------------ */
-/* O2: local-field Gray-code walk over all 2^n states                   */
+/* O2: local-field Gray-code walk over a range of Gray indices          */
 /* ------------------------------------------------------------------ */
 
+/* The coupling of variables v and k in the single-flip identity is
+ * S_kv = Q_kv + Q_vk for v != k.  O2 stores it row by row, S[k][0..np),
+ * with S_kk = 0 and zero padding up to np (a multiple of 8), so that the
+ * field update after a flip of k reads one contiguous row.  Adding S_kk = 0
+ * to f_k leaves it unchanged, as it must be (f_k does not depend on x_k). */
+#define O2_PAD 8
+
 typedef struct {
-    int n, is_int;
+    int n, np, is_int;
     const void *Q;
+    const int64_t *Si;       /* np x np int64 coupling rows (int input) */
+    const double *Sf;        /* np x np double coupling rows (fp32 input) */
     uint64_t i0, i1;         /* Gray-index range [i0, i1) */
     int64_t bestEi;
     double bestEf;
@@ -244,84 +253,153 @@ typedef struct {
     int have;
 } o2_job_t;
 
-static void *o2_worker(void *arg)
+/* One walk over the job's Gray-index range, for coupling rows of length np. */
+static inline __attribute__((always_inline)) void o2_walk_i_np(o2_job_t *j, const int np)
 {
-    o2_job_t *j = (o2_job_t *)arg;
     const int n = j->n;
+    const int32_t *Q = (const int32_t *)j->Q;
+    int64_t f[ORACLE_MAX_N];
     int x[ORACLE_MAX_N];
     uint64_t row = j->i0 ^ (j->i0 >> 1);  /* reflected Gray code of i0 */
     for (int v = 0; v < n; v++) x[v] = (int)((row >> (n - 1 - v)) & 1u);
-    j->have = 0;
-    if (j->is_int) {
-        const int32_t *Q = (const int32_t *)j->Q;
-        int64_t f[ORACLE_MAX_N];
-        int64_t E = energy_i(n, Q, row);
-        for (int k = 0; k < n; k++) {
-            int64_t s = Q[(size_t)k * n + k];
-            for (int v = 0; v < n; v++)
-                if (v != k && x[v]) s += (int64_t)Q[(size_t)k * n + v] + Q[(size_t)v * n + k];
-            f[k] = s;
-        }
-        for (uint64_t i = j->i0;; i++) {
-            if (!j->have || E < j->bestEi || (E == j->bestEi && row < j->bestIdx)) {
-                j->have = 1;
-                j->bestEi = E;
-                j->bestIdx = row;
-            }
-            if (i + 1 >= j->i1) break;
-            int t = __builtin_ctzll(i + 1);      /* Gray level that flips */
-            int k = n - 1 - t;                   /* vector position, MSB-left */
-            int d = x[k] ? -1 : 1;               /* +1 when x_k goes 0 -> 1 */
-            E += d * f[k];
-            x[k] ^= 1;
-            row ^= 1ull << t;
-            for (int v = 0; v < n; v++)
-                if (v != k) f[v] += d * ((int64_t)Q[(size_t)v * n + k] + Q[(size_t)k * n + v]);
-        }
-    } else {
-        const float *Q = (const float *)j->Q;
-        double f[ORACLE_MAX_N];
-        double E = energy_f(n, Q, row);
-        for (int k = 0; k < n; k++) {
-            double s = Q[(size_t)k * n + k];
-            for (int v = 0; v < n; v++)
-                if (v != k && x[v]) s += (double)Q[(size_t)k * n + v] + (double)Q[(size_t)v * n + k];
-            f[k] = s;
-        }
-        for (uint64_t i = j->i0;; i++) {
-            if (!j->have || E < j->bestEf || (E == j->bestEf && row < j->bestIdx)) {
-                j->have = 1;
-                j->bestEf = E;
-                j->bestIdx = row;
-            }
-            if (i + 1 >= j->i1) break;
-            int t = __builtin_ctzll(i + 1);
-            int k = n - 1 - t;
-            double d = x[k] ? -1.0 : 1.0;
-            E += d * f[k];
-            x[k] ^= 1;
-            row ^= 1ull << t;
-            for (int v = 0; v < n; v++)
-                if (v != k) f[v] += d * ((double)Q[(size_t)v * n + k] + (double)Q[(size_t)k * n + v]);
-        }
+    for (int v = n; v < np; v++) f[v] = 0;
+    int64_t E = energy_i(n, Q, row);
+    for (int k = 0; k < n; k++) {         /* f_k = Q_kk + sum_{v != k} S_kv x_v */
+        int64_t s = Q[(size_t)k * n + k];
+        for (int v = 0; v < n; v++)
+            if (x[v]) s += j->Si[(size_t)k * np + v];
+        f[k] = s;
     }
+    j->have = 0;
+    for (uint64_t i = j->i0;; i++) {
+        if (!j->have || E < j->bestEi || (E == j->bestEi && row < j->bestIdx)) {
+            j->have = 1;
+            j->bestEi = E;
+            j->bestIdx = row;
+        }
+        if (i + 1 >= j->i1) break;
+        int t = __builtin_ctzll(i + 1);      /* Gray level that flips */
+        int k = n - 1 - t;                   /* vector position, MSB-left */
+        const int64_t *S = j->Si + (size_t)k * np;
+        row ^= 1ull << t;
+        if (x[k]) {                          /* x_k goes 1 -> 0: delta = -1 */
+            E -= f[k];
+            for (int v = 0; v < np; v++) f[v] -= S[v];
+        } else {                             /* x_k goes 0 -> 1: delta = +1 */
+            E += f[k];
+            for (int v = 0; v < np; v++) f[v] += S[v];
+        }
+        x[k] ^= 1;
+    }
+}
+
+static inline __attribute__((always_inline)) void o2_walk_f_np(o2_job_t *j, const int np)
+{
+    const int n = j->n;
+    const float *Q = (const float *)j->Q;
+    double f[ORACLE_MAX_N];
+    int x[ORACLE_MAX_N];
+    uint64_t row = j->i0 ^ (j->i0 >> 1);
+    for (int v = 0; v < n; v++) x[v] = (int)((row >> (n - 1 - v)) & 1u);
+    for (int v = n; v < np; v++) f[v] = 0.0;
+    double E = energy_f(n, Q, row);
+    for (int k = 0; k < n; k++) {
+        double s = Q[(size_t)k * n + k];
+        for (int v = 0; v < n; v++)
+            if (x[v]) s += j->Sf[(size_t)k * np + v];
+        f[k] = s;
+    }
+    j->have = 0;
+    for (uint64_t i = j->i0;; i++) {
+        if (!j->have || E < j->bestEf || (E == j->bestEf && row < j->bestIdx)) {
+            j->have = 1;
+            j->bestEf = E;
+            j->bestIdx = row;
+        }
+        if (i + 1 >= j->i1) break;
+        int t = __builtin_ctzll(i + 1);
+        int k = n - 1 - t;
+        const double *S = j->Sf + (size_t)k * np;
+        row ^= 1ull << t;
+        if (x[k]) {
+            E -= f[k];
+            for (int v = 0; v < np; v++) f[v] -= S[v];
+        } else {
+            E += f[k];
+            for (int v = 0; v < np; v++) f[v] += S[v];
+        }
+        x[k] ^= 1;
+    }
+}
+
+/* The row length np is passed as a constant (one copy of the walk per
+ * multiple of 8), so the field update compiles to straight-line vector code. */
+#define O2_DISPATCH(body, j)                                                    \
+    switch ((j)->np) {                                                          \
+    case 8: body(j, 8); break;   case 16: body(j, 16); break;                   \
+    case 24: body(j, 24); break; case 32: body(j, 32); break;                   \
+    case 40: body(j, 40); break; case 48: body(j, 48); break;                   \
+    case 56: body(j, 56); break; default: body(j, 64); break;                   \
+    }
+
+/* The walk proper, compiled for several instruction sets; the loader picks
+ * the widest one the host supports (results do not depend on the choice:
+ * every step is exact integer arithmetic or the same double additions). */
+__attribute__((target_clones("avx512f", "avx2", "default")))
+static void o2_walk_i(o2_job_t *j)
+{
+    O2_DISPATCH(o2_walk_i_np, j)
+}
+
+__attribute__((target_clones("avx512f", "avx2", "default")))
+static void o2_walk_f(o2_job_t *j)
+{
+    O2_DISPATCH(o2_walk_f_np, j)
+}
+
+static void *o2_worker(void *arg)
+{
+    o2_job_t *j = (o2_job_t *)arg;
+    if (j->is_int) o2_walk_i(j);
+    else o2_walk_f(j);
     return NULL;
 }
 
-static int o2_solve(int n, const void *Q, int is_int, int threads, int64_t *Ei, double *Ef,
-                    uint64_t *idx)
+/* best (E, index) over the Gray indices [i0, i1), i.e. over the states
+ * g(i) = i ^ (i >> 1) for i0 <= i < i1 */
+static int o2_solve(int n, const void *Q, int is_int, uint64_t i0, uint64_t i1, int threads,
+                    int64_t *Ei, double *Ef, uint64_t *idx)
 {
     if (n < 1 || n > 62 || !Q || !idx) return -1;
     uint64_t total = 1ull << n;
-    int T = resolve_threads(threads, total);
+    if (i0 >= i1 || i1 > total) return -1;
+    int T = resolve_threads(threads, i1 - i0);
+    int np = (n + O2_PAD - 1) / O2_PAD * O2_PAD;
+    int64_t *Si = NULL;
+    double *Sf = NULL;
+    if (is_int) Si = (int64_t *)calloc((size_t)np * np, sizeof(int64_t));
+    else Sf = (double *)calloc((size_t)np * np, sizeof(double));
     o2_job_t *jobs = (o2_job_t *)calloc((size_t)T, sizeof(o2_job_t));
     pthread_t *tid = (pthread_t *)calloc((size_t)T, sizeof(pthread_t));
-    if (!jobs || !tid) { free(jobs); free(tid); return -2; }
-    uint64_t per = total / (uint64_t)T, rem = total % (uint64_t)T, at = 0;
+    if (!jobs || !tid || (!Si && !Sf)) { free(jobs); free(tid); free(Si); free(Sf); return -2; }
+    for (int k = 0; k < n; k++)
+        for (int v = 0; v < n; v++) {
+            if (v == k) continue;
+            if (is_int)
+                Si[(size_t)k * np + v] = (int64_t)((const int32_t *)Q)[(size_t)k * n + v] +
+                                         ((const int32_t *)Q)[(size_t)v * n + k];
+            else
+                Sf[(size_t)k * np + v] = (double)((const float *)Q)[(size_t)k * n + v] +
+                                         (double)((const float *)Q)[(size_t)v * n + k];
+        }
+    uint64_t count = i1 - i0, per = count / (uint64_t)T, rem = count % (uint64_t)T, at = i0;
     for (int t = 0; t < T; t++) {
         jobs[t].n = n;
+        jobs[t].np = np;
         jobs[t].is_int = is_int;
         jobs[t].Q = Q;
+        jobs[t].Si = Si;
+        jobs[t].Sf = Sf;
         jobs[t].i0 = at;
         at += per + ((uint64_t)t < rem ? 1 : 0);
         jobs[t].i1 = at;
@@ -344,19 +422,37 @@ static int o2_solve(int n, const void *Q, int is_int, int threads, int64_t *Ei, 
     if (Ef) *Ef = jobs[b].bestEf;
     free(jobs);
     free(tid);
+    free(Si);
+    free(Sf);
     return 0;
 }
 
 int oracle_gray_i(int n, const int32_t *Q, int threads, int64_t *E, uint64_t *idx)
 {
-    if (!E) return -1;
-    return o2_solve(n, Q, 1, threads, E, NULL, idx);
+    if (!E || n < 1 || n > 62) return -1;
+    return o2_solve(n, Q, 1, 0, 1ull << n, threads, E, NULL, idx);
 }
 
 int oracle_gray_f(int n, const float *Q, int threads, double *E, uint64_t *idx)
 {
+    if (!E || n < 1 || n > 62) return -1;
+    return o2_solve(n, Q, 0, 0, 1ull << n, threads, NULL, E, idx);
+}
+
+/* best (E, index) over the states of Gray indices [i0, i1): a shard of the
+ * whole walk, so that long walks can be split and resumed */
+int oracle_gray_range_i(int n, const int32_t *Q, uint64_t i0, uint64_t i1, int threads,
+                        int64_t *E, uint64_t *idx)
+{
     if (!E) return -1;
-    return o2_solve(n, Q, 0, threads, NULL, E, idx);
+    return o2_solve(n, Q, 1, i0, i1, threads, E, NULL, idx);
+}
+
+int oracle_gray_range_f(int n, const float *Q, uint64_t i0, uint64_t i1, int threads,
+                        double *E, uint64_t *idx)
+{
+    if (!E) return -1;
+    return o2_solve(n, Q, 0, i0, i1, threads, NULL, E, idx);
 }
 
 /* number of worker threads a call with threads <= 0 uses */

@@ -194,3 +194,42 @@ def test_zero_and_degenerate(orc):
     assert orc.solve(np.array([[-5]], dtype=np.int32)) == [(-5, 1)]
     neg = np.full((6, 6), -1, dtype=np.int32)
     assert orc.solve(neg) == [(-36, 63)]
+
+
+def test_gray3_paper_figure(orc):
+    """Sec. III-B, Fig. "3-bit Gray code sequence": step i visits g(i) = i ^ (i >> 1), and
+    step i -> i + 1 flips vector position k = 3 - 1 - ctz(i + 1) (MSB-left).  O2's
+    Gray-index range entry walks exactly the states the figure lists for that range."""
+    _, rows = read_table("gray3.txt")
+    codes = [r[1] for r in rows]
+    assert [int(r[0]) for r in rows] == list(range(8))
+    for i, code in enumerate(codes):
+        assert code == format(i ^ (i >> 1), "03b")
+        if i + 1 < 8:
+            diff = [p for p in range(3) if code[p] != codes[i + 1][p]]
+            ctz = ((i + 1) & -(i + 1)).bit_length() - 1
+            assert diff == [3 - 1 - ctz]
+    Q = np.diag([-4, -2, -1]).astype(np.int32)       # E(x) = -index, so the minimum names the
+    for i0 in range(8):                              # largest row the walk visited
+        for i1 in range(i0 + 1, 9):
+            top = max(int(c, 2) for c in codes[i0:i1])
+            for threads in (1, 2):
+                assert orc.gray_solve_range(Q, i0, i1, threads=threads) == (-top, top)
+
+
+@pytest.mark.parametrize("threads", [1, 3])
+def test_gray_range_equals_direct(orc, threads):
+    """O2 over a Gray-index range [i0, i1) = the direct minimum over the states g(i) in it."""
+    n = 12
+    Q = inputs.full_int(n, -500, 500, seed=31)
+    Qf = inputs.normal_fp32(n, seed=32)
+    rng = np.random.default_rng(5)
+    ranges = [(0, 1), (0, 2 ** n), (2 ** n - 1, 2 ** n), (1000, 1001)]
+    ranges += [tuple(sorted(rng.choice(2 ** n + 1, size=2, replace=False))) for _ in range(6)]
+    for i0, i1 in ranges:
+        states = [i ^ (i >> 1) for i in range(i0, i1)]
+        exp = min((orc.energy(Q, g), g) for g in states)
+        assert orc.gray_solve_range(Q, i0, i1, threads=threads) == exp
+        ef, gf = min((orc.energy(Qf, g), g) for g in states)
+        got = orc.gray_solve_range(Qf, i0, i1, threads=threads)
+        assert got[1] == gf and abs(got[0] - ef) <= 1e-9 * np.abs(Qf.astype(np.float64)).sum()
