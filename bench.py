@@ -27,8 +27,9 @@ topk             = the k = 1024 lowest-energy states of a dense n = 40 int32
 serving          = Poisson arrivals at a fixed rate (seed 7), n ~ U{16..40},
                    80% int32 U[-100,100] / 20% float32 N(0,1): p50/p99 latency
                    (arrival -> result) and aggregate states/s through the
-                   continuous-batching server; plus the same requests submitted
-                   at once (saturation throughput).
+                   continuous-batching server; the same requests submitted
+                   at once (saturation throughput and capacity in requests/s);
+                   and Poisson arrivals at half that capacity (half_load).
 """
 import argparse
 import hashlib
@@ -75,9 +76,36 @@ def traffic_from_profile():
     return float(m_b.group(1))
 
 
+def host_cpus():
+    """CPUs this process may run on: the affinity mask, capped by a cgroup CPU
+    quota when one is set; with the counts it came from and the CPU model."""
+    nproc = os.cpu_count() or 1
+    affinity = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else nproc
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as f:
+            q, period = f.read().split()[:2]
+        if q != "max":
+            quota = -(-int(q) // int(period))
+    except (OSError, ValueError):
+        pass
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = min(affinity, quota) if quota else affinity
+    return usable, {"nproc": nproc, "affinity": affinity, "cgroup_quota_cpus": quota,
+                    "cpu_model": model}
+
+
 def cpu_baseline(Q, budget_s=20.0):
     import oracle
-    threads = min(16, os.cpu_count() or 1)
+    threads, info = host_cpus()
     n = Q.shape[0]
     first = 0x5A5A5A5 << 17          # a fixed contiguous slice of the 2^44 index space
     probe = 1 << 22
@@ -88,9 +116,12 @@ def cpu_baseline(Q, budget_s=20.0):
     t0 = time.perf_counter()
     oracle.solve_range(Q, first, count, k=1, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": count / dt, "unit": "states/s", "cores": threads, "kind": "oracle",
-            "sample": f"direct evaluation of {count} consecutive states (indices "
-                      f"[{first}, {first + count})) of the n={n} instance, {dt:.1f} s"}
+    out = {"value": count / dt, "unit": "states/s", "cores": threads, "kind": "oracle",
+           "sample": f"direct evaluation of {count} consecutive states (indices "
+                     f"[{first}, {first + count})) of the n={n} instance, {dt:.1f} s, "
+                     f"one thread per usable host CPU"}
+    out.update(info)
+    return out
 
 
 TUNE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2607_04857_amd",
@@ -145,12 +176,17 @@ def topk(q, torch, n=40, k=1024, steps=2):
 
 
 def serving(q, count=600, rate_hz=150.0):
+    """The served mix at a light fixed rate, at saturation (every request
+    submitted at once), and at half the saturation capacity measured here
+    (requests/s), where requests overlap on the device."""
     import threading
     from paper_2607_04857_amd import inputs
-    reqs = inputs.poisson_requests(count, rate_hz, 16, 40, seed=7, int_fraction=0.8)
-    states = sum(2.0 ** Q.shape[0] for _, Q in reqs)
 
-    def run(paced):
+    def mix(rate):
+        # the same instances at any rate (the arrival gaps scale, the draws do not change)
+        return inputs.poisson_requests(count, rate, 16, 40, seed=7, int_fraction=0.8)
+
+    def run(reqs, paced):
         srv = q.Server(mem_budget_bytes=8 << 30, max_slots=512)
         tickets = [None] * len(reqs)
 
@@ -174,15 +210,26 @@ def serving(q, count=600, rate_hz=150.0):
         srv.close()
         return st, info, wall
 
-    st, info, wall = run(True)
-    sat, _, sat_wall = run(False)
+    reqs = mix(rate_hz)
+    states = sum(2.0 ** Q.shape[0] for _, Q in reqs)
+    st, info, wall = run(reqs, True)
+    sat, _, sat_wall = run(reqs, False)
+    capacity = count / sat_wall                      # requests/s at saturation
+    half_rate = 0.5 * capacity
+    reqs_h = mix(half_rate)
+    hst, hinfo, hwall = run(reqs_h, True)
     return {"workload": f"{count} requests, Poisson {rate_hz:g}/s, n~U{{16..40}}, 80% int32 "
                         "U[-100,100] / 20% fp32 N(0,1), seed 7",
             "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "states_per_s": states / wall,
             "offered_states_per_s": states / reqs[-1][0], "ticks": info["ticks"],
             "mem_peak_bytes": info["mem_peak"],
             "saturation_states_per_s": states / sat_wall,
-            "saturation_p50_ms": sat["p50_ms"], "saturation_p99_ms": sat["p99_ms"]}
+            "saturation_p50_ms": sat["p50_ms"], "saturation_p99_ms": sat["p99_ms"],
+            "capacity_req_per_s": capacity,
+            "half_load": {"rate_req_per_s": half_rate, "p50_ms": hst["p50_ms"],
+                          "p99_ms": hst["p99_ms"], "states_per_s": states / hwall,
+                          "offered_states_per_s": states / reqs_h[-1][0],
+                          "ticks": hinfo["ticks"]}}
 
 
 def main():

@@ -495,10 +495,13 @@ qubo_status_t qubo_server_submit(qubo_server_t *s, const void *Q, int n, qubo_dt
         // Served requests walk 2^12-step items (a quarter of a batch's): a
         // tick then lasts about a millisecond at light load, which sets the
         // latency of a request that arrives while one runs; under a backlog
-        // the ticks grow instead (enqueue_tick).
+        // the ticks grow instead (enqueue_tick).  The planner's cap of 2^20
+        // items per instance still holds (L >= A - 20), so large requests
+        // keep their item records (16 B each) and their finish bounded.
         qplan::Plan &P = r->job.plans[0];
-        if (!P.direct && P.L > kServeL) {
-            P.L = kServeL;
+        const int serveL = std::max(kServeL, P.A - 20);
+        if (!P.direct && P.L > serveL) {
+            P.L = serveL;
             P.items = uint64_t(1) << (P.A - P.L);
         }
         if (dtype == QUBO_FP32) {

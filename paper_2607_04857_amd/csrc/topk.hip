@@ -15,6 +15,7 @@
 //      E = E_p(row) + E_s(s) + x_p M_int[:, s] (Sec. II-C), keeping the
 //      states at or below the largest selected chunk key (the k chunk minima
 //      are k states at or below it, so the k-th smallest energy is too);
+//      an instance with fewer than k chunks keeps all of its states;
 //   4. select the k smallest (E, index) among them, sorted;
 //   5. verify each energy from T, rescore fp32 instances in float64 and sort
 //      those by (E64, index).
@@ -220,10 +221,14 @@ __global__ __launch_bounds__(256) void topk_compact_kernel(const int32_t *__rest
 // Step 3: block b rescans chunk rows[b] (if b < *rowCount) and appends its
 // states with E <= the largest selected chunk key to (stE, stI), densely
 // (wave-aggregated slots counted in *stCount, zeroed by the chunk select).
+// With fewer than k chunks selected (the instance has fewer than k chunks)
+// the k-th smallest state may lie above every chunk minimum, so every state
+// of every chunk is kept: at most rc << B < k << B entries.
 __global__ __launch_bounds__(256) void topk_rescan_kernel(const Inst *__restrict__ inst,
                                                           const uint64_t *__restrict__ rows,
                                                           const int32_t *__restrict__ rowE,
                                                           const int32_t *__restrict__ rowCount,
+                                                          int k,
                                                           int32_t *__restrict__ stE,
                                                           uint64_t *__restrict__ stI,
                                                           int32_t *__restrict__ stCount)
@@ -235,7 +240,8 @@ __global__ __launch_bounds__(256) void topk_rescan_kernel(const Inst *__restrict
     const uint32_t b = blockIdx.x;
     const int32_t rc = *rowCount;
     if (int32_t(b) >= rc) return;
-    const int32_t bound = rowE[rc - 1];   // rows are sorted by (key, row)
+    // rows are sorted by (key, row)
+    const int32_t bound = rc < k ? INT32_MAX : rowE[rc - 1];
     const int lane = int(threadIdx.x) & (kWave - 1);
     const uint64_t row = rows[b];
     // E_p(row) = sum over set prefix bits i <= j of T[i][j]; prefix variable
@@ -397,7 +403,7 @@ hipError_t launch_topk_finish(const Inst *d_inst, const Inst &hI, const TopkBufs
         ch.clear = buf.segCount;     // [0]: the rescan's state counter
         hipLaunchKernelGGL(topk_select_kernel, dim3(1), dim3(kSelThreads), 0, stream, ch);
         hipLaunchKernelGGL(topk_rescan_kernel, dim3(k), dim3(256), 0, stream, d_inst, buf.chunkR,
-                           buf.chunkE, buf.chunkCount, buf.stE, buf.stI, buf.segCount);
+                           buf.chunkE, buf.chunkCount, k, buf.stE, buf.stI, buf.segCount);
         st.count = buf.segCount;     // states kept by the rescan, densely
         st.mult = 1;
     }

@@ -12,6 +12,9 @@ matrix" (Sec. V-C); these generators produce that workload:
   -(R_i + 1) where x*_i = 1 and +(R_i + 1) where x*_i = 0, with R_i the sum of
   |Q_ij| + |Q_ji| over j != i; any single flip towards x* then lowers the
   energy by at least 1 whatever the other bits are).
+* ``edge_int(n, total, seed)``: upper-triangular int32 Q whose absolute entries
+  sum to exactly ``total`` (the int32 exactness limit of the solver is
+  sum |T| <= 2^30 - 1, so ``total = 2**30 - 1`` sits on it).
 * ``batch(count, n_lo, n_hi, seed, kind)``: many instances of uneven size.
 * ``poisson_requests(...)``: arrival times and instances for the serving mix.
 
@@ -47,6 +50,22 @@ def planted(n: int, lo: int, hi: int, seed: int):
     if np.abs(Q).max() > 2**31 - 1:
         raise ValueError("planted instance does not fit int32")
     return Q.astype(np.int32), xstar
+
+
+def edge_int(n: int, total: int, seed: int) -> np.ndarray:
+    """Upper-triangular int32 Q (random signs and magnitudes) with sum |Q_ij| == total."""
+    rng = np.random.default_rng(seed)
+    iu = np.triu_indices(n)
+    m = len(iu[0])
+    w = rng.random(m) + 0.05
+    mag = np.floor(w / w.sum() * total).astype(np.int64)
+    short = int(total - mag.sum())              # 0 <= short < m after flooring
+    mag[rng.choice(m, size=short, replace=False)] += 1
+    sign = np.where(rng.random(m) < 0.5, -1, 1)
+    Q = np.zeros((n, n), dtype=np.int64)
+    Q[iu] = sign * mag
+    assert int(np.abs(Q).sum()) == total and np.abs(Q).max() <= 2**31 - 1
+    return Q.astype(np.int32)
 
 
 def full_int(n: int, lo: int, hi: int, seed: int) -> np.ndarray:

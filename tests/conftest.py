@@ -36,3 +36,24 @@ def orc():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+def check_fp32(orc, Q, got, E_star, idx_star=None):
+    """Accept an fp32 answer only on the oracle's own rescoring of the returned state.
+
+    Reading of the fp32 path (fixed point, then a float64 rescore of the
+    returned state): the oracle's float64 energy of ``got.index`` must equal
+    the reported energy (up to float64 summation order), lie within
+    ``got.tol`` of the oracle minimum ``E_star``, and ``got.tol`` must meet
+    the 1e-5 * sum|Q| bound.  A different index is accepted only as such a
+    near-tie.
+    """
+    import numpy as np
+    scale = float(np.abs(np.asarray(Q, dtype=np.float64)).sum())
+    e = orc.energy(Q, got.index)
+    assert abs(e - got.energy) <= 1e-9 * scale + 1e-12, (got, e)
+    assert e <= E_star + got.tol, (got, e, E_star)
+    assert abs(got.energy - E_star) <= got.tol, (got, E_star)
+    assert got.tol <= 1e-5 * scale, (got.tol, scale)
+    if idx_star is not None and got.index != idx_star:
+        assert e - E_star <= got.tol

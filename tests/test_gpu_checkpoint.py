@@ -3,6 +3,7 @@ solve and the oracle."""
 import numpy as np
 import pytest
 
+from conftest import check_fp32
 from paper_2607_04857_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -48,7 +49,8 @@ def test_sliced_small_instances_match_oracle(tmp_path, orc):
         if Q.dtype == np.int32:
             assert (r.energy_i, r.index) == (E, idx)
         else:
-            assert abs(r.energy - E) <= r.tol and r.energy == whole.energy
+            check_fp32(orc, Q, r, E, idx)
+            assert r.energy == whole.energy
 
 
 def test_planted_n46_in_slices(tmp_path, orc):

@@ -9,7 +9,7 @@ import os
 import numpy as np
 import pytest
 
-from conftest import GOLDEN
+from conftest import GOLDEN, check_fp32
 from paper_2607_04857_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -94,9 +94,7 @@ def test_fp32(q, orc, tier):
         Q = inputs.normal_fp32(n, seed)
         got = q.solve(Q, tier=tier)
         E, idx = orc.solve(Q, k=1)[0]
-        assert abs(got.energy - E) <= got.tol
-        assert got.tol <= 1e-5 * np.abs(Q.astype(np.float64)).sum()
-        assert got.index == idx or got.energy <= E + got.tol
+        check_fp32(orc, Q, got, E, idx)
 
 
 def _golden():
@@ -108,7 +106,7 @@ def _golden():
                                   "n33_int_u100_s12", "n36_int_u1000_s2", "n36_planted_u1000_s3",
                                   "n28_fp32_s6", "n32_fp32_s13"])
 @pytest.mark.parametrize("tier", TIERS)
-def test_stored_oracle_results(q, name, tier):
+def test_stored_oracle_results(q, orc, name, tier):
     g = _golden()
     if name not in g:
         pytest.skip("stored value not generated")
@@ -123,9 +121,7 @@ def test_stored_oracle_results(q, name, tier):
         assert [got.energy_i, got.index] == e["best"]
     else:
         E, idx = e["best"]
-        assert abs(got.energy - E) <= got.tol
-        assert got.tol <= 1e-5 * np.abs(Q.astype(np.float64)).sum()
-        assert got.index == idx or got.energy <= E + got.tol
+        check_fp32(orc, Q, got, E, idx)
 
 
 @pytest.mark.parametrize("tier", TIERS)
@@ -246,3 +242,30 @@ def test_algebraic_invariances(q, orc):
     worst = orc.solve(-Q, k=1)[0]
     assert (rneg.energy_i, rneg.index) == worst
     assert orc.energy(Q, rneg.index) == -rneg.energy_i
+
+
+@pytest.mark.parametrize("tier", TIERS)
+def test_int32_exactness_edge(q, orc, tier):
+    """A dense instance on the int32 exactness limit, sum |T| = 2^30 - 1
+    exactly (one more is refused with QUBO_EOVERFLOW): the whole solve, a
+    restricted item range (unseeded, so its thresholds start from the
+    no-energy value) and top-64, all against the oracle."""
+    n = 22
+    Q = inputs.edge_int(n, 2**30 - 1, seed=2230)
+    info = q.plan_info(Q, tier=tier)
+    assert info["sum_abs_t"] == 2**30 - 1
+    got = q.solve(Q, tier=tier)
+    assert (got.energy_i, got.index) == orc.solve(Q, k=1)[0]
+    L, B, items = info["L"], info["B"], info["items"]
+    span = 1 << (L + B)
+    for c0, cnt in ((0, 1), (items // 3, 2), (items - 1, 1)):
+        r = q.solve(Q, tier=tier, item_first=c0, item_count=cnt)
+        exp = min(orc.solve_range(Q, _gray(c) * span, span, k=1)[0] for c in range(c0, c0 + cnt))
+        assert (r.energy_i, r.index) == exp, (c0, cnt, r, exp)
+    res, pairs = q.solve(Q, k=64)
+    assert pairs == [(int(e), int(i)) for e, i in orc.solve(Q, k=64)]
+    over = Q.copy()
+    over[0, 0] += 1 if over[0, 0] >= 0 else -1
+    with pytest.raises(q.QuboError) as e:
+        q.solve(over)
+    assert e.value.status == -2

@@ -136,3 +136,19 @@ def test_stored_oracle_topk():
         checked += 1
         print(f"{name}: top-{len(ref)} ok", flush=True)
     assert checked >= 3
+
+
+def test_fewer_chunks_than_k(orc):
+    """2^A chunks < k: the rescan must keep every state of every chunk, not
+    only those under the largest chunk minimum.  n = 16, B = 9 (128 chunks),
+    prefix diagonal in [-3, 0], suffix diagonal +100: each chunk's minimum is
+    its all-zero suffix, and the 1024 lowest states need 896 states with one
+    suffix bit set."""
+    import paper_2607_04857_amd as q
+    rng = np.random.default_rng(1616)
+    d = np.concatenate([rng.integers(-3, 1, 7), np.full(9, 100)])
+    Q = np.diag(d).astype(np.int32)
+    res, pairs = _exact(orc, q, Q, 1024, B=9)
+    assert (res.A, res.B) == (7, 9)
+    Q2 = inputs.uniform_int(15, -100, 100, 1515)
+    _exact(orc, q, Q2, 1000, B=10)            # 32 chunks, k = 1000
