@@ -147,6 +147,28 @@ qubo_status_t qubo_solve_device(const void *dQ, int n, qubo_dtype_t dtype, int k
                                 void *hip_stream, qubo_result_t *out,
                                 qubo_state_t *topk);
 
+/* Allocation-free variant of qubo_solve with k = 1, for callers that cannot
+ * allocate device memory (code that runs under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same plan, kernels and
+ * result as qubo_solve(Q, n, dtype, 1, out, NULL).  Q: host memory as for
+ * qubo_solve; work is ordered on hip_stream (a hipStream_t; NULL = the null
+ * stream) and the call returns after synchronising it.  The job's device
+ * memory is a fixed scratch array of qubo_noalloc_scratch_bytes() bytes
+ * (16 MiB) that the library holds on each device it runs on until the
+ * process ends; the call makes no device or pinned-host allocation
+ * (hipMalloc, hipMallocAsync, hipHostMalloc or a library routine that
+ * allocates) and no hipFree.  A plan whose device image exceeds the scratch
+ * (large n: the item records grow with the work items) returns QUBO_ENOMEM
+ * with the sizes in qubo_last_error().  Every call on one device shares that
+ * device's scratch and leaves its contents behind; calls that overlap on one
+ * device (another thread, or another stream before this call returns) race
+ * and must be serialised by the caller. */
+qubo_status_t qubo_solve_noalloc(const void *Q, int n, qubo_dtype_t dtype, void *hip_stream,
+                                 qubo_result_t *out);
+
+/* Size in bytes of qubo_solve_noalloc's per-device scratch array. */
+size_t qubo_noalloc_scratch_bytes(void);
+
 /* Solve `count` independent instances (host memory) in one persistent walk
  * launch.  Q[i] is n[i] x n[i] of dtype[i].  out[i] receives instance i's
  * result (best state only).  The whole sequence is replayed from a HIP graph. */

@@ -4,6 +4,10 @@ Every step of a solve runs inside the HIP library (see ``include/qubo.h``);
 this module only marshals arguments.  There is no CPU fallback: if the
 library is missing, every call raises ``QuboLibraryMissing``.
 
+A process that uses torch's GPU support as well should import torch before
+the first call here: torch ships its own HIP runtime, and when this library
+has already brought up the system one, torch finds no device.
+
 Conventions (paper Sec. I and II-B): E(x) = sum_{i,j} Q_ij x_i x_j; a state
 is its row ``index`` in the lexicographic matrix U_N (x_0 is the most
 significant bit); the answer is the minimum energy with the lowest index.
@@ -85,6 +89,8 @@ _SIGS = {
                            ctypes.POINTER(_State)]),
     "qubo_solve_device": (_I, [_VP, _I, _I, _I, _VP, ctypes.POINTER(_Result),
                                ctypes.POINTER(_State)]),
+    "qubo_solve_noalloc": (_I, [_VP, _I, _I, _VP, ctypes.POINTER(_Result)]),
+    "qubo_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     "qubo_solve_batch": (_I, [_I, ctypes.POINTER(_VP), ctypes.POINTER(_I), ctypes.POINTER(_I),
                               ctypes.POINTER(_Result)]),
     "qubo_batch_create": (_I, [_I, ctypes.POINTER(_VP), ctypes.POINTER(_I), ctypes.POINTER(_I),
@@ -243,6 +249,20 @@ def solve_device(Qt, k: int = 1, stream=None):
         pairs = [(t.energy if dt == QUBO_FP32 else t.energy_i, int(t.index)) for t in top]
         return res, pairs
     return res
+
+
+def solve_noalloc(Q, stream=None) -> Result:
+    """Best state of a host matrix through ``qubo_solve_noalloc`` (no device
+    allocation: the library's per-device scratch array holds the job)."""
+    Qc, dt = _as_q(Q)
+    out = _Result()
+    s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+    _check(lib().qubo_solve_noalloc(Qc.ctypes.data, Qc.shape[0], dt, s, ctypes.byref(out)))
+    return _result(out, Qc.shape[0])
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib().qubo_noalloc_scratch_bytes())
 
 
 def _batch_args(Qs: Sequence):
