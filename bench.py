@@ -245,7 +245,19 @@ def main():
                     help="skip the n=44 solves (profiling the batched or served kernels alone)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES (HBM counter calibration)")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="only sweep the VALU probe (every op at 1..8 waves per SIMD) and "
+                         "print one JSON line per measurement")
     args = ap.parse_args()
+    if args.valu_probe:
+        import paper_2607_04857_amd as q
+        for op in ("add", "min3", "add+salu", "add+branch", "pk_add16", "pk_min16", "add_3w",
+                   "add_f32"):
+            for w in range(1, 9):
+                rate, ms = q.probe_valu(op, w, 4096)
+                print(json.dumps({"op": op, "waves_per_simd": w, "lane_ops_per_s": rate,
+                                  "ms": ms}), flush=True)
+        return
     if args.copy_probe:
         import torch
         src = torch.ones(args.copy_probe // 4, dtype=torch.int32, device="cuda:0")

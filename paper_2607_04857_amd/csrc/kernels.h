@@ -49,21 +49,28 @@ struct Inst {
     int32_t *K;            // this instance's K table (kslot-th table of the K array)
     const float *Qf;
     ItemRes *res;          // this launch's item results: item g of the launch
-                           // (item_begin <= g < item_end) writes res[g - item_begin]
+                           // (item_begin <= g < item_end) that found a candidate
+                           // writes res[g - item_begin] ...
+    uint32_t *bits;        // ... and sets bit bit0 + (g - item_begin) of the
+                           // instance's item bitmap (bit q <-> res record q of
+                           // the instance; cleared by the table build), so the
+                           // finish reads only records that were written
+    uint64_t bit0;
     int n, A, B, L;
     int direct;            // 1: no walk, direct evaluation of all 2^n states
     int kslot;             // index of the K table in the launch's K array
     uint64_t item_begin;   // this launch's walk-item range [item_begin, item_end)
     uint64_t item_end;
     uint64_t item_local0;  // the instance's own item number of launch item item_begin
-    uint64_t n_items;      // item records the finish reduces (res[0 .. n_items))
+    uint64_t n_items;      // item records of the instance (res[0 .. n_items), bitmap
+                           // words bits[0 .. ceil(n_items / 32)))
     int32_t *gbest;        // best energy any wave has found for the instance
                            // (kNoEnergy from the table build on)
 };
 
 struct ItemRes {
-    int32_t E;         // best energy accepted inside the item (kNoEnergy: none)
-    int32_t found;
+    int32_t E;         // best energy accepted inside the item
+    int32_t found;     // 1 (only items that found a candidate write a record)
     uint64_t row;      // prefix row (U_A row) of that chunk
 };
 
@@ -119,7 +126,8 @@ struct FinalRes {
     int32_t pad;
 };
 
-// Builds M, EB, S, K for every instance and zeroes n_counters item counters.
+// Builds M, EB, S, K for every instance, clears each instance's item bitmap
+// and shared best, and zeroes n_counters item counters.
 hipError_t launch_tables(const Inst *d_insts, int n_inst, int max_A, unsigned long long *d_counters,
                          int n_counters, hipStream_t stream);
 

@@ -207,6 +207,12 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
         atomicExch(I.gbest, kNoEnergy);
         __threadfence();
     }
+    if (I.bits) {   // no item has reported yet
+        const uint64_t words = (I.n_items + 31) / 32;
+        for (uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < words;
+             w += uint64_t(gridDim.x) * blockDim.x)
+            I.bits[w] = 0u;
+    }
     if (I.direct) return;
     const int n = I.n, A = I.A, B = I.B;
     const uint32_t NS = 1u << B;
@@ -614,7 +620,6 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
     // the tables, addressed as global memory (uniform base + lane offset +
     // immediate), not through generic pointers
     const gint32 *M = nullptr, *EB = nullptr, *S = nullptr;
-    ItemRes *ires = nullptr;
     int kbase = 0;                // this instance's K table: kall[kbase ...] (scalar loads)
     int A = 0, L = 0;
     uint64_t item_begin = 0, item_local0 = 0;
@@ -654,7 +659,6 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
             L = I.L;
             item_begin = I.item_begin;
             item_local0 = I.item_local0;
-            ires = I.res;
             static_for<0, G>([&](auto tc) {
                 constexpr int t = decltype(tc)::value;
                 const bool have = t < A;
@@ -1012,15 +1016,22 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
             }
         }
 
-        if (TIER != 3 && lane == 0) {
+        if (TIER != 3 && found && lane == 0) {
+            // Only items that found a candidate leave a record, marked in the
+            // instance's bitmap (the record and bitmap pointers are read from
+            // the descriptor here, on this rare path, rather than held in
+            // registers through the walk).
             ItemRes r;
-            r.E = found ? itemE : kNoEnergy;
-            r.found = found;
-            r.row = found ? itemRow : 0ull;
-            ires[g - item_begin] = r;
+            r.E = itemE;
+            r.found = 1;
+            r.row = itemRow;
+            const uint64_t q = g - item_begin;
+            insts[cur].res[q] = r;
+            const uint64_t b = insts[cur].bit0 + q;
+            atomicOr(insts[cur].bits + (b >> 5), 1u << (b & 31));
             // publish once per item: every wave starting an item of this
             // instance at once would otherwise contend on one address
-            if (found) atomicMin(gbest, itemE);
+            atomicMin(gbest, itemE);
         }
     }
     if constexpr (TIER == 3) tk_flush();
@@ -1028,37 +1039,52 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
 
 // ---------------------------------------------------------------- finish
 
+// Lexicographic (E, index) minimum over the block: butterflies inside each
+// wave, then the wave results through LDS (sE, sI: one slot per wave).
 __device__ void block_lexmin(int64_t &bE, uint64_t &bI, int64_t *sE, uint64_t *sI)
 {
-    const int t = threadIdx.x;
-    sE[t] = bE;
-    sI[t] = bI;
-    __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-        if (t < off) {
-            int64_t e = sE[t + off];
-            uint64_t i = sI[t + off];
-            if (e < sE[t] || (e == sE[t] && i < sI[t])) {
-                sE[t] = e;
-                sI[t] = i;
-            }
-        }
-        __syncthreads();
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) {
+        const int64_t e = __shfl_xor(bE, off, kWave);
+        const uint64_t i = __shfl_xor(bI, off, kWave);
+        lexmin(bE, bI, e, i);
     }
-    bE = sE[0];
-    bI = sI[0];
+    const int w = int(threadIdx.x) / kWave, nw = int(blockDim.x) / kWave;
+    if (int(threadIdx.x) % kWave == 0) {
+        sE[w] = bE;
+        sI[w] = bI;
+    }
+    __syncthreads();
+    bE = INT64_MAX;
+    bI = ~0ull;
+    for (int k = 0; k < nw; k++) lexmin(bE, bI, sE[k], sI[k]);
     __syncthreads();
 }
 
-constexpr int kFinishThreads = 1024;   // the record reduction is latency-bound: many loads in flight
+// Energy of U_N row idx from T staged in LDS, one lane per variable (the
+// whole wave must call it): the same sum as energy_int.
+__device__ int64_t wave_energy(const int32_t *T, int n, uint64_t idx)
+{
+    const int l = int(threadIdx.x) % kWave;
+    int64_t part = 0;
+    if (l < n && ((idx >> (n - 1 - l)) & 1)) {
+        for (int j = l; j < n; j++)
+            if ((idx >> (n - 1 - j)) & 1) part += T[l * n + j];
+    }
+    return wave_sum64(part);
+}
+
+constexpr int kFinishThreads = 1024;
 
 __global__ __launch_bounds__(kFinishThreads) void finish_kernel(const Inst *__restrict__ insts,
                                                                 FinalRes *__restrict__ out)
 {
-    __shared__ int64_t sE[kFinishThreads];
-    __shared__ uint64_t sI[kFinishThreads];
+    __shared__ int64_t sE[kFinishThreads / kWave];
+    __shared__ uint64_t sI[kFinishThreads / kWave];
+    __shared__ int64_t sC[kMaxVars];   // suffix fields of the winning chunk
+    __shared__ int64_t sEp;            // its prefix energy
     // T (and the caller's float32 Q) staged in LDS: every energy below reads
-    // O(n^2) entries, and the float64 rescore runs on one thread in a fixed
+    // entries of T, and the float64 rescore runs on one thread in a fixed
     // order, where global-memory latency would dominate
     __shared__ int32_t sT[kMaxVars * kMaxVars];
     __shared__ float sQ[kMaxVars * kMaxVars];
@@ -1077,22 +1103,16 @@ __global__ __launch_bounds__(kFinishThreads) void finish_kernel(const Inst *__re
         for (uint64_t r = threadIdx.x; r < N; r += blockDim.x) lexmin(bE, bI, energy_int(sT, n, r), r);
         block_lexmin(bE, bI, sE, sI);
     } else {
-        // eight independent record loads in flight per thread: the loop is
-        // bound by memory latency, not by the comparisons
-        constexpr int U = 8;
-        const uint64_t bd = blockDim.x;
-        uint64_t k = threadIdx.x;
-        for (; k + (U - 1) * bd < I.n_items; k += U * bd) {
-            ItemRes r[U];
-#pragma unroll
-            for (int u = 0; u < U; u++) r[u] = I.res[k + u * bd];
-#pragma unroll
-            for (int u = 0; u < U; u++)
-                if (r[u].found) lexmin(bE, bI, r[u].E, r[u].row);
-        }
-        for (; k < I.n_items; k += bd) {
-            const ItemRes r = I.res[k];
-            if (r.found) lexmin(bE, bI, r.E, r.row);
+        // the records of items whose bit is set (the others were never written)
+        const uint64_t words = (I.n_items + 31) / 32;
+        for (uint64_t w = threadIdx.x; w < words; w += blockDim.x) {
+            uint32_t x = I.bits[w];
+            while (x) {
+                const uint32_t b = uint32_t(__builtin_ctz(x));
+                x &= x - 1u;
+                const ItemRes r = I.res[w * 32 + b];
+                lexmin(bE, bI, r.E, r.row);
+            }
         }
         block_lexmin(bE, bI, sE, sI);
         const int64_t Estar = bE;
@@ -1100,18 +1120,49 @@ __global__ __launch_bounds__(kFinishThreads) void finish_kernel(const Inst *__re
         if (Estar == INT64_MAX) {
             status = 2;   // no item reported a candidate
         } else {
-            // Argmin reconstruction (ConstructState of Alg. 2): lowest suffix
-            // of chunk rowstar whose energy equals E*.
+            // Argmin reconstruction (ConstructState of Alg. 2): the lowest
+            // suffix s of chunk rowstar whose energy equals E*, from T.  With
+            // the prefix fixed, E(row, s) = E_p(row) + sum_{t in s} c_t +
+            // sum_{t < u in s} T[A+t][A+u] (Sec. II-C), where c_t = T[A+t][A+t]
+            // + sum over the set prefix variables v of T[v][A+t].
+            const int A = I.A, B = I.B;
+            if (threadIdx.x < kWave) {
+                const int l = int(threadIdx.x);
+                int64_t part = 0;
+                if (l < A && ((rowstar >> (A - 1 - l)) & 1)) {
+                    for (int j = l; j < A; j++)
+                        if ((rowstar >> (A - 1 - j)) & 1) part += sT[l * n + j];
+                }
+                part = wave_sum64(part);
+                if (l == 0) sEp = part;
+                if (l < B) {
+                    int64_t c = sT[(A + l) * n + (A + l)];
+                    for (int v = 0; v < A; v++)
+                        if ((rowstar >> (A - 1 - v)) & 1) c += sT[v * n + A + l];
+                    sC[l] = c;
+                }
+            }
+            __syncthreads();
             bE = INT64_MAX;
             bI = ~0ull;
-            const uint32_t NS = 1u << I.B;
+            const uint32_t NS = 1u << B;
             for (uint32_t s = threadIdx.x; s < NS; s += blockDim.x) {
-                const uint64_t idx = (rowstar << I.B) | s;
-                const int64_t e = energy_int(sT, n, idx);
-                if (e == Estar) lexmin(bE, bI, e, idx);
+                int64_t e = sEp;
+                for (int t = 0; t < B; t++) {
+                    if (!((s >> (B - 1 - t)) & 1)) continue;
+                    e += sC[t];
+                    for (int u = t + 1; u < B; u++)
+                        if ((s >> (B - 1 - u)) & 1) e += sT[(A + t) * n + A + u];
+                }
+                if (e == Estar) lexmin(bE, bI, e, (rowstar << B) | s);
             }
             block_lexmin(bE, bI, sE, sI);
-            if (bE != Estar) status = 3;  // walk claimed an energy the chunk lacks
+            if (bE != Estar) {
+                status = 3;   // the walk claimed an energy the chunk lacks
+            } else if (threadIdx.x < kWave) {
+                // the winner evaluated in full from T must agree
+                if (wave_energy(sT, n, bI) != Estar) status = 3;
+            }
         }
     }
     if (threadIdx.x == 0) {

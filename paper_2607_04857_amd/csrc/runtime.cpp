@@ -18,7 +18,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct JobOffsets {
     size_t insts = 0, counter = 0, res = 0, out = 0, K = 0, gbest = 0;
-    std::vector<size_t> T, Qf, M, EB, S;
+    std::vector<size_t> T, Qf, M, EB, S, bits;
     // top-k (k > 1, one instance)
     size_t gthr = 0, hist = 0, lowbin = 0, candN = 0, candE = 0, candR = 0, listE = 0, listR = 0, listCount = 0, chunkE = 0, chunkR = 0, chunkCount = 0,
            stE = 0, stI = 0, segCount = 0, selE = 0, selR = 0, selCount = 0, topk = 0;
@@ -108,6 +108,13 @@ static JobOffsets compute_offsets(const Job &job, size_t *stage_bytes, size_t *b
     off = align_up(off + ni * qk::kKTable * sizeof(int32_t), 256);
     o.res = off;
     off = align_up(off + size_t(job.total_items) * sizeof(qk::ItemRes), 256);
+    // one bit per item record of each instance (which records were written)
+    for (size_t i = 0; i < ni; i++) {
+        const qplan::Plan &P = job.plans[i];
+        const size_t words = P.direct ? 0 : size_t((P.walk_items() + 31) / 32);
+        o.bits.push_back(off);
+        off = align_up(off + std::max<size_t>(words, 1) * sizeof(uint32_t), 256);
+    }
     o.out = off;
     off = align_up(off + ni * sizeof(qk::FinalRes), 256);
     o.gbest = off;
@@ -230,6 +237,8 @@ qubo_status_t job_bind(Job *job, void *d_mem)
         I.K = reinterpret_cast<int32_t *>(base + o.K) + i * qk::kKTable;
         I.Qf = job->qf[i] ? reinterpret_cast<const float *>(base + o.Qf[i]) : nullptr;
         I.res = job->d_res + item;
+        I.bits = P.direct ? nullptr : reinterpret_cast<uint32_t *>(base + o.bits[i]);
+        I.bit0 = 0;
         I.n = P.n;
         I.A = P.A;
         I.B = P.B;

@@ -278,6 +278,7 @@ qubo_status_t enqueue_tick(qubo_server *s, TickBuf &t, bool *launched)
         I.item_end = g + c;
         I.item_local0 = r->next_item;
         I.res = r->base.res + r->next_item;
+        I.bit0 = r->next_item;          // I.bits: the request's whole bitmap
         t.h_walk[nw++] = I;
         g += c;
         launches.back().count++;

@@ -36,10 +36,11 @@ ENTRIES = {
     "n24_int_u100_s1": ("uniform_int", dict(n=24, lo=-100, hi=100, seed=1), "O1", 16),
     "n36_int_u1000_s2": ("uniform_int", dict(n=36, lo=-1000, hi=1000, seed=2), "O2", 1),
     "n36_planted_u1000_s3": ("planted", dict(n=36, lo=-1000, hi=1000, seed=3), "O2", 1),
-    "n30_int_u1000_s10": ("uniform_int", dict(n=30, lo=-1000, hi=1000, seed=10), "O1", 4),
+    "n30_int_u1000_s10": ("uniform_int", dict(n=30, lo=-1000, hi=1000, seed=10), "O1", 1024),
+    "n32_int_u1000_s14": ("uniform_int", dict(n=32, lo=-1000, hi=1000, seed=14), "O1", 1024),
     "n31_int_u10000_s11": ("uniform_int", dict(n=31, lo=-10000, hi=10000, seed=11), "O2", 1),
     "n33_int_u100_s12": ("uniform_int", dict(n=33, lo=-100, hi=100, seed=12), "O2", 1),
-    "n28_fp32_s6": ("normal_fp32", dict(n=28, seed=6), "O1", 4),
+    "n28_fp32_s6": ("normal_fp32", dict(n=28, seed=6), "O1", 1024),
     "n32_fp32_s13": ("normal_fp32", dict(n=32, seed=13), "O2", 1),
 }
 

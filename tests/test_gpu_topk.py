@@ -112,7 +112,7 @@ def test_full_size_properties(orc):
     print(f"n=40 k=64: walk {res.kernel_ms:.1f} ms (k=1: {one.kernel_ms:.1f} ms)", flush=True)
 
 
-def test_stored_oracle_topk():
+def test_stored_oracle_topk(orc):
     """The stored oracle answers (written by tests/golden/make_oracle_goldens.py
     from oracle/ alone) include top-k lists up to n = 33."""
     import json
@@ -131,7 +131,14 @@ def test_stored_oracle_topk():
         if g["dtype"] == "int32":
             assert pairs == [(int(e), int(i)) for e, i in ref], name
         else:
-            for (e, _), (re_, _) in zip(pairs, ref):
+            # each reported energy is the oracle's float64 energy of that state,
+            # the states are distinct and ordered by (energy, index), and the
+            # i-th energy is within tol of the oracle's i-th smallest
+            scale = float(np.abs(Q.astype(np.float64)).sum())
+            assert len({i for _, i in pairs}) == len(pairs), name
+            assert pairs == sorted(pairs), name
+            for (e, i), (re_, _) in zip(pairs, ref):
+                assert abs(orc.energy(Q, i) - e) <= 1e-9 * scale + 1e-12, name
                 assert abs(e - re_) <= res.tol, name
         checked += 1
         print(f"{name}: top-{len(ref)} ok", flush=True)
