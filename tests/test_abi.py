@@ -87,6 +87,26 @@ def test_fp32_fixed_point_scale():
     assert info["eps_q"] * 2 <= 1e-5 * np.abs(Q.astype(np.float64)).sum()
 
 
+@pytest.mark.parametrize("n,full", [(60, False), (60, True), (46, False), (20, True)])
+def test_fp32_tolerance_bound(n, full):
+    """tol = 2 eps_q = nnz 2^-p, and p is the largest exponent with
+    S 2^p <= 2^29 (S = sum |T|), so tol < nnz S / 2^28 <= n(n+1)/2 * sum|Q| / 2^28:
+    at most 6.9e-6 sum|Q| for every n <= 60, under the 1e-5 bound."""
+    rng = np.random.default_rng(n)
+    Q = rng.standard_normal((n, n)).astype(np.float32)
+    if not full:
+        Q = np.triu(Q)
+    info = q.plan_info(Q)
+    T = np.triu(Q.astype(np.float64)) + np.tril(Q.astype(np.float64), -1).T
+    S = np.abs(T).sum()
+    nnz = int(np.count_nonzero(T))
+    tol = 2 * info["eps_q"]
+    assert tol == pytest.approx(nnz * 2.0 ** -info["p"])
+    assert tol < nnz * S / 2 ** 28
+    sq = float(np.abs(Q.astype(np.float64)).sum())
+    assert tol < n * (n + 1) / 2 * sq / 2 ** 28 <= 6.9e-6 * sq
+
+
 def test_fp32_zero_and_nonfinite():
     assert q.plan_info(np.zeros((16, 16), dtype=np.float32))["p"] == 0
     Q = inputs.normal_fp32(16, 4)
