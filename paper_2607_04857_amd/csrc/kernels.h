@@ -75,8 +75,8 @@ struct ItemRes {
 };
 
 // Top-k (k > 1) state of one walk launch over a single instance.  Each
-// wave keeps, in LDS, the k smallest chunk keys (E_p + min over the chunk,
-// prefix row) it has met; a chunk can belong to the instance's k smallest
+// wave keeps, in listE / listR (its slot of k entries), the k smallest chunk
+// keys (E_p + min over the chunk, prefix row) it has met; a chunk can belong to the instance's k smallest
 // chunks only if its minimum is at most the largest E of any full list, so
 // waves share that bound through gthr (atomic min).
 struct TopkWalk {
@@ -148,11 +148,12 @@ bool walk_variant_exists(int mcols, int vgpr_levels);
 // topk_k > 1 accounts for tier 3's LDS list.
 int walk_occupancy(int mcols, int vgpr_levels, int tier, int topk_k = 0);
 
-// LDS bytes of one tier-3 wave's list.
-constexpr int kTopkMetaWords = 13;  // 64-bit words of list scalars ahead of the entries
-__host__ __device__ inline size_t topk_lds_bytes(int k)
+// LDS bytes of one tier-3 wave's list scalars (its k entries are in listE /
+// listR in global memory).
+constexpr int kTopkMetaWords = 13;  // 64-bit words of list scalars
+__host__ __device__ inline size_t topk_lds_bytes()
 {
-    return size_t(kTopkMetaWords) * 8 + size_t(k) * (sizeof(uint64_t) + sizeof(int32_t));
+    return size_t(kTopkMetaWords) * 8;
 }
 
 // Top-k finish of one instance (descriptor d_inst, host copy hI): select the

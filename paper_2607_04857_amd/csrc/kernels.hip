@@ -377,7 +377,8 @@ constexpr int walk_waves_per_simd()
 // Bytes of dynamic LDS ahead of the LDS rows (the tier-3 list), 16-aligned.
 __host__ __device__ inline size_t lds_rows_offset(int tier, int k)
 {
-    return tier == 3 ? (topk_lds_bytes(k) + 15) & ~size_t(15) : 0;
+    (void)k;
+    return tier == 3 ? (topk_lds_bytes() + 15) & ~size_t(15) : 0;
 }
 template <int MC>
 constexpr size_t lds_rows_bytes()
@@ -385,11 +386,16 @@ constexpr size_t lds_rows_bytes()
     return size_t(2) * MC * kWave * sizeof(int32_t);
 }
 
-// ---- tier-3 list (top-k).  One wave per workgroup; the list lives in
-// dynamic LDS: kTopkMetaWords 64-bit words of scalars, then k rows and k
-// energies.  All list state stays in LDS (not SGPRs) and the list code sits
-// in functions that are not inlined: only the rare candidate path touches
-// it, and the walk's registers stay those of tier 2.
+// ---- tier-3 list (top-k).  One wave per workgroup.  The list's scalars
+// live in dynamic LDS (kTopkMetaWords 64-bit words); its k entries (E and
+// prefix row) live in global memory, at listE / listR + blockIdx.x * k, and
+// entry p is written and read only by lane p % 64, so each lane reads its own
+// earlier writes in program order and no fence is needed.  Only the rare
+// candidate path touches the entries (from L2), and the LDS stays free for
+// the row cache, so tier 3 runs the LDS row-cache variants at four waves per
+// SIMD whatever k is.  No list state is held in registers and the list code
+// sits in functions that are not inlined: the walk's registers stay those of
+// tier 2.
 //   M[0] entries used  M[1] slot of the largest key  M[2] its E (kNoEnergy
 //   until the list is full)  M[3] lowest shared bound seen  M[4] k
 //   M[5] histogram bin shift
@@ -409,8 +415,15 @@ extern __shared__ uint64_t tk_lds[];
 
 __device__ __forceinline__ int32_t *tk_M() { return reinterpret_cast<int32_t *>(tk_lds); }
 __device__ __forceinline__ uint64_t *tk_P() { return tk_lds + 4; }
-__device__ __forceinline__ uint64_t *tk_R() { return tk_lds + kTopkMetaWords; }
-__device__ __forceinline__ int32_t *tk_E(int k) { return reinterpret_cast<int32_t *>(tk_R() + k); }
+// this wave's k list entries in global memory
+__device__ __forceinline__ int32_t *tk_E(int k)
+{
+    return reinterpret_cast<int32_t *>(sread64(tk_P()[2])) + size_t(blockIdx.x) * size_t(k);
+}
+__device__ __forceinline__ uint64_t *tk_R(int k)
+{
+    return reinterpret_cast<uint64_t *>(sread64(tk_P()[3])) + size_t(blockIdx.x) * size_t(k);
+}
 __device__ __forceinline__ int32_t *tk_gthr()
 {
     return reinterpret_cast<int32_t *>(sread64(tk_P()[1]));
@@ -456,10 +469,10 @@ __device__ __noinline__ int32_t tk_threshold()
 // E to the shared bound; returns that E.
 __device__ int32_t tk_rescan(int k)
 {
-    __syncthreads();              // lane 0's LDS stores are visible to the wave
+    __syncthreads();              // lane 0's LDS scalar stores are visible to the wave
     const int lane = int(threadIdx.x);
     const int32_t *E = tk_E(k);
-    const uint64_t *R = tk_R();
+    const uint64_t *R = tk_R(k);
     int32_t mE = INT32_MIN;
     uint64_t mR = 0;
     int mP = 0;
@@ -553,11 +566,11 @@ __device__ __noinline__ int32_t tk_insert(int32_t Ec, uint64_t rc)
     bool entered = false;
     if (cnt < k) {
         __syncthreads();
-        if (threadIdx.x == 0) {
+        if (int(threadIdx.x) == cnt % kWave) {   // the lane that owns entry cnt
             tk_E(k)[cnt] = Ec;
-            tk_R()[cnt] = rc;
-            M[0] = cnt + 1;
+            tk_R(k)[cnt] = rc;
         }
+        if (threadIdx.x == 0) M[0] = cnt + 1;
         entered = true;
         if (cnt + 1 == k) lkth = tk_rescan(k);
     } else {
@@ -565,9 +578,9 @@ __device__ __noinline__ int32_t tk_insert(int32_t Ec, uint64_t rc)
         if (Ec < lkth || (Ec == lkth && rc < lkR)) {
             const int pos = sread(M[1]);
             __syncthreads();
-            if (threadIdx.x == 0) {
+            if (int(threadIdx.x) == pos % kWave) {   // the lane that owns entry pos
                 tk_E(k)[pos] = Ec;
-                tk_R()[pos] = rc;
+                tk_R(k)[pos] = rc;
             }
             entered = true;
             lkth = tk_rescan(k);
@@ -581,20 +594,14 @@ __device__ __noinline__ int32_t tk_insert(int32_t Ec, uint64_t rc)
     return min(lkth, sread(M[3]));
 }
 
-// Copy the wave's list to listE/listR at slot blockIdx.x * k.
+// Publish the number of entries of the wave's list (the entries are already
+// in listE / listR at slot blockIdx.x * k).
 __device__ __noinline__ void tk_flush()
 {
     __syncthreads();
     const int32_t *M = tk_M();
     const uint64_t *P = tk_P();
     const int cnt = sread(M[0]);
-    const int k = sread(M[4]);
-    int32_t *gE = reinterpret_cast<int32_t *>(sread64(P[2])) + size_t(blockIdx.x) * size_t(k);
-    uint64_t *gR = reinterpret_cast<uint64_t *>(sread64(P[3])) + size_t(blockIdx.x) * size_t(k);
-    for (int p = int(threadIdx.x); p < cnt; p += kWave) {
-        gE[p] = tk_E(k)[p];
-        gR[p] = tk_R()[p];
-    }
     if (threadIdx.x == 0) reinterpret_cast<int32_t *>(sread64(P[4]))[blockIdx.x] = cnt;
 }
 
@@ -952,10 +959,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
             const uint32_t nsb = uint32_t(sbEnd - sb0);
             for (uint32_t ks = 0; ks < nsb; ks++) {
                 const uint64_t sb = sb0 + ks;
-                // (tier 3, short of registers for its lists, keeps the
-                // wave minimum instead of the lane minimum)
-                if constexpr (TIER == 3) W0 = wave_min_bcast(tree_min<MC>(E));
-                else lm0 = tree_min<MC>(E);
+                lm0 = tree_min<MC>(E);
                 static_for<0, 2>([&](auto hc) {
                     constexpr int h = decltype(hc)::value;
                     // the 16 steps of half h, with (CHECK) or without the
@@ -992,11 +996,9 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                     static_for<0, kLowLevels>([&](auto tc) { tb -= min(0, H[decltype(tc)::value]); });
                     // any lane at or below the bound (the wave minimum W0 is
                     // formed only then)
-                    bool cold;
-                    if constexpr (TIER == 3) cold = W0 <= tb;
-                    else cold = __builtin_amdgcn_ballot_w64(lm0 <= tb) != 0;
+                    const bool cold = __builtin_amdgcn_ballot_w64(lm0 <= tb) != 0;
                     if (__builtin_expect(cold, 0)) {
-                        if constexpr (TIER != 3) W0 = wave_min_bcast(lm0);
+                        W0 = wave_min_bcast(lm0);
                         // exact per-step thresholds and tests
                         build_tp(h, tab2);
                         static_for<0, H16>([&](auto oc) {

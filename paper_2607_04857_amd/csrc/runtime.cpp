@@ -483,10 +483,12 @@ qubo_status_t solve_host(const void *Q, int n, qubo_dtype_t dtype, int k, const 
         qplan::Plan &P = job.plans[0];
         if (!P.direct) {
             P.tier = 3;
-            // The LDS row cache shares LDS with the list.  While both fit four
-            // waves per SIMD the variant with levels 0-2 in VGPRs is the
-            // fastest top-k walk (its registers leave room for the list
-            // code); beyond that the VGPR row cache (three waves) wins.
+            // The list entries live in global memory and only their scalars
+            // in LDS, so the LDS row cache keeps four waves per SIMD for any
+            // k; its variant with levels 0-2 in VGPRs is the fastest top-k
+            // walk (its registers leave room for the list code).  Should it
+            // ever not fit four waves, the VGPR row cache (three waves) is
+            // taken instead.
             if ((P.vgpr_levels == 4 || P.vgpr_levels == 3) && !(opt && opt->vgpr_levels))
                 P.vgpr_levels = qk::walk_occupancy(P.mcols, 3, 3, k) >= 4 * 4 ? 3 : 6;
         }
