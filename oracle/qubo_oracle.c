@@ -344,14 +344,22 @@ static inline __attribute__((always_inline)) void o2_walk_f_np(o2_job_t *j, cons
 
 /* The walk proper, compiled for several instruction sets; the loader picks
  * the widest one the host supports (results do not depend on the choice:
- * every step is exact integer arithmetic or the same double additions). */
-__attribute__((target_clones("avx512f", "avx2", "default")))
+ * every step is exact integer arithmetic or the same double additions).
+ * Sanitizer builds define ORACLE_NO_TARGET_CLONES: the loader resolves the
+ * clones (ifunc) before a sanitizer runtime has started. */
+#ifdef ORACLE_NO_TARGET_CLONES
+#define O2_CLONES
+#else
+#define O2_CLONES __attribute__((target_clones("avx512f", "avx2", "default")))
+#endif
+
+O2_CLONES
 static void o2_walk_i(o2_job_t *j)
 {
     O2_DISPATCH(o2_walk_i_np, j)
 }
 
-__attribute__((target_clones("avx512f", "avx2", "default")))
+O2_CLONES
 static void o2_walk_f(o2_job_t *j)
 {
     O2_DISPATCH(o2_walk_f_np, j)

@@ -20,119 +20,16 @@
 #include <cstring>
 #include <string>
 
+#include "hostio.h"
 #include "plan.h"
 #include "runtime.h"
 
 namespace {
 
-constexpr const char *kMagic = "qubo-checkpoint 1";
-
-struct Ckpt {
-    int n = 0;
-    int dtype = 0;
-    uint64_t qhash = 0;
-    int A = 0, B = 0, L = 0, tier = 0, vgpr_levels = 0;
-    uint64_t items = 0, next_item = 0;
-    int found = 0;
-    int64_t energy_i = 0;
-    double energy = 0.0;
-    uint64_t index = 0;
-    int p = 0;
-    double tol = 0.0;
-    double walk_ms = 0.0;
-};
-
-// FNV-1a, 64 bit, over n, the dtype and the n*n input words.
-uint64_t input_hash(const void *Q, int n, qubo_dtype_t dtype)
-{
-    uint64_t h = 0xcbf29ce484222325ull;
-    auto mix = [&h](unsigned char b) {
-        h ^= b;
-        h *= 0x100000001b3ull;
-    };
-    const uint32_t head[2] = {uint32_t(n), uint32_t(dtype)};
-    for (uint32_t w : head)
-        for (int b = 0; b < 4; ++b) mix(static_cast<unsigned char>(w >> (8 * b)));
-    const unsigned char *p = static_cast<const unsigned char *>(Q);
-    for (size_t i = 0; i < size_t(n) * n * 4; ++i) mix(p[i]);
-    return h;
-}
-
-bool write_ckpt(const char *path, const Ckpt &c, std::string *msg)
-{
-    const std::string tmp = std::string(path) + ".tmp";
-    FILE *f = std::fopen(tmp.c_str(), "w");
-    if (!f) {
-        *msg = "cannot write " + tmp + ": " + std::strerror(errno);
-        return false;
-    }
-    int w = std::fprintf(
-        f,
-        "%s\nn %d\ndtype %d\nqhash %016llx\nplan %d %d %d %d %d\nitems %llu\nnext_item %llu\n"
-        "found %d\nenergy_i %lld\nenergy %.17g\nindex %llu\np %d\ntol %.17g\nwalk_ms %.17g\n",
-        kMagic, c.n, c.dtype, static_cast<unsigned long long>(c.qhash), c.A, c.B, c.L, c.tier,
-        c.vgpr_levels, static_cast<unsigned long long>(c.items),
-        static_cast<unsigned long long>(c.next_item), c.found, static_cast<long long>(c.energy_i),
-        c.energy, static_cast<unsigned long long>(c.index), c.p, c.tol, c.walk_ms);
-    bool ok = w > 0 && std::fflush(f) == 0;
-    ok = (std::fclose(f) == 0) && ok;
-    if (!ok) {
-        *msg = "write failed: " + tmp;
-        return false;
-    }
-    if (std::rename(tmp.c_str(), path) != 0) {
-        *msg = std::string("cannot rename to ") + path + ": " + std::strerror(errno);
-        return false;
-    }
-    return true;
-}
-
-// 1: read; 0: no such file; -1: unreadable or malformed (msg set).
-int read_ckpt(const char *path, Ckpt *c, std::string *msg)
-{
-    FILE *f = std::fopen(path, "r");
-    if (!f) {
-        if (errno == ENOENT) return 0;
-        *msg = std::string("cannot read ") + path + ": " + std::strerror(errno);
-        return -1;
-    }
-    char magic[64] = {0};
-    unsigned long long qh = 0, items = 0, next = 0, index = 0;
-    long long ei = 0;
-    int got = 0;
-    bool ok = std::fgets(magic, sizeof magic, f) != nullptr &&
-              std::strncmp(magic, kMagic, std::strlen(kMagic)) == 0 &&
-              (magic[std::strlen(kMagic)] == '\n' || magic[std::strlen(kMagic)] == 0);
-    if (ok) {
-        got = std::fscanf(f,
-                          " n %d dtype %d qhash %llx plan %d %d %d %d %d items %llu next_item %llu"
-                          " found %d energy_i %lld energy %lg index %llu p %d tol %lg walk_ms %lg",
-                          &c->n, &c->dtype, &qh, &c->A, &c->B, &c->L, &c->tier, &c->vgpr_levels,
-                          &items, &next, &c->found, &ei, &c->energy, &index, &c->p, &c->tol,
-                          &c->walk_ms);
-        ok = got == 17;
-    }
-    if (ok) {
-        char extra[8];
-        ok = std::fscanf(f, " %7s", extra) == EOF;   // nothing may follow
-    }
-    std::fclose(f);
-    c->qhash = qh;
-    c->items = items;
-    c->next_item = next;
-    c->energy_i = ei;
-    c->index = index;
-    if (ok)
-        ok = c->n >= 1 && c->n <= qplan::kMaxN && (c->dtype == QUBO_INT32 || c->dtype == QUBO_FP32) &&
-             c->next_item <= c->items && (c->found == 0 || c->found == 1) &&
-             (c->found || c->next_item == 0) && c->index < (uint64_t(1) << c->n) &&
-             (c->B == 0 || c->A + c->B == c->n) && c->walk_ms >= 0.0;
-    if (!ok) {
-        *msg = std::string("malformed checkpoint ") + path;
-        return -1;
-    }
-    return 1;
-}
+using qhost::Ckpt;
+using qhost::input_hash;
+using qhost::read_ckpt;
+using qhost::write_ckpt;
 
 void to_result(const Ckpt &c, uint64_t states_done, double total_ms, qubo_result_t *out)
 {

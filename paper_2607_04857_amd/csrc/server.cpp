@@ -29,6 +29,7 @@
 #include <unordered_map>
 
 #include "runtime.h"
+#include "serve_policy.h"
 
 namespace {
 
@@ -151,13 +152,20 @@ void complete_tick(qubo_server *s, TickBuf &t)
     s->cv_done.notify_all();
 }
 
-// Admit queued requests; returns the newly admitted ones (device set-up pending).
+// Admit queued requests (policy: qsched::admit_count); returns the newly
+// admitted ones (device set-up pending).
 std::vector<Request *> take_admissions(qubo_server *s)
 {
     std::vector<Request *> adm;
-    while (!s->queue.empty() && int(s->active.size()) < s->max_slots && !s->free_kslots.empty()) {
+    std::vector<size_t> bytes;
+    bytes.reserve(s->queue.size());
+    for (const Request *r : s->queue) bytes.push_back(r->job.bytes);
+    const size_t free_slots = std::min(size_t(s->max_slots) - std::min(size_t(s->max_slots),
+                                                                      s->active.size()),
+                                       s->free_kslots.size());
+    size_t n_adm = qsched::admit_count(bytes, s->mem_used, s->budget, free_slots);
+    for (; n_adm > 0; n_adm--) {
         Request *r = s->queue.front();
-        if (s->mem_used + r->job.bytes > s->budget) break;   // wait for memory to free up
         s->queue.pop_front();
         s->mem_used += r->job.bytes;
         s->mem_peak = std::max(s->mem_peak, s->mem_used);
@@ -235,24 +243,15 @@ qubo_status_t enqueue_tick(qubo_server *s, TickBuf &t, bool *launched)
     std::sort(walkers.begin(), walkers.end(), [](Request *a, Request *b) {
         return a->job.plans[0].items - a->next_item < b->job.plans[0].items - b->next_item;
     });
-    std::vector<uint64_t> share(walkers.size(), 0);
-    // Under a backlog the tick grows: doubled past four ticks' work, and
-    // doubled again for every further factor of two, up to 16x: fewer tick
+    // Under a backlog the tick grows (qsched::tick_scale): fewer tick
     // boundaries (each costs a drain of the walk grid and a finish launch),
     // at no cost in latency since requests queue anyway.
-    uint64_t backlog = 0;
-    for (Request *r : walkers) backlog += r->job.plans[0].items - r->next_item;
-    uint64_t scale = 1;
-    while (scale < 16 && backlog > 4 * scale * s->tick_items) scale *= 2;
-    uint64_t budget = scale * s->tick_items, total = 0;
-    for (size_t k = 0; k < walkers.size(); k++) {
-        Request *r = walkers[k];
-        const uint64_t left = r->job.plans[0].items - r->next_item;
-        const uint64_t fair = std::max<uint64_t>(1, budget / (walkers.size() - k));
-        share[k] = std::min(left, fair);
-        budget = budget > share[k] ? budget - share[k] : 0;
-        total += share[k];
-    }
+    std::vector<uint64_t> left(walkers.size());
+    for (size_t k = 0; k < walkers.size(); k++)
+        left[k] = walkers[k]->job.plans[0].items - walkers[k]->next_item;
+    const std::vector<uint64_t> share = qsched::tick_shares(left, s->tick_items);
+    uint64_t total = 0;
+    for (uint64_t c : share) total += c;
     if (total == 0 && finishers.empty()) return QUBO_OK;
     // descriptors grouped by variant; item numbering restarts in every group
     std::vector<size_t> idx(walkers.size());
