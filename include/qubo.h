@@ -90,7 +90,7 @@ typedef struct {
 
 /* Plan overrides, mainly for tests and the autotuner.  Zero-initialise for the
  * defaults.  B: suffix bits in [6, 10] (0 = default 10); L: log2 Gray steps per
- * work item in [5, A] (0 = default); tier: 0 = default, 1 or 2 to force that
+ * work item in [6, A] (0 = default); tier: 0 = default, 1 or 2 to force that
  * walk tier; waves_per_cu: resident walk waves per compute unit (0 = the
  * occupancy limit); vgpr_levels: see below.
  * item_first, item_count: walk only work items [item_first, item_first +

@@ -9,16 +9,18 @@
 //   EB  [2^B]         suffix energies E_s(U_B) (Sec. III-A, preprocessing 2)
 //   S   [A][64]       S[w][l] = T[min(l,w)][max(l,w)] for l != w < A, else 0:
 //                     the prefix couplings, one lane per variable
-//   K   [6][16]+[4]   (all instances' K tables are contiguous) tier-2 bound
-//                     constants per super-block offset o and table (0: o < 16;
-//                     1: o >= 16, level-4 bit rising; 2: o >= 16, falling):
-//                     rows 0..2 hold C2 = ELOW + D, rows 3..5 hold D, where D
-//                     is the minimum over all 2^B columns of E_sd(o) -
-//                     E_sd(super-block start) and ELOW the low-low coupling
-//                     energy of the low pattern at o; then min_o C2 per table;
-//                     then SL[64][4]: SL[w][t] = coupling of prefix variable w
-//                     with the low variable A-1-t (0 when equal), so a flip of
-//                     w moves the low fields by scalar loads only
+//   K   [6][32]+[8]   (all instances' K tables are contiguous) tier-2 bound
+//                     constants per 64-step super-block offset o and table
+//                     (0: o < 32; 1: o >= 32, level-5 bit rising; 2: o >= 32,
+//                     falling), entry o mod 32: rows 0..2 hold C2 = ELOW + D,
+//                     rows 3..5 hold D, where D is the minimum over all 2^B
+//                     columns of E_sd(o) - E_sd(super-block start) and ELOW
+//                     the low-low coupling energy of the low pattern at o;
+//                     then the minimum of C2 over each 16-step segment
+//                     (table tab, segment h: entry 2 tab + h mod 2); then
+//                     SL[64][5]: SL[w][t] = coupling of prefix variable w
+//                     with the low variable A-1-t (0 when equal), so a flip
+//                     of w moves the low fields by scalar loads only
 //   Qf  [n][n] fp32   caller's float32 Q (fp32 instances only, for rescoring)
 #pragma once
 
@@ -28,12 +30,16 @@
 namespace qk {
 
 constexpr int kWave = 64;
-constexpr int kSuperLog = 5;          // unrolled super-block: 32 Gray steps
-constexpr int kLowLevels = 4;         // Gray levels with static patterns in a super-block
+constexpr int kSuperLog = 6;          // unrolled super-block: 64 Gray steps
+constexpr int kLowLevels = 5;         // Gray levels with static patterns in a super-block
 constexpr int kPatterns = 1 << kLowLevels;
-constexpr int kKC2Min = 6 * kPatterns;   // min over o of C2 per table (3 used of 4)
-constexpr int kKBound = kKC2Min + 4;     // bound constants at the head of a K table
-constexpr int kKTable = kKBound + 4 * kWave;  // + SL[w][t], t < 4: ints per K table
+constexpr int kSegSteps = 16;         // steps per tier-2 bound-test segment
+constexpr int kSegs = (1 << kSuperLog) / kSegSteps;
+static_assert(kSegs == 4 && kSegSteps == kPatterns / 2,
+              "the walk flips level 4 after segments 0 and 2 and level 5 after segment 1");
+constexpr int kKC2Min = 6 * kPatterns;   // min of C2 per (table, 16-step segment)
+constexpr int kKBound = kKC2Min + 8;     // bound constants at the head of a K table
+constexpr int kKTable = kKBound + kLowLevels * kWave;  // + SL[w][t], t < kLowLevels
 constexpr int kMaxVgprLevels = 12;    // at most Gray levels 0..11 keep their M_int row in VGPRs
 constexpr int32_t kNoEnergy = 1 << 30;  // above every energy the walk can meet
 constexpr int kMaxVars = 60;          // largest n the planner accepts

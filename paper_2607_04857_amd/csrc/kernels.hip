@@ -16,14 +16,16 @@
 //    chip: by default levels 0-2 and 5 in VGPRs and 3-4 in LDS (8 KB per
 //    wave), which fits 128 VGPRs and so four waves per SIMD; other variants
 //    keep 5, 6, 8 or 12 levels in VGPRs; higher levels are read from L2 when
-//    they flip (level 6 once per 128 steps);
+//    they flip (level 6 once per 128 steps; level 5, in the 5-level variants,
+//    once per 64);
 //  * wavefronts take work items (2^L consecutive Gray steps of the prefix,
 //    the "straightforward" split of Sec. III-C.1 along the Gray index) from an
-//    atomic counter; the grid is persistent;
+//    atomic counter, one at a time; the grid is persistent;
 //  * the scalar unit keeps the prefix self-energy E_p: the walk is unrolled
-//    over 32-step super-blocks in which the four lowest Gray levels follow a
-//    static pattern, so E_p of each of the 16 low patterns is tabulated in
-//    SGPRs and refreshed only when a higher prefix bit flips;
+//    over 64-step super-blocks in which the five lowest Gray levels follow a
+//    static pattern and level 5 flips once, in the middle, so the flip
+//    sequence is known at compile time and E_p of each low pattern follows
+//    from SGPR fields refreshed only when a higher prefix bit flips;
 //  * the candidate test "min over the chunk + E_p <= best" is, by default
 //    (tier 2), a lower bound from one DPP wave minimum per super-block and a
 //    per-offset table, tested against a cheap upper bound of the thresholds
@@ -271,40 +273,40 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
     // not start from an energy found outside it)
     if (I.gbest && I.item_local0 == 0 && I.n_items == (uint64_t(1) << (A - I.L)))
         seed_best(I, int(threadIdx.x) / kWave);
-    for (uint32_t e = threadIdx.x; e < uint32_t(A) * 4u; e += blockDim.x) {
-        const int w = int(e / 4), t = int(e % 4), l = A - 1 - t;
+    for (uint32_t e = threadIdx.x; e < uint32_t(A) * kLowLevels; e += blockDim.x) {
+        const int w = int(e / kLowLevels), t = int(e % kLowLevels), l = A - 1 - t;
         int32_t v = 0;
         if (l != w) v = (l < w) ? T[l * n + w] : T[w * n + l];
         I.K[kKBound + e] = v;
     }
-    // Tier-2 bound constants.  Inside a 32-step super-block the four lowest
-    // Gray levels follow the static pattern p(o) = g(o) & 15 from 0, and the
-    // level-4 bit moves once (by +-1) at o = 16, so
-    //   E_sd(o) - E_sd(0) = sum_{t<4} p_t(o) M[A-1-t] + [o >= 16] c4 M[A-5].
+    // Tier-2 bound constants.  Inside a 64-step super-block the five lowest
+    // Gray levels follow the static pattern p(o) = g(o) & 31 from 0, and the
+    // level-5 bit moves once (by cm = +-1) at o = 32, so
+    //   E_sd(o) - E_sd(0) = sum_{t<5} p_t(o) M[A-1-t] + [o >= 32] cm M[A-6].
     // D = its minimum over all 2^B columns, a lower bound of how far the
     // chunk minimum can fall from its value at the super-block start.
-    // All 48 (table, offset) minima at once: per-thread minima over the
+    // All 96 (table, offset) minima at once: per-thread minima over the
     // thread's columns, wave minima by shuffles, one exchange through LDS.
     constexpr int NQ = 3 * kPatterns;
     __shared__ int32_t red[256 / kWave][NQ];
     __shared__ int32_t c2s[NQ];
-    int32_t mcol[4][5];   // M rows of levels 0..4 at this thread's columns
+    int32_t mcol[4][kLowLevels + 1];   // M rows of levels 0..kLowLevels at this thread's columns
     for (int k = 0; k < 4; k++) {
         const uint32_t col = threadIdx.x + 256u * uint32_t(k);
-        for (int t = 0; t < 5; t++)   // from this block's partial-sum tables
+        for (int t = 0; t <= kLowLevels; t++)
             mcol[k][t] = col < NS ? part[A - 1 - t][col & 31u] + part[A - 1 - t][32u + (col >> 5)] : 0;
     }
     const int wl = int(threadIdx.x) % kWave, wv = int(threadIdx.x) / kWave;
     for (int q = 0; q < NQ; q++) {
-        const int tab = q / kPatterns, o16 = q % kPatterns;
-        const int c4 = tab == 0 ? 0 : (tab == 1 ? 1 : -1);
-        const int o = tab == 0 ? o16 : kPatterns + o16;
+        const int tab = q / kPatterns, oo = q % kPatterns;
+        const int cm = tab == 0 ? 0 : (tab == 1 ? 1 : -1);
+        const int o = tab == 0 ? oo : kPatterns + oo;
         const int pat = (o ^ (o >> 1)) & (kPatterns - 1);
         int32_t mn = INT32_MAX;
         for (int k = 0; k < 4; k++) {
             if (threadIdx.x + 256u * uint32_t(k) >= NS) continue;
-            int32_t v = c4 * mcol[k][4];
-            for (int t = 0; t < 4; t++)
+            int32_t v = cm * mcol[k][kLowLevels];
+            for (int t = 0; t < kLowLevels; t++)
                 if ((pat >> t) & 1) v += mcol[k][t];
             mn = min(mn, v);
         }
@@ -313,26 +315,27 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
     }
     __syncthreads();
     if (int(threadIdx.x) < NQ) {
-        const int q = int(threadIdx.x), tab = q / kPatterns, o16 = q % kPatterns;
-        const int o = tab == 0 ? o16 : kPatterns + o16;
+        const int q = int(threadIdx.x), tab = q / kPatterns, oo = q % kPatterns;
+        const int o = tab == 0 ? oo : kPatterns + oo;
         const int pat = (o ^ (o >> 1)) & (kPatterns - 1);
         int32_t d = red[0][q];
         for (int w = 1; w < 256 / kWave; w++) d = min(d, red[w][q]);
         int32_t elow = 0;   // couplings among the set low variables
-        for (int t = 0; t < 4; t++)
-            for (int u = t + 1; u < 4; u++)
+        for (int t = 0; t < kLowLevels; t++)
+            for (int u = t + 1; u < kLowLevels; u++)
                 if (((pat >> t) & 1) && ((pat >> u) & 1)) elow += T[(A - 1 - u) * n + (A - 1 - t)];
-        I.K[(3 + tab) * kPatterns + o16] = d;
-        I.K[tab * kPatterns + o16] = elow + d;
+        I.K[(3 + tab) * kPatterns + oo] = d;
+        I.K[tab * kPatterns + oo] = elow + d;
         c2s[q] = elow + d;
     }
     __syncthreads();
-    if (threadIdx.x < 3) {
+    if (threadIdx.x < 6) {   // min of C2 over each 16-step segment of each table
+        const int tab = int(threadIdx.x) / 2, sg = int(threadIdx.x) % 2;
         int32_t m = INT32_MAX;
-        for (int o16 = 0; o16 < kPatterns; o16++) m = min(m, c2s[threadIdx.x * kPatterns + o16]);
+        for (int oo = sg * kSegSteps; oo < (sg + 1) * kSegSteps; oo++) m = min(m, c2s[tab * kPatterns + oo]);
         I.K[kKC2Min + threadIdx.x] = m;
     }
-    if (threadIdx.x == 3) I.K[kKC2Min + 3] = 0;
+    if (threadIdx.x == 6 || threadIdx.x == 7) I.K[kKC2Min + threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------- walk
@@ -354,10 +357,10 @@ __device__ __forceinline__ int32_t wave_min_bcast(int32_t v)
 
 // TIER 1: the chunk minimum (v_min3 tree) is compared with the threshold at
 //         every Gray step.
-// TIER 2: each lane takes its chunk minimum lm0 once per 32-step
+// TIER 2: each lane takes its chunk minimum lm0 once per 64-step
 //         super-block; at offset o the chunk minimum is at least
 //         W0 + D(o) (table K), W0 the wave minimum of lm0, so step o needs
-//         only the scalar test W0 <= THR - D(o).  Each 16-step half first
+//         only the scalar test W0 <= THR - D(o).  Each 16-step segment first
 //         tests lm0 against an upper bound of its 16 thresholds (one vector
 //         compare); only when a lane passes are W0 and the exact thresholds
 //         formed and tested.
@@ -613,8 +616,8 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
     unsigned long long *__restrict__ counter, const int32_t *__restrict__ kall, TopkWalk tk)
 {
     static_assert(TIER >= 1 && TIER <= 3, "tier");
-    static_assert(G >= kSuperLog && G <= kMaxVgprLevels, "VGPR-resident levels");
-    constexpr int H16 = kPatterns;   // steps per half super-block
+    static_assert(G >= kLowLevels && G <= kMaxVgprLevels, "VGPR-resident levels");
+    constexpr int SEG = kSegSteps;   // steps per segment
     const int lane = int(threadIdx.x);
     const uint32_t ulane = threadIdx.x;
     // row v of a lane-major [rows][MC*64] table: uniform base pointer
@@ -631,8 +634,8 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
     int A = 0, L = 0;
     uint64_t item_begin = 0, item_local0 = 0;
     int32_t R[G][MC];        // M_int rows of Gray levels 0..G-1 (variable A-1-t)
-    int32_t S4 = 0;          // couplings of the level-4 variable, one lane each
-    int32_t S4L[kLowLevels];  // couplings of the level-4 variable with the low ones
+    int32_t Smid = 0;          // couplings of the middle-level variable, one lane each
+    int32_t SmidL[kLowLevels];  // couplings of the middle-level variable with the low ones
     const int32_t *Tm = nullptr;  // the instance's folded T (the diagonal is
     int nT = 0;                   // re-read per item rather than held in a VGPR)
     int32_t CR[kPatterns];   // low-low coupling increments per pattern
@@ -681,10 +684,10 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                     for (int j = 0; j < MC; j++) R[t][j] = have ? trow(M, v)[j * kWave + ulane] : 0;
                 }
             });
-            S4 = S[size_t(A - 5) * kWave + ulane];
+            Smid = S[size_t(A - 1 - kLowLevels) * kWave + ulane];
             static_for<0, kLowLevels>([&](auto tc) {
                 constexpr int t = decltype(tc)::value;
-                S4L[t] = kall[kbase + kKBound + (A - 5) * 4 + t];
+                SmidL[t] = kall[kbase + kKBound + (A - 1 - kLowLevels) * kLowLevels + t];
             });
             Tm = I.T;
             nT = I.n;
@@ -750,10 +753,10 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
         // variables 0..A-5), plus its diagonal; one lane per variable.
         const int32_t diagl = lane < A ? Tm[lane * nT + lane] : 0;   // T[l][l], lane l < A
         int32_t F = diagl;
-        for (int w = 0; w <= A - 5; w++)
+        for (int w = 0; w <= A - 1 - kLowLevels; w++)
             if ((row0 >> (A - 1 - w)) & 1) F += S[size_t(w) * kWave + ulane];
         // E_nl = energy of the non-low prefix bits = (sum_set F_w + T_ww) / 2
-        const bool lbit = lane <= A - 5 && ((row0 >> (A - 1 - lane)) & 1);
+        const bool lbit = lane <= A - 1 - kLowLevels && ((row0 >> (A - 1 - lane)) & 1);
         int32_t Enl = int32_t(wave_sum64(lbit ? int64_t(F) + diagl : 0) / 2);
         Enl = sread(Enl);
         int32_t H[kLowLevels];
@@ -775,33 +778,38 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                 THR[p] = THR[pp] - H[t] - CR[p];
             });
         };
-        // TIER 2: for the 16 offsets o of half super-block `half`,
-        //   tp(o) = best - E_p(low pattern at o) - D(o)   (K table tab),
-        // computed by walking the Gray sequence of patterns; hs = the sum of
-        // H[t] over the set low bits.  The first half walks the patterns
-        // g(o2), the second half g(o2) ^ 8 (the same bit sequence with bit 3
-        // inverted).  f(o2, tp) is called for every offset.  Step o can hold a
-        // candidate only if W0 <= tp(o).
-        auto for_each_tp = [&](int half, int tab, auto &&f) {
-            int32_t hs = half ? H[kLowLevels - 1] : 0;   // pattern 8 opens the second half
-            static_for<0, H16>([&](auto oc) {
+        // TIER 2: for the 16 offsets o of segment `seg` (o = 16 seg + o2),
+        //   tp(o) = best - E_p(low pattern at o) - C2(o)   (K table tab),
+        // computed by walking the Gray sequence of patterns g(o) & 31 from
+        // the segment's first one; hs = the sum of H[t] over the set low
+        // bits.  f(o2, tp) is called for every offset.  Step o can hold a
+        // candidate only if W0 <= tp(o) + D(o) - ELOW(o).
+        auto for_each_tp = [&](auto segc, int tab, auto &&f) {
+            constexpr int seg = decltype(segc)::value;
+            constexpr int o0 = seg * SEG;
+            constexpr int p0 = (o0 ^ (o0 >> 1)) & (kPatterns - 1);
+            int32_t hs = 0;
+            static_for<0, kLowLevels>([&](auto tc) {
+                constexpr int t = decltype(tc)::value;
+                if constexpr ((p0 >> t) & 1) hs += H[t];
+            });
+            static_for<0, SEG>([&](auto oc) {
                 constexpr int o2 = decltype(oc)::value;
+                constexpr int o = o0 + o2;
                 if constexpr (o2 > 0) {
-                    constexpr int pa0 = (o2 - 1) ^ ((o2 - 1) >> 1), pa1 = o2 ^ (o2 >> 1);
+                    constexpr int pa0 = ((o - 1) ^ ((o - 1) >> 1)) & (kPatterns - 1);
+                    constexpr int pa1 = (o ^ (o >> 1)) & (kPatterns - 1);
                     constexpr int t = cx_ctz(pa0 ^ pa1);
-                    constexpr bool rise0 = ((pa1 >> t) & 1) != 0;
-                    const bool rise = (half && t == kLowLevels - 1) ? !rise0 : rise0;
-                    hs = rise ? hs + H[t] : hs - H[t];
+                    if constexpr (((pa1 >> t) & 1) != 0) hs += H[t];
+                    else hs -= H[t];
                 }
-                // best is read afresh: a candidate found at an earlier offset
-                // of the same half has already lowered it
-                f(oc, (best - Enl) - hs - kall[kbase + tab * kPatterns + o2]);
+                f(oc, (best - Enl) - hs - kall[kbase + tab * kPatterns + (o & (kPatterns - 1))]);
             });
         };
-        // Thresholds of the current half, kept in SGPRs.
-        int32_t TP[H16];
-        auto build_tp = [&](int half, int tab) {
-            for_each_tp(half, tab, [&](auto oc, int32_t tp) { TP[decltype(oc)::value] = tp; });
+        // Thresholds of the current segment, kept in SGPRs.
+        int32_t TP[SEG];
+        auto build_tp = [&](auto segc, int tab) {
+            for_each_tp(segc, tab, [&](auto oc, int32_t tp) { TP[decltype(oc)::value] = tp; });
         };
         if constexpr (TIER == 1) build_thr();
 
@@ -824,7 +832,8 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
         int32_t W0 = 0;    // TIER 2: exact wave minimum at the super-block start
                            // (taken on the cold path only)
         int32_t lm0 = 0;   // TIER 2: this lane's chunk minimum at the super-block start
-        int tab2 = 0;      // TIER 2: K table of the current half
+        int tab2 = 0;      // TIER 2: K table of the current segment (0 before the middle
+                           // flip, 1 / 2 after it with level 5 rising / falling)
 
         // Candidate test at Gray step i with chunk minimum lm and threshold thr.
         auto candidate = [&](int32_t lm, int32_t thr, uint64_t i) {
@@ -839,11 +848,11 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                     itemE = Ec;
                     itemRow = rc;
                     found = 1;
-                    static_for<0, kPatterns>([&](auto pc) {
-                        constexpr int p = decltype(pc)::value;
-                        if constexpr (TIER == 1) THR[p] += d;
-                        else TP[p] += d;
-                    });
+                    if constexpr (TIER == 1) {
+                        static_for<0, kPatterns>([&](auto pc) { THR[decltype(pc)::value] += d; });
+                    } else {
+                        static_for<0, SEG>([&](auto pc) { TP[decltype(pc)::value] += d; });
+                    }
                 }
             }
         };
@@ -858,20 +867,20 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                     const int32_t nb = sread(tk_insert(Ec, i ^ (i >> 1)));
                     const int32_t d = nb - best;
                     best = nb;
-                    static_for<0, kPatterns>([&](auto pc) { TP[decltype(pc)::value] += d; });
+                    static_for<0, SEG>([&](auto pc) { TP[decltype(pc)::value] += d; });
                 }
             }
         };
 
-        // Low flip of static level t (< 4) with static direction (Alg. 2:
+        // Low flip of static level t (< kLowLevels) with static direction (Alg. 2:
         // E_sd += delta M_int[k]).
         auto low_flip = [&](auto tc, auto upc) {
             constexpr int t = decltype(tc)::value;
             constexpr bool up = decltype(upc)::value;
-            if constexpr (LR && t == 3) {
+            if constexpr (LR && (t == 3 || t == 4)) {
 #pragma unroll
                 for (int j = 0; j < MC; j++) {
-                    const int32_t r = ldsR[j * kWave + lane];
+                    const int32_t r = ldsR[(t - 3) * (MC * kWave) + j * kWave + lane];
                     E[j] = up ? E[j] + r : E[j] - r;
                 }
             } else {
@@ -880,24 +889,29 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
             }
             pin_vec<MC>(E);
         };
-        // Level-4 flip in the middle of super-block sb.
+        // Flip of level kLowLevels in the middle of super-block sb (its
+        // direction alternates between super-blocks).
         auto middle_flip = [&](uint64_t sb) {
             const bool up = (sb & 1) == 0;
-            int32_t R4[MC];
+            constexpr int tm = kLowLevels;
+            if constexpr (G > tm) {
+                if (up) {
 #pragma unroll
-            for (int j = 0; j < MC; j++) R4[j] = LR ? ldsR[(MC * kWave) + j * kWave + lane] : R[4][j];
-            if (up) {
+                    for (int j = 0; j < MC; j++) E[j] += R[tm][j];
+                } else {
 #pragma unroll
-                for (int j = 0; j < MC; j++) E[j] += R4[j];
+                    for (int j = 0; j < MC; j++) E[j] -= R[tm][j];
+                }
             } else {
+                const int ws = up ? A - 1 - tm : 2 * A - 1 - tm;
 #pragma unroll
-                for (int j = 0; j < MC; j++) E[j] -= R4[j];
+                for (int j = 0; j < MC; j++) E[j] += trow(M, ws)[j * kWave + ulane];
             }
             pin_vec<MC>(E);
-            nonlow_flip(A - 5, up, up ? S4 : -S4, S4L);
+            nonlow_flip(A - 1 - tm, up, up ? Smid : -Smid, SmidL);
             return up;
         };
-        // Flip entering super-block sb + 1 (Gray level >= 5).
+        // Flip entering super-block sb + 1 (Gray level >= kSuperLog).
         auto boundary_flip = [&](uint64_t sb) {
             const uint64_t ip1 = (sb + 1) << kSuperLog;
             const int t = __builtin_ctzll(ip1);
@@ -928,18 +942,18 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
             int32_t SLw[kLowLevels];
             static_for<0, kLowLevels>([&](auto tc) {
                 constexpr int tt = decltype(tc)::value;
-                SLw[tt] = kall[kbase + kKBound + w * 4 + tt];
+                SLw[tt] = kall[kbase + kKBound + w * kLowLevels + tt];
             });
             nonlow_flip(w, up, S[size_t(ws) * kWave + ulane], SLw);
         };
 
         if constexpr (TIER == 1) {
             for (uint64_t sb = sb0; sb < sbEnd; sb++) {
-                static_for<0, 32>([&](auto oc) {
+                static_for<0, (1 << kSuperLog)>([&](auto oc) {
                     constexpr int o = decltype(oc)::value;
                     constexpr int pat = (o ^ (o >> 1)) & (kPatterns - 1);
                     candidate(tree_min<MC>(E), THR[pat], (sb << kSuperLog) | uint64_t(o));
-                    if constexpr (o < 31) {
+                    if constexpr (o < (1 << kSuperLog) - 1) {
                         constexpr int t = cx_ctz(o + 1);
                         if constexpr (t < kLowLevels) {
                             constexpr bool up = ((((o + 1) ^ ((o + 1) >> 1)) >> t) & 1) != 0;
@@ -960,59 +974,67 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
             for (uint32_t ks = 0; ks < nsb; ks++) {
                 const uint64_t sb = sb0 + ks;
                 lm0 = tree_min<MC>(E);
-                static_for<0, 2>([&](auto hc) {
-                    constexpr int h = decltype(hc)::value;
-                    // the 16 steps of half h, with (CHECK) or without the
-                    // per-step bound test, and the 15 low flips between them
-                    // Every step's chunk energies stay observable through the
-                    // (rarely taken) test, so each state gets its add.
-                    // exact test of step o2 (cold path)
+                tab2 = 0;
+                // four 16-step segments, each with (cold) or without the
+                // per-step bound tests; every step's chunk energies stay
+                // observable through the (rarely taken) test, so each state
+                // gets its add
+                static_for<0, kSegs>([&](auto sc) {
+                    constexpr int h = decltype(sc)::value;
+                    // exact test of step o (cold path)
                     auto step_check = [&](auto oc) {
                         constexpr int o2 = decltype(oc)::value;
-                        constexpr int o = h * H16 + o2;
+                        constexpr int o = h * SEG + o2;
                         if (W0 <= TP[o2]) {
-                            const int32_t thr = TP[o2] + kall[kbase + (3 + tab2) * kPatterns + o2];
+                            const int32_t thr =
+                                TP[o2] + kall[kbase + (3 + tab2) * kPatterns + (o & (kPatterns - 1))];
                             if constexpr (TIER == 3)
                                 candidate3(tree_min<MC>(E), thr, (sb << kSuperLog) | uint64_t(o));
                             else
                                 candidate(tree_min<MC>(E), thr, (sb << kSuperLog) | uint64_t(o));
                         }
                     };
-                    // the low flip after step o2 (none after the last step)
+                    // the low flip after step o (none after the segment's last)
                     auto step_flip = [&](auto oc) {
                         constexpr int o2 = decltype(oc)::value;
-                        constexpr int o = h * H16 + o2;
-                        if constexpr (o2 < H16 - 1) {
+                        constexpr int o = h * SEG + o2;
+                        if constexpr (o2 < SEG - 1) {
                             constexpr int t = cx_ctz(o + 1);
                             constexpr bool up = ((((o + 1) ^ ((o + 1) >> 1)) >> t) & 1) != 0;
                             low_flip(std::integral_constant<int, t>{},
                                      std::integral_constant<bool, up>{});
                         }
                     };
-                    // One scalar test for the half: an upper bound of its 16
+                    // One scalar test for the segment: an upper bound of its 16
                     // thresholds tp(o) = best - Enl - hs(o) - C2(o), since
-                    // hs(o) >= sum_t min(0, H[t]) and C2(o) >= min_o C2.
-                    int32_t tb = best - Enl - kall[kbase + kKC2Min + tab2];
+                    // hs(o) >= sum_t min(0, H[t]) and C2(o) >= the segment's
+                    // minimum of C2; any lane at or below it takes the cold
+                    // path (the wave minimum W0 is formed only then)
+                    int32_t tb = best - Enl - kall[kbase + kKC2Min + tab2 * 2 + (h & 1)];
                     static_for<0, kLowLevels>([&](auto tc) { tb -= min(0, H[decltype(tc)::value]); });
-                    // any lane at or below the bound (the wave minimum W0 is
-                    // formed only then)
                     const bool cold = __builtin_amdgcn_ballot_w64(lm0 <= tb) != 0;
                     if (__builtin_expect(cold, 0)) {
                         W0 = wave_min_bcast(lm0);
-                        // exact per-step thresholds and tests
-                        build_tp(h, tab2);
-                        static_for<0, H16>([&](auto oc) {
+                        build_tp(sc, tab2);
+                        static_for<0, SEG>([&](auto oc) {
                             step_check(oc);
                             step_flip(oc);
                         });
                     } else {
-                        static_for<0, H16>([&](auto oc) { step_flip(oc); });
+                        static_for<0, SEG>([&](auto oc) { step_flip(oc); });
                     }
-                    if constexpr (h == 0) {
+                    // the flip after the segment's last step: level 5 in the
+                    // middle, level 4 (static direction) after segments 0 and
+                    // 2, the boundary flip after the last
+                    if constexpr (h == kSegs / 2 - 1) {
                         tab2 = middle_flip(sb) ? 1 : 2;
+                    } else if constexpr (h < kSegs - 1) {
+                        constexpr int o = (h + 1) * SEG;
+                        constexpr int t = cx_ctz(o);
+                        constexpr bool up = (((o ^ (o >> 1)) >> t) & 1) != 0;
+                        low_flip(std::integral_constant<int, t>{}, std::integral_constant<bool, up>{});
                     } else if (ks + 1 < nsb) {
                         boundary_flip(sb);
-                        tab2 = 0;
                     }
                 });
             }

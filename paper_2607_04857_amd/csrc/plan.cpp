@@ -94,7 +94,7 @@ bool tune_valid(const TuneEntry &e, std::string *msg)
     }
     const int A = e.n - e.B;
     if (e.L != 0 && (e.L < kSuper || e.L > A || A - e.L > 20)) {
-        *msg = "tuning entry L must be 0 or in [max(5, A - 20), A]";
+        *msg = "tuning entry L must be 0 or in [max(6, A - 20), A]";
         return false;
     }
     return true;
@@ -247,7 +247,7 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
     if (opt && opt->L) {
         L = opt->L;
         if (L < kSuper || L > P.A) {
-            *msg = "option L must be in [5, A]";
+            *msg = "option L must be in [6, A]";
             return QUBO_EINVAL;
         }
     } else if (use_tune && tuned.L && !many && tuned.B == P.B) {

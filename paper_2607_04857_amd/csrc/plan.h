@@ -16,7 +16,7 @@ namespace qplan {
 
 // Kernel geometry shared by planner and kernels.
 constexpr int kWave = 64;          // lanes per wavefront
-constexpr int kSuper = 5;          // log2 of the unrolled Gray super-block (32 steps)
+constexpr int kSuper = 6;          // log2 of the unrolled Gray super-block (64 steps)
 constexpr int kMaxN = 60;
 constexpr int kDirectMaxN = 14;    // n at or below this: direct evaluation, no walk
 constexpr int64_t kIntSumLimit = (int64_t(1) << 30) - 1;   // sum |T| bound, int32 input

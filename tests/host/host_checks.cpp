@@ -139,7 +139,7 @@ static std::string mutate(const std::string &s, std::mt19937_64 &rng)
 static int run_json()
 {
     std::vector<qplan::TuneEntry> in;
-    for (int n = 15; n <= 44; n++) {
+    for (int n = 16; n <= 44; n++) {   // n - B must hold one 64-step super-block
         qplan::TuneEntry e;
         e.n = n;
         e.dtype = n % 3 ? QUBO_INT32 : QUBO_FP32;

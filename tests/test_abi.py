@@ -131,7 +131,7 @@ def test_split_options_and_validation():
         info = q.plan_info(Q, B=B, L=7)
         assert (info["B"], info["A"], info["L"]) == (B, 24 - B, 7)
         assert info["items"] == 2 ** (24 - B - 7)
-    for bad in (dict(B=5), dict(B=11), dict(L=4), dict(L=30), dict(tier=3)):
+    for bad in (dict(B=5), dict(B=11), dict(L=5), dict(L=30), dict(tier=3)):
         with pytest.raises(q.QuboError) as e:
             q.plan_info(Q, **bad)
         assert e.value.status == -1

@@ -49,7 +49,7 @@ def test_walk_small(q, orc, n, tier):
 
 @pytest.mark.parametrize("tier", TIERS)
 @pytest.mark.parametrize("B", [6, 7, 8, 9, 10])
-@pytest.mark.parametrize("L", [5, 7, 0])
+@pytest.mark.parametrize("L", [6, 7, 0])
 def test_split_invariance(q, orc, B, L, tier):
     Q = inputs.uniform_int(21, -500, 500, 77)
     _check(q, orc, Q, B=B, L=L, tier=tier)
@@ -57,7 +57,7 @@ def test_split_invariance(q, orc, B, L, tier):
 
 @pytest.mark.parametrize("tier", TIERS)
 @pytest.mark.parametrize("B,G", [(9, 8), (10, 8), (10, 6), (10, 5), (10, 4), (10, 3)])
-@pytest.mark.parametrize("L", [5, 9])
+@pytest.mark.parametrize("L", [6, 9])
 def test_vgpr_levels(q, orc, B, G, L, tier):
     Q = inputs.uniform_int(23, -500, 500, 78)
     got = _check(q, orc, Q, B=B, L=L, tier=tier, vgpr_levels=G)

@@ -61,8 +61,8 @@ def test_ties(orc):
 def test_small_item_sizes_many_lists(orc):
     import paper_2607_04857_amd as q
     Q = inputs.uniform_int(24, -100, 100, 1300)
-    _exact(orc, q, Q, 1024, L=5)          # 2^9 items of 32 steps
-    _exact(orc, q, Q, 50, L=5, waves_per_cu=1)
+    _exact(orc, q, Q, 1024, L=6)          # 2^8 items of 64 steps
+    _exact(orc, q, Q, 50, L=6, waves_per_cu=1)
 
 
 def test_fp32(orc):

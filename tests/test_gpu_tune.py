@@ -65,10 +65,10 @@ def test_autotune_writes_cache_and_drives_solves(q, orc, tmp_path):
 
 
 def test_batch_with_mixed_variants(q, orc):
-    ns = list(range(15, 27))
+    ns = list(range(16, 28))
     q.tune_set(_table(ns) + _table(ns, "fp32"))
     Qs = [inputs.uniform_int(n, -100, 100, 700 + n) for n in ns]
-    Qs += [inputs.normal_fp32(n, 800 + n) for n in (15, 18, 22)]
+    Qs += [inputs.normal_fp32(n, 800 + n) for n in (16, 18, 22)]
     Qs += [inputs.uniform_int(n, -100, 100, 720 + n) for n in (3, 26, 20, 21)]
     b = q.Batch(Qs)
     for rep in range(2):
@@ -85,7 +85,7 @@ def test_batch_with_mixed_variants(q, orc):
 
 
 def test_server_with_mixed_variants(q, orc):
-    ns = list(range(15, 27))
+    ns = list(range(16, 28))
     q.tune_set(_table(ns) + _table(ns, "fp32"))
     Qs = [inputs.uniform_int(n, -100, 100, 760 + n) for n in ns for _ in range(2)]
     Qs += [inputs.normal_fp32(n, 860 + n) for n in (16, 24)]

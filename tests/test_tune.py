@@ -62,7 +62,7 @@ def test_direct_sizes_ignore_the_table(q):
     {"n": 30, "B": 8, "L": 0, "tier": 2, "vgpr_levels": 6},      # G=6 needs B=10
     {"n": 30, "B": 7, "L": 0, "tier": 2, "vgpr_levels": 8},      # G=8 needs B>=9
     {"n": 30, "B": 10, "L": 21, "tier": 2, "vgpr_levels": 6},    # L > A
-    {"n": 30, "B": 10, "L": 4, "tier": 2, "vgpr_levels": 6},     # L < 5
+    {"n": 30, "B": 10, "L": 5, "tier": 2, "vgpr_levels": 6},     # L < 6
     {"n": 61, "B": 10, "L": 0, "tier": 2, "vgpr_levels": 6},     # n too large
     {"n": 16, "B": 12, "L": 0, "tier": 2, "vgpr_levels": 6},     # prefix too short
 ])
