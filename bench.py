@@ -47,12 +47,18 @@ METRIC = ("states/sec on 1 MI355X (single n=44; batched mixed-n) vs VALU peak; "
           "p50/p99 solve latency")
 HEADLINE = dict(n=44, lo=-10000, hi=10000, seed=4)
 PMC_FILE = os.path.join(ROOT, "profiles", "walk_n44_pmc.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_2607_04857_amd", "csrc", "kernels.hip")
+# sources of the walk kernel (its template, helpers, layout and the unit of
+# the headline variant); a PMC summary taken with other sources is stale
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2607_04857_amd", "csrc", f)
+               for f in ("kernels.h", "kcommon.h", "walk.h", "walk_g6.hip")]
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def kernel_name(r):
@@ -69,7 +75,7 @@ def traffic_from_profile():
     if not os.path.exists(PMC_FILE):
         return None
     txt = open(PMC_FILE).read()
-    m_h = re.search(r"kernels\.hip sha256\[:16\]:\s*`?([0-9a-f]{16})", txt)
+    m_h = re.search(r"walk sources sha256\[:16\]:\s*`?([0-9a-f]{16})", txt)
     m_b = re.search(r"HBM bytes per walk launch:\s*([0-9.eE+]+)", txt)
     if not m_h or not m_b or m_h.group(1) != kernel_hash():
         return None
