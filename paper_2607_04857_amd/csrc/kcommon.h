@@ -115,4 +115,48 @@ __device__ __forceinline__ void lexmin(int64_t &bE, uint64_t &bI, int64_t e, uin
     }
 }
 
+// Greedy single-flip descent of the calling wave from start state `start`
+// (all-zero for start 0, a hashed state otherwise).  Lane l holds variable l
+// (n <= 60 < 64) and its field f_l = T_ll + the couplings with the set
+// variables, so flipping l changes E by +-f_l; the largest decrease is taken
+// (lowest lane on ties) until no flip lowers E.  Returns the local minimum's
+// energy in E_out and its variables (bit l = variable l) in xm_out, the same
+// in every lane.
+__device__ inline void greedy_descent(const int32_t *T, int n, uint32_t start, int32_t &E_out,
+                                      uint64_t &xm_out)
+{
+    const int lane = int(threadIdx.x) % kWave;
+    uint32_t h = start * 0x9E3779B9u + uint32_t(lane) * 0x85EBCA6Bu;
+    h ^= h >> 15;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 13;
+    int x = (start != 0 && lane < n) ? int(h & 1u) : 0;
+    const uint64_t xm = __builtin_amdgcn_ballot_w64(x != 0);
+    int32_t f = 0, own = 0;   // field; sum of row l over the set j >= l
+    if (lane < n) {
+        f = T[lane * n + lane];
+        own = x ? T[lane * n + lane] : 0;
+        for (int j = 0; j < n; j++) {
+            if (j == lane || !((xm >> j) & 1)) continue;
+            const int32_t c = j < lane ? T[j * n + lane] : T[lane * n + j];
+            f += c;
+            if (x && j > lane) own += c;
+        }
+    }
+    int32_t E = int32_t(wave_sum64(own));
+    for (int it = 0; it < 4 * n; it++) {
+        const int32_t gain = lane < n ? (x ? -f : f) : INT32_MAX;
+        // smallest gain (DPP minimum), lowest lane on ties
+        const int32_t g = wave_min(gain);
+        if (g >= 0) break;
+        const int k = int(__builtin_ctzll(__builtin_amdgcn_ballot_w64(gain == g)));
+        const int32_t sgn = __shfl(x, k, kWave) ? -1 : 1;   // 1 -> 0 subtracts couplings
+        E += g;
+        if (lane == k) x ^= 1;
+        else if (lane < n) f += sgn * (k < lane ? T[k * n + lane] : T[lane * n + k]);
+    }
+    E_out = E;
+    xm_out = __builtin_amdgcn_ballot_w64(x != 0);
+}
+
 }  // namespace qk

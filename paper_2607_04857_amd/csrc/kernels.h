@@ -162,6 +162,13 @@ __host__ __device__ inline size_t topk_lds_bytes()
     return size_t(kTopkMetaWords) * 8;
 }
 
+// Seeds the shared top-k bound *d_gthr of one walked instance before its
+// walk: the k-th smallest energy of up to 4096 states with distinct prefix
+// rows near a local minimum (every walked chunk must be in the walk: full
+// item range only).  Leaves *d_gthr unchanged when the instance has fewer
+// such states than k.
+hipError_t launch_topk_seed(const Inst *d_inst, int32_t *d_gthr, int k, hipStream_t stream);
+
 // Top-k finish of one instance (descriptor d_inst, host copy hI): select the
 // k smallest chunks of the walk lists, rescan them (or, direct, evaluate all
 // 2^n states), select and sort the k smallest states, verify their energies

@@ -43,53 +43,22 @@ namespace qk {
 
 // ---------------------------------------------------------------- tables
 
-// Greedy single-flip descent from two starts per wave (the all-zero state
+// Greedy single-flip descents from two starts per wave (the all-zero state
 // for wave 0's first start, hashed states otherwise), lowering the
 // instance's shared best to the energy of the local minima found.  Any
 // state's energy is a valid threshold for the walk (the state's own chunk
 // still passes it), and a local minimum of a dense QUBO is usually close to
-// the global one, so walk waves start with a near-final threshold.  Lane l
-// holds variable l (n <= 60 < 64) and its field f_l = T_ll + sum of the
-// couplings with the set variables: flipping l changes E by +-f_l.
+// the global one, so walk waves start with a near-final threshold.
 __device__ void seed_best(const Inst &I, int wave)
 {
-    const int n = I.n, lane = int(threadIdx.x) % kWave;
-    const int32_t *T = I.T;
     int32_t bestE = kNoEnergy;
     for (int rep = 0; rep < 2; rep++) {
-        const uint32_t start = uint32_t(wave) * 2u + uint32_t(rep);
-        uint32_t h = start * 0x9E3779B9u + uint32_t(lane) * 0x85EBCA6Bu;
-        h ^= h >> 15;
-        h *= 0xC2B2AE35u;
-        h ^= h >> 13;
-        int x = (start != 0 && lane < n) ? int(h & 1u) : 0;
-        uint64_t xm = __builtin_amdgcn_ballot_w64(x != 0);
-        int32_t f = 0, own = 0;   // field; sum of row l over the set j >= l
-        if (lane < n) {
-            f = T[lane * n + lane];
-            own = x ? T[lane * n + lane] : 0;
-            for (int j = 0; j < n; j++) {
-                if (j == lane || !((xm >> j) & 1)) continue;
-                const int32_t c = j < lane ? T[j * n + lane] : T[lane * n + j];
-                f += c;
-                if (x && j > lane) own += c;
-            }
-        }
-        int32_t E = int32_t(wave_sum64(own));
-        for (int it = 0; it < 4 * n; it++) {
-            const int32_t gain = lane < n ? (x ? -f : f) : INT32_MAX;
-            // smallest gain (DPP minimum), lowest lane on ties
-            const int32_t g = wave_min(gain);
-            if (g >= 0) break;
-            const int k = int(__builtin_ctzll(__builtin_amdgcn_ballot_w64(gain == g)));
-            const int32_t sgn = __shfl(x, k, kWave) ? -1 : 1;   // 1 -> 0 subtracts couplings
-            E += g;
-            if (lane == k) x ^= 1;
-            else if (lane < n) f += sgn * (k < lane ? T[k * n + lane] : T[lane * n + k]);
-        }
+        int32_t E;
+        uint64_t xm;
+        greedy_descent(I.T, I.n, uint32_t(wave) * 2u + uint32_t(rep), E, xm);
         bestE = min(bestE, E);
     }
-    if (lane == 0) atomicMin(I.gbest, bestE);
+    if (int(threadIdx.x) % kWave == 0) atomicMin(I.gbest, bestE);
 }
 
 __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ insts,

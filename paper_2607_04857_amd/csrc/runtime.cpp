@@ -301,6 +301,14 @@ qubo_status_t job_enqueue_kernels(const Job &job, hipStream_t stream, hipEvent_t
                               stream),
             "tables kernel");
     if (walk_begin) QRT_HIP(hipEventRecord(walk_begin, stream), "hipEventRecord");
+    if (job.topk > 1) {
+        // a bound of the k-th smallest chunk key from states near a local
+        // minimum, when the walk covers every chunk (timed with the walk)
+        const qk::Inst &I = job.h_inst0;
+        if (!I.direct && I.item_local0 == 0 && I.n_items == (uint64_t(1) << (I.A - I.L)))
+            QRT_HIP(qk::launch_topk_seed(job.d_insts, job.tkb.walk.gthr, job.topk, stream),
+                    "top-k seed kernel");
+    }
     for (size_t k = 0; k < job.groups.size(); k++) {
         const WalkGroup &g = job.groups[k];
         QRT_HIP(qk::launch_walk(g.mcols, g.vgpr_levels, g.tier, job.d_insts + g.first, g.count,

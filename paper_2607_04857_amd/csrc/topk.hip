@@ -24,6 +24,7 @@
 // the tied entries; keys are unique (a row is walked once, an index occurs
 // once), so exactly min(k, candidates) entries are kept.
 #include "device_energy.h"
+#include "kcommon.h"
 #include "kernels.h"
 
 namespace qk {
@@ -369,7 +370,146 @@ __global__ __launch_bounds__(kSelThreads) void topk_final_kernel(
     }
 }
 
+// ---------------------------------------------------------------- seed
+// Upper bound of the k-th smallest chunk key, set as the shared bound before
+// the walk (which then only lowers it).  Chunks of distinct prefix rows are
+// distinct, and a state's energy bounds its own chunk's key from above, so
+// the k-th smallest energy over states with k or more distinct prefix rows
+// bounds the k-th smallest chunk key.  The states: a local minimum x* of
+// eight greedy descents and the states that differ from it in one to four
+// prefix variables (the first kSeedStates in order of the number of flips,
+// each group in colex order).  Their energies follow from x*'s single-flip
+// changes d_i and the couplings: flipping the set F changes E by
+//   sum_{i in F} d_i + sum_{i<j in F} s_i s_j T_ij,   s_i = 1 - 2 x_i.
+constexpr int kSeedStates = 4096;
+constexpr int kSeedThreads = 256;
+
+__device__ __forceinline__ int64_t binom_small(int v, int r)   // C(v, r), r <= 4
+{
+    if (v < r) return 0;
+    int64_t c = 1;
+    for (int t = 0; t < r; t++) c = c * (v - t) / (t + 1);
+    return c;
+}
+
+__global__ __launch_bounds__(kSeedThreads) void topk_seed_kernel(const Inst *__restrict__ inst,
+                                                                 int32_t *gthr, int k)
+{
+    const Inst &I = *inst;
+    const int n = I.n, A = I.A;
+    const int32_t *T = I.T;
+    const int tid = int(threadIdx.x), lane = tid % kWave, wave = tid / kWave;
+    __shared__ int32_t wE[kSeedThreads / kWave];
+    __shared__ uint64_t wX[kSeedThreads / kWave];
+    __shared__ int32_t d[kWave];
+    __shared__ int32_t sg[kWave];
+    __shared__ int32_t Ec[kSeedStates];
+    __shared__ int64_t sBest;
+    __shared__ uint64_t sXm;
+    __shared__ uint32_t sCount;
+
+    // 1. the best local minimum of eight descents (two per wave)
+    int32_t bE = kNoEnergy;
+    uint64_t bX = 0;
+    for (int rep = 0; rep < 2; rep++) {
+        int32_t E;
+        uint64_t xm;
+        greedy_descent(T, n, uint32_t(wave) * 2u + uint32_t(rep), E, xm);
+        if (E < bE || (E == bE && xm < bX)) {
+            bE = E;
+            bX = xm;
+        }
+    }
+    if (lane == 0) {
+        wE[wave] = bE;
+        wX[wave] = bX;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int32_t e = wE[0];
+        uint64_t x = wX[0];
+        for (int w = 1; w < kSeedThreads / kWave; w++)
+            if (wE[w] < e || (wE[w] == e && wX[w] < x)) {
+                e = wE[w];
+                x = wX[w];
+            }
+        sBest = e;
+        sXm = x;
+    }
+    __syncthreads();
+    const uint64_t xm = sXm;
+    // 2. single-flip changes and signs at x*, one thread per variable
+    if (tid < n) {
+        const int xl = int((xm >> tid) & 1);
+        int32_t f = T[tid * n + tid];
+        for (int j = 0; j < n; j++)
+            if (j != tid && ((xm >> j) & 1)) f += j < tid ? T[j * n + tid] : T[tid * n + j];
+        d[tid] = xl ? -f : f;
+        sg[tid] = xl ? -1 : 1;
+    }
+    // 3. the states with 0..4 prefix variables flipped
+    int64_t groups[5];
+    int64_t total = 0;
+    for (int p = 0; p <= 4; p++) {
+        groups[p] = binom_small(A, p);
+        total += groups[p];
+    }
+    const int M = int(total < kSeedStates ? total : kSeedStates);
+    if (M < k) return;   // fewer distinct rows than k: no bound
+    __syncthreads();
+    for (int c = tid; c < M; c += kSeedThreads) {
+        int p = 0;
+        int64_t rank = c;
+        while (rank >= groups[p]) rank -= groups[p++];
+        int v[4];
+        for (int r = p; r >= 1; r--) {   // colex unranking of the p-subset
+            int x = r - 1;
+            while (binom_small(x + 1, r) <= rank) x++;
+            rank -= binom_small(x, r);
+            v[r - 1] = x;
+        }
+        int64_t e = sBest;
+        for (int a = 0; a < p; a++) {
+            e += d[v[a]];
+            for (int b = 0; b < a; b++) {
+                const int i = v[b], j = v[a];   // i < j
+                e += int64_t(sg[i] * sg[j]) * T[i * n + j];
+            }
+        }
+        Ec[c] = int32_t(e);
+    }
+    __syncthreads();
+    // 4. the k-th smallest of the M energies: the least value v with at
+    //    least k energies <= v (bisection on v with block-wide counts)
+    int64_t lo = INT32_MAX, hi = INT32_MIN;
+    for (int c = 0; c < M; c++) {   // every thread the same bounds
+        lo = min(lo, int64_t(Ec[c]));
+        hi = max(hi, int64_t(Ec[c]));
+    }
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (tid == 0) sCount = 0;
+        __syncthreads();
+        uint32_t cnt = 0;
+        for (int c = tid; c < M; c += kSeedThreads) cnt += Ec[c] <= mid ? 1u : 0u;
+        atomicAdd(&sCount, cnt);
+        __syncthreads();
+        const uint32_t total_le = sCount;
+        __syncthreads();
+        if (total_le >= uint32_t(k)) hi = mid;
+        else lo = mid + 1;
+    }
+    if (tid == 0) atomicMin(gthr, int32_t(lo));
+}
+
 }  // namespace
+
+hipError_t launch_topk_seed(const Inst *d_inst, int32_t *d_gthr, int k, hipStream_t stream)
+{
+    if (k < 2 || k > kSeedStates) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(topk_seed_kernel, dim3(1), dim3(kSeedThreads), 0, stream, d_inst, d_gthr, k);
+    return hipGetLastError();
+}
 
 hipError_t launch_topk_finish(const Inst *d_inst, const Inst &hI, const TopkBufs &buf, int k,
                               FinalRes *d_best, hipStream_t stream)
