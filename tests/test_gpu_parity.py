@@ -125,6 +125,22 @@ def test_stored_oracle_results(q, orc, name, tier):
 
 
 @pytest.mark.parametrize("tier", TIERS)
+def test_headline_instance_equals_oracle(q, tier):
+    """The n = 44 instance of the headline measurement (int32 U[-10^4, 10^4],
+    seed 4), solved whole in the default plan, equals the oracle's stored
+    answer over all 2^44 states (O2 in resumable shards, written by
+    make_oracle_goldens.py)."""
+    e = _golden()["n44_int_u10000_s4"]
+    assert e["method"] == "O2" and e["kwargs"] == dict(n=44, lo=-10000, hi=10000, seed=4)
+    Q = inputs.uniform_int(**e["kwargs"])
+    got = q.solve(Q, tier=tier)
+    print("headline44", tier, got.energy_i, got.index, e["best"], f"{got.kernel_ms:.1f} ms",
+          flush=True)
+    assert got.states == 2 ** 44
+    assert [got.energy_i, got.index] == e["best"]
+
+
+@pytest.mark.parametrize("tier", TIERS)
 def test_planted_n44(q, orc, tier):
     Q, xstar = inputs.planted(44, -10000, 10000, 8)
     got = q.solve(Q, tier=tier)
