@@ -492,13 +492,15 @@ qubo_status_t solve_host(const void *Q, int n, qubo_dtype_t dtype, int k, const 
         if (!P.direct) {
             P.tier = 3;
             // The list entries live in global memory and only their scalars
-            // in LDS, so the LDS row cache keeps four waves per SIMD for any
-            // k; its variant with levels 0-2 in VGPRs is the fastest top-k
-            // walk (its registers leave room for the list code).  Should it
-            // ever not fit four waves, the VGPR row cache (three waves) is
-            // taken instead.
-            if ((P.vgpr_levels == 4 || P.vgpr_levels == 3) && !(opt && opt->vgpr_levels))
-                P.vgpr_levels = qk::walk_occupancy(P.mcols, 3, 3, k) >= 4 * 4 ? 3 : 6;
+            // in LDS, so the LDS row caches keep four waves per SIMD for any
+            // k.  With the seeded bound the default one ("4") is the fastest
+            // top-k walk (its one spilled register is reloaded once per
+            // super-block); "3" is next, and the VGPR row cache (three
+            // waves) is taken should neither fit four waves.
+            if ((P.vgpr_levels == 4 || P.vgpr_levels == 3) && !(opt && opt->vgpr_levels)) {
+                if (qk::walk_occupancy(P.mcols, 4, 3, k) >= 4 * 4) P.vgpr_levels = 4;
+                else P.vgpr_levels = qk::walk_occupancy(P.mcols, 3, 3, k) >= 4 * 4 ? 3 : 6;
+            }
         }
     }
     st = solve_planned(job, stream, opt ? opt->waves_per_cu : 0, out, topk);

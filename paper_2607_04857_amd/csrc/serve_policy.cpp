@@ -19,7 +19,7 @@ size_t admit_count(const std::vector<size_t> &queued_bytes, size_t mem_used, siz
 uint64_t tick_scale(uint64_t backlog_items, uint64_t tick_items)
 {
     uint64_t scale = 1;
-    while (scale < 16 && backlog_items > 4 * scale * tick_items) scale *= 2;
+    while (scale < kMaxTickScale && backlog_items > 4 * scale * tick_items) scale *= 2;
     return scale;
 }
 

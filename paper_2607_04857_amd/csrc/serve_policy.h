@@ -25,9 +25,14 @@ namespace qsched {
 size_t admit_count(const std::vector<size_t> &queued_bytes, size_t mem_used, size_t budget,
                    size_t free_slots);
 
+// Largest tick budget multiplier: at 64 a tick gives each resident wave
+// about 128 items, so the drain at the tick's end (at most one item per
+// wave) costs under 1% of the tick.
+constexpr uint64_t kMaxTickScale = 64;
+
 // Budget multiplier for a tick: 1, doubled while the unissued work exceeds
-// four ticks' worth at the current multiplier, up to 16 (fewer tick
-// boundaries under a backlog, where requests wait anyway).
+// four ticks' worth at the current multiplier, up to kMaxTickScale (fewer
+// tick boundaries under a backlog, where requests wait anyway).
 uint64_t tick_scale(uint64_t backlog_items, uint64_t tick_items);
 
 // Items each walking request issues in one tick.  left: unissued items per

@@ -380,7 +380,8 @@ static int run_sched()
     CHECK(qsched::admit_count({size_t(-1)}, 0, 100, 8) == 0);         // no overflow
     CHECK(qsched::tick_shares({}, 8).empty());
     CHECK(qsched::tick_shares({1, 100}, 8) == std::vector<uint64_t>({1, 31}));   // backlog 101: scale 4
-    CHECK(qsched::tick_scale(0, 8) == 1 && qsched::tick_scale(1u << 20, 8) == 16);
+    CHECK(qsched::tick_scale(0, 8) == 1 && qsched::tick_scale(1u << 20, 8) == qsched::kMaxTickScale);
+    CHECK(qsched::tick_scale(4 * 16 * 8, 8) == 16 && qsched::tick_scale(4 * 16 * 8 + 1, 8) == 32);
     std::printf("sched: %d finished, %d refused, %d deferrals, %d slot uses\n", finished, rejected,
                 deferrals, slot_uses);
     return g_fail ? 1 : 0;
