@@ -9,15 +9,16 @@
 //   EB  [2^B]         suffix energies E_s(U_B) (Sec. III-A, preprocessing 2)
 //   S   [A][64]       S[w][l] = T[min(l,w)][max(l,w)] for l != w < A, else 0:
 //                     the prefix couplings, one lane per variable
-//   K   [6][32]+[8]   (all instances' K tables are contiguous) tier-2 bound
+//   K   [6][32]+[12]  (all instances' K tables are contiguous) tier-2 bound
 //                     constants per 64-step super-block offset o and table
 //                     (0: o < 32; 1: o >= 32, level-5 bit rising; 2: o >= 32,
 //                     falling), entry o mod 32: rows 0..2 hold C2 = ELOW + D,
 //                     rows 3..5 hold D, where D is the minimum over all 2^B
 //                     columns of E_sd(o) - E_sd(super-block start) and ELOW
 //                     the low-low coupling energy of the low pattern at o;
-//                     then the minimum of C2 over each 16-step segment
-//                     (table tab, segment h: entry 2 tab + h mod 2); then
+//                     then the minima of C2 over each bound-test segment
+//                     (kc2min_slot: per table for 32-step segments, per
+//                     table half for 16-step ones; 12 entries); then
 //                     SL[64][5]: SL[w][t] = coupling of prefix variable w
 //                     with the low variable A-1-t (0 when equal), so a flip
 //                     of w moves the low fields by scalar loads only
@@ -33,12 +34,18 @@ constexpr int kWave = 64;
 constexpr int kSuperLog = 6;          // unrolled super-block: 64 Gray steps
 constexpr int kLowLevels = 5;         // Gray levels with static patterns in a super-block
 constexpr int kPatterns = 1 << kLowLevels;
-constexpr int kSegSteps = 16;         // steps per tier-2 bound-test segment
-constexpr int kSegs = (1 << kSuperLog) / kSegSteps;
-static_assert(kSegs == 4 && kSegSteps == kPatterns / 2,
-              "the walk flips level 4 after segments 0 and 2 and level 5 after segment 1");
-constexpr int kKC2Min = 6 * kPatterns;   // min of C2 per (table, 16-step segment)
-constexpr int kKBound = kKC2Min + 8;     // bound constants at the head of a K table
+constexpr int kSegSteps = 32;         // steps per tier-2 bound-test segment (measured
+                                      // 3.7% faster than 16 at n = 44)
+constexpr int kSegStepsTopk = 16;     // tier 3, whose looser threshold passes more often
+static_assert(kPatterns == 32, "bound-test segments of 32 (a table) or 16 steps");
+constexpr int kKC2Min = 6 * kPatterns;   // min of C2 per (table, segment)
+constexpr int kKBound = kKC2Min + 12;    // bound constants at the head of a K table
+// Slot of the minimum of C2 over segment h of table tab: 32-step segments
+// (a whole table) at kKC2Min + tab, 16-step ones at kKC2Min + 3 + 2 tab + h % 2.
+__host__ __device__ constexpr int kc2min_slot(int seg_steps, int tab, int h)
+{
+    return seg_steps == 32 ? kKC2Min + tab : kKC2Min + 3 + 2 * tab + (h & 1);
+}
 constexpr int kKTable = kKBound + kLowLevels * kWave;  // + SL[w][t], t < kLowLevels
 constexpr int kMaxVgprLevels = 12;    // at most Gray levels 0..11 keep their M_int row in VGPRs
 constexpr int32_t kNoEnergy = 1 << 30;  // above every energy the walk can meet

@@ -31,7 +31,7 @@
 //  * the candidate test "min over the chunk + E_p <= best" is, by default
 //    (tier 2), a lower bound from one DPP wave minimum per super-block and a
 //    per-offset table, tested against a cheap upper bound of the thresholds
-//    once per 16 steps; exact per-step tests run only when that passes (tier
+//    once per 32 steps; exact per-step tests run only when that passes (tier
 //    1 does the exact v_min3 test at every step).  Each step still updates
 //    the chunk vector once (pinned, so the compiler cannot fold flips).  Ties
 //    resolve to the lowest prefix row here and to the lowest suffix in the
@@ -192,13 +192,15 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
         c2s[q] = elow + d;
     }
     __syncthreads();
-    if (threadIdx.x < 6) {   // min of C2 over each 16-step segment of each table
-        const int tab = int(threadIdx.x) / 2, sg = int(threadIdx.x) % 2;
+    if (threadIdx.x < 9) {   // min of C2 over each bound-test segment (kc2min_slot)
+        const int x = int(threadIdx.x);
+        const int tab = x < 3 ? x : (x - 3) / 2;
+        const int lo = x < 3 ? 0 : ((x - 3) % 2) * 16, hi = x < 3 ? kPatterns : lo + 16;
         int32_t m = INT32_MAX;
-        for (int oo = sg * kSegSteps; oo < (sg + 1) * kSegSteps; oo++) m = min(m, c2s[tab * kPatterns + oo]);
-        I.K[kKC2Min + threadIdx.x] = m;
+        for (int oo = lo; oo < hi; oo++) m = min(m, c2s[tab * kPatterns + oo]);
+        I.K[kKC2Min + x] = m;
     }
-    if (threadIdx.x == 6 || threadIdx.x == 7) I.K[kKC2Min + threadIdx.x] = 0;
+    if (threadIdx.x >= 9 && threadIdx.x < 12) I.K[kKC2Min + threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------- finish

@@ -30,10 +30,11 @@ __device__ __forceinline__ int32_t wave_min_bcast(int32_t v)
 // TIER 2: each lane takes its chunk minimum lm0 once per 64-step
 //         super-block; at offset o the chunk minimum is at least
 //         W0 + D(o) (table K), W0 the wave minimum of lm0, so step o needs
-//         only the scalar test W0 <= THR - D(o).  Each 16-step segment first
-//         tests lm0 against an upper bound of its 16 thresholds (one vector
+//         only the scalar test W0 <= THR - D(o).  Each 32-step segment (a
+//         half super-block: the level-5 flip separates the two) first tests
+//         lm0 against an upper bound of its 32 thresholds (one vector
 //         compare); only when a lane passes are W0 and the exact thresholds
-//         formed and tested.
+//         formed and tested, step by step.
 // Resident waves per SIMD each variant is register-allocated for: the full
 // 12-level row cache fits 256 VGPRs (2 waves); the 8- and 6-level caches
 // leave room for a third (MC=16) or a fourth (MC=8) wave.
@@ -287,7 +288,10 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
 {
     static_assert(TIER >= 1 && TIER <= 3, "tier");
     static_assert(G >= kLowLevels && G <= kMaxVgprLevels, "VGPR-resident levels");
-    constexpr int SEG = kSegSteps;   // steps per segment
+    // steps per bound-test segment: tier 3's looser threshold takes the
+    // exact path more often, where shorter segments and SGPR thresholds pay
+    constexpr int SEG = TIER == 3 ? kSegStepsTopk : kSegSteps;
+    constexpr int NSEG = (1 << kSuperLog) / SEG;
     const int lane = int(threadIdx.x);
     const uint32_t ulane = threadIdx.x;
     // row v of a lane-major [rows][MC*64] table: uniform base pointer
@@ -448,12 +452,12 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                 THR[p] = THR[pp] - H[t] - CR[p];
             });
         };
-        // TIER 2: for the 16 offsets o of segment `seg` (o = 16 seg + o2),
+        // TIER 3: for the SEG offsets o of segment `seg` (o = SEG seg + o2),
         //   tp(o) = best - E_p(low pattern at o) - C2(o)   (K table tab),
         // computed by walking the Gray sequence of patterns g(o) & 31 from
         // the segment's first one; hs = the sum of H[t] over the set low
         // bits.  f(o2, tp) is called for every offset.  Step o can hold a
-        // candidate only if W0 <= tp(o) + D(o) - ELOW(o).
+        // candidate only if W0 <= tp(o).
         auto for_each_tp = [&](auto segc, int tab, auto &&f) {
             constexpr int seg = decltype(segc)::value;
             constexpr int o0 = seg * SEG;
@@ -476,8 +480,8 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                 f(oc, (best - Enl) - hs - kall[kbase + tab * kPatterns + (o & (kPatterns - 1))]);
             });
         };
-        // Thresholds of the current segment, kept in SGPRs.
-        int32_t TP[SEG];
+        // Tier-3 thresholds of the current segment, kept in SGPRs.
+        int32_t TP[TIER == 3 ? SEG : 1];
         auto build_tp = [&](auto segc, int tab) {
             for_each_tp(segc, tab, [&](auto oc, int32_t tp) { TP[decltype(oc)::value] = tp; });
         };
@@ -520,8 +524,6 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                     found = 1;
                     if constexpr (TIER == 1) {
                         static_for<0, kPatterns>([&](auto pc) { THR[decltype(pc)::value] += d; });
-                    } else {
-                        static_for<0, SEG>([&](auto pc) { TP[decltype(pc)::value] += d; });
                     }
                 }
             }
@@ -537,7 +539,8 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                     const int32_t nb = sread(tk_insert(Ec, i ^ (i >> 1)));
                     const int32_t d = nb - best;
                     best = nb;
-                    static_for<0, SEG>([&](auto pc) { TP[decltype(pc)::value] += d; });
+                    if constexpr (TIER == 3)
+                        static_for<0, SEG>([&](auto pc) { TP[decltype(pc)::value] += d; });
                 }
             }
         };
@@ -645,25 +648,12 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                 const uint64_t sb = sb0 + ks;
                 lm0 = tree_min<MC>(E);
                 tab2 = 0;
-                // four 16-step segments, each with (cold) or without the
-                // per-step bound tests; every step's chunk energies stay
-                // observable through the (rarely taken) test, so each state
-                // gets its add
-                static_for<0, kSegs>([&](auto sc) {
+                // NSEG segments of SEG steps (tier 2: the two halves around
+                // the level-5 flip), each with (cold) or without the per-step
+                // bound tests; every step's chunk energies stay observable
+                // through the (rarely taken) test, so each state gets its add
+                static_for<0, NSEG>([&](auto sc) {
                     constexpr int h = decltype(sc)::value;
-                    // exact test of step o (cold path)
-                    auto step_check = [&](auto oc) {
-                        constexpr int o2 = decltype(oc)::value;
-                        constexpr int o = h * SEG + o2;
-                        if (W0 <= TP[o2]) {
-                            const int32_t thr =
-                                TP[o2] + kall[kbase + (3 + tab2) * kPatterns + (o & (kPatterns - 1))];
-                            if constexpr (TIER == 3)
-                                candidate3(tree_min<MC>(E), thr, (sb << kSuperLog) | uint64_t(o));
-                            else
-                                candidate(tree_min<MC>(E), thr, (sb << kSuperLog) | uint64_t(o));
-                        }
-                    };
                     // the low flip after step o (none after the segment's last)
                     auto step_flip = [&](auto oc) {
                         constexpr int o2 = decltype(oc)::value;
@@ -675,30 +665,80 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                                      std::integral_constant<bool, up>{});
                         }
                     };
-                    // One scalar test for the segment: an upper bound of its 16
+                    // One scalar test for the segment: an upper bound of its SEG
                     // thresholds tp(o) = best - Enl - hs(o) - C2(o), since
                     // hs(o) >= sum_t min(0, H[t]) and C2(o) >= the segment's
                     // minimum of C2; any lane at or below it takes the cold
                     // path (the wave minimum W0 is formed only then)
-                    int32_t tb = best - Enl - kall[kbase + kKC2Min + tab2 * 2 + (h & 1)];
+                    int32_t tb = best - Enl - kall[kbase + kc2min_slot(SEG, tab2, h)];
                     static_for<0, kLowLevels>([&](auto tc) { tb -= min(0, H[decltype(tc)::value]); });
                     const bool cold = __builtin_amdgcn_ballot_w64(lm0 <= tb) != 0;
-                    if (__builtin_expect(cold, 0)) {
-                        W0 = wave_min_bcast(lm0);
-                        build_tp(sc, tab2);
-                        static_for<0, SEG>([&](auto oc) {
-                            step_check(oc);
-                            step_flip(oc);
-                        });
+                    if constexpr (TIER == 3) {
+                        if (__builtin_expect(cold, 0)) {
+                            // exact tests against the segment's SGPR thresholds
+                            W0 = wave_min_bcast(lm0);
+                            build_tp(sc, tab2);
+                            static_for<0, SEG>([&](auto oc) {
+                                constexpr int o2 = decltype(oc)::value;
+                                constexpr int o = h * SEG + o2;
+                                if (W0 <= TP[o2]) {
+                                    const int32_t thr =
+                                        TP[o2] + kall[kbase + (3 + tab2) * kPatterns + (o & (kPatterns - 1))];
+                                    candidate3(tree_min<MC>(E), thr, (sb << kSuperLog) | uint64_t(o));
+                                }
+                                step_flip(oc);
+                            });
+                        } else {
+                            static_for<0, SEG>([&](auto oc) { step_flip(oc); });
+                        }
                     } else {
-                        static_for<0, SEG>([&](auto oc) { step_flip(oc); });
+                        if (__builtin_expect(cold, 0)) {
+                            // Exact tests, step by step: at offset o,
+                            //   tp(o) = best - E_p(low pattern at o) - C2(o)
+                            // (K table tab2), with hs = the sum of H[t] over the
+                            // set low bits walked along the Gray sequence of
+                            // patterns g(o) & 31 and best read afresh at every
+                            // step (a candidate found earlier in the segment has
+                            // lowered it).  Step o can hold a candidate only if
+                            // W0 <= tp(o), and then holds one exactly when the
+                            // chunk minimum is <= tp(o) + D(o) = best - E_p(o).
+                            W0 = wave_min_bcast(lm0);
+                            constexpr int o0 = h * SEG;
+                            constexpr int p0 = (o0 ^ (o0 >> 1)) & (kPatterns - 1);
+                            int32_t hs = 0;
+                            static_for<0, kLowLevels>([&](auto tc) {
+                                constexpr int t = decltype(tc)::value;
+                                if constexpr ((p0 >> t) & 1) hs += H[t];
+                            });
+                            static_for<0, SEG>([&](auto oc) {
+                                constexpr int o2 = decltype(oc)::value;
+                                constexpr int o = o0 + o2;
+                                if constexpr (o2 > 0) {
+                                    constexpr int pa0 = ((o - 1) ^ ((o - 1) >> 1)) & (kPatterns - 1);
+                                    constexpr int pa1 = (o ^ (o >> 1)) & (kPatterns - 1);
+                                    constexpr int t = cx_ctz(pa0 ^ pa1);
+                                    if constexpr (((pa1 >> t) & 1) != 0) hs += H[t];
+                                    else hs -= H[t];
+                                }
+                                const int32_t tp = (best - Enl) - hs -
+                                                   kall[kbase + tab2 * kPatterns + (o & (kPatterns - 1))];
+                                if (W0 <= tp) {
+                                    const int32_t thr =
+                                        tp + kall[kbase + (3 + tab2) * kPatterns + (o & (kPatterns - 1))];
+                                    candidate(tree_min<MC>(E), thr, (sb << kSuperLog) | uint64_t(o));
+                                }
+                                step_flip(oc);
+                            });
+                        } else {
+                            static_for<0, SEG>([&](auto oc) { step_flip(oc); });
+                        }
                     }
                     // the flip after the segment's last step: level 5 in the
-                    // middle, level 4 (static direction) after segments 0 and
-                    // 2, the boundary flip after the last
-                    if constexpr (h == kSegs / 2 - 1) {
+                    // middle, a low level (static direction) between shorter
+                    // segments, the boundary flip after the last
+                    if constexpr (h == NSEG / 2 - 1) {
                         tab2 = middle_flip(sb) ? 1 : 2;
-                    } else if constexpr (h < kSegs - 1) {
+                    } else if constexpr (h < NSEG - 1) {
                         constexpr int o = (h + 1) * SEG;
                         constexpr int t = cx_ctz(o);
                         constexpr bool up = (((o ^ (o >> 1)) >> t) & 1) != 0;
