@@ -254,11 +254,13 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
         L = tuned.L;
     } else {
         L = P.A < 14 ? P.A : 14;
-        // An instance sharing the GPU (batch, server) still gets at least 64
-        // items where its prefix allows: a small one then finishes on 64
-        // waves instead of one (server latency), a large one keeps 2^14-step
-        // items.
-        if (many && P.A - L < 6) L = P.A - 6 < kSuper ? kSuper : P.A - 6;
+        // An instance sharing the GPU (batch, server) gets up to 64 items
+        // where its prefix allows, of at least 2^kManyMinL steps: a small one
+        // then finishes on several waves instead of one (server latency), a
+        // large one keeps 2^14-step items, and no item is so short that its
+        // set-up (finding its instance among thousands, loading that
+        // instance's rows, the state from scratch) outweighs its walk.
+        if (many && P.A - L < 6) L = std::max(std::min(P.A, kManyMinL), P.A - 6);
         if (!many && P.A - L < 13) L = P.A - 13 < 9 ? 9 : P.A - 13;
         if (!many && P.A - L > 18) L = P.A - 18;
         if (L > P.A) L = P.A;

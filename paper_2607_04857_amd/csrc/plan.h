@@ -17,6 +17,9 @@ namespace qplan {
 // Kernel geometry shared by planner and kernels.
 constexpr int kWave = 64;          // lanes per wavefront
 constexpr int kSuper = 6;          // log2 of the unrolled Gray super-block (64 steps)
+constexpr int kManyMinL = 10;      // log2 of the shortest item of an instance in a batch or
+                                   // the server (4096 copies of n = 22: 4.0 ms per replay
+                                   // with 2^6-step items, 1.3 ms with 2^10-step ones)
 constexpr int kMaxN = 60;
 constexpr int kDirectMaxN = 14;    // n at or below this: direct evaluation, no walk
 constexpr int64_t kIntSumLimit = (int64_t(1) << 30) - 1;   // sum |T| bound, int32 input
