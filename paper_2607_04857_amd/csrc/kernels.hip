@@ -269,15 +269,22 @@ __global__ __launch_bounds__(kFinishThreads) void finish_kernel(const Inst *__re
         for (uint64_t r = threadIdx.x; r < N; r += blockDim.x) lexmin(bE, bI, energy_int(sT, n, r), r);
         block_lexmin(bE, bI, sE, sI);
     } else {
-        // the records of items whose bit is set (the others were never written)
+        // the records of items whose bit is set (the others were never
+        // written); each thread takes four consecutive bitmap words at a
+        // time, loaded together before any is examined
         const uint64_t words = (I.n_items + 31) / 32;
-        for (uint64_t w = threadIdx.x; w < words; w += blockDim.x) {
-            uint32_t x = I.bits[w];
-            while (x) {
-                const uint32_t b = uint32_t(__builtin_ctz(x));
-                x &= x - 1u;
-                const ItemRes r = I.res[w * 32 + b];
-                lexmin(bE, bI, r.E, r.row);
+        for (uint64_t w0 = uint64_t(threadIdx.x) * 4; w0 < words; w0 += uint64_t(blockDim.x) * 4) {
+            uint32_t x[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) x[k] = w0 + k < words ? I.bits[w0 + k] : 0u;
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                while (x[k]) {
+                    const uint32_t b = uint32_t(__builtin_ctz(x[k]));
+                    x[k] &= x[k] - 1u;
+                    const ItemRes r = I.res[(w0 + k) * 32 + b];
+                    lexmin(bE, bI, r.E, r.row);
+                }
             }
         }
         block_lexmin(bE, bI, sE, sI);
