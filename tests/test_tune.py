@@ -182,3 +182,21 @@ def test_unknown_scope_in_cache_rejected(q, tmp_path):
     with pytest.raises(q.QuboError) as ei:
         q.tune_load(str(path), KEY)
     assert "scope" in ei.value.message
+
+
+def test_shipped_cache_loads_whole(q):
+    """The tuning cache shipped with the package is valid for this build: every
+    entry passes the planner's checks (a stale entry would make the library
+    reject the whole file and fall back to the built-in plans), both scopes
+    and both dtypes are present, and an entry drives the plan it names."""
+    import os
+    path = os.path.join(os.path.dirname(q.__file__), "tuning", "gfx950_256cu.json")
+    doc = json.load(open(path))
+    assert doc["device"] == "gfx950/256cu"
+    assert q.tune_load(path, "gfx950/256cu") == len(doc["entries"])
+    kinds = {(e["scope"], e["dtype"]) for e in doc["entries"]}
+    assert kinds == {("single", "int32"), ("single", "fp32"), ("batch", "int32"), ("batch", "fp32")}
+    e = q.tune_lookup(40)
+    assert e is not None
+    info = q.plan_info(inputs.uniform_int(40, -100, 100, 40))
+    assert (info["B"], info["tier"], info["vgpr_levels"]) == (e["B"], e["tier"], e["vgpr_levels"])
