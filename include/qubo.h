@@ -141,8 +141,14 @@ qubo_status_t qubo_solve_ex(const void *Q, int n, qubo_dtype_t dtype, int k,
 
 /* Solve one instance whose Q is already in DEVICE memory of the current HIP
  * device (e.g. a torch tensor's data_ptr), ordering all work on hip_stream
- * (a hipStream_t; NULL = the null stream).  Returns after the result has been
- * copied back (the stream is synchronised). */
+ * (a hipStream_t; NULL = the null stream).  Q is read only on the device:
+ * the fold, the int32 exactness proof and the float32 fixed-point scaling run
+ * in a kernel ordered after whatever wrote dQ on that stream, with the same
+ * arithmetic (and so the same plan, T, p and answer) as qubo_solve on a host
+ * copy.  Returns after the result has been copied back (the stream is
+ * synchronised once, at the end); input errors (QUBO_EOVERFLOW,
+ * QUBO_ENONFINITE) are detected on the device and reported then, after a
+ * walk that skips every item. */
 qubo_status_t qubo_solve_device(const void *dQ, int n, qubo_dtype_t dtype, int k,
                                 void *hip_stream, qubo_result_t *out,
                                 qubo_state_t *topk);

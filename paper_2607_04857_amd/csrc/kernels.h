@@ -54,6 +54,22 @@ constexpr int kMaxPrefixRows = 60 - 6;   // A = n - B <= 60 - 6
 
 struct ItemRes;
 
+// An instance whose Q is prepared on the device (lone solve of a device
+// pointer): the preparation's outcome, written by prepare_kernel.
+constexpr int64_t kExactSumLimit = (int64_t(1) << 30) - 1;   // sum |T| bound of the int32 walk
+constexpr int32_t kPrepOverflow = 1;    // int32 input with sum |T| above kExactSumLimit
+constexpr int32_t kPrepNonFinite = 2;   // float32 input with a NaN or Inf
+constexpr int32_t kPrepInternal = 3;    // scaled float32 matrix above the bound
+struct PrepOut {
+    int32_t status;      // 0, or kPrepOverflow / kPrepNonFinite / kPrepInternal
+    int32_t p;           // fixed-point exponent (float32 input), else 0
+    int64_t sum_abs;     // sum of |T_ij|, i <= j, of the int32 matrix solved
+    double eps_q;        // per-state quantisation bound (float32 input), else 0
+    int64_t hist_lo;     // top-k histogram: energy of bin 0's lower edge ...
+    int32_t hist_shift;  // ... and the bin shift
+    int32_t pad;
+};
+
 struct Inst {
     const int32_t *T;
     int32_t *M;
@@ -79,6 +95,8 @@ struct Inst {
                            // words bits[0 .. ceil(n_items / 32)))
     int32_t *gbest;        // best energy any wave has found for the instance
                            // (kNoEnergy from the table build on)
+    const PrepOut *prep;   // device-prepared instance: its preparation (an error
+                           // makes the walk skip all items), else null
 };
 
 struct ItemRes {
@@ -102,6 +120,8 @@ struct TopkWalk {
     int64_t hist_lo;     // energy of bin 0's lower edge (-sum|T|)
     int hist_shift;      // bin = (E - hist_lo) >> hist_shift
     int k;
+    const PrepOut *prep; // device-prepared instance: hist_lo and hist_shift come
+                         // from here instead (null otherwise)
 };
 constexpr int kTopkBins = 16384;
 
@@ -139,8 +159,16 @@ struct FinalRes {
     int32_t pad;
 };
 
+// Fold, check and (float32) scale the caller's device matrix dQ (n x n,
+// row-major, int32 or float32) into the instance's upper-triangular int32 T
+// (d_T, n x n), exactly as the host planner does, and write the outcome to
+// *d_prep.  On an input error T is left zero and the status says why.
+hipError_t launch_prepare(const void *dQ, int n, int is_fp32, int32_t *d_T, PrepOut *d_prep,
+                          hipStream_t stream);
+
 // Builds M, EB, S, K for every instance, clears each instance's item bitmap
-// and shared best, and zeroes n_counters item counters.
+// and shared best, and zeroes n_counters item counters (for a device-prepared
+// instance whose preparation failed, the counters are set past every item).
 hipError_t launch_tables(const Inst *d_insts, int n_inst, int max_A, unsigned long long *d_counters,
                          int n_counters, hipStream_t stream);
 

@@ -66,8 +66,11 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
                                                      int n_counters)
 {
     const Inst I = insts[blockIdx.y];
-    if (blockIdx.x == 0 && blockIdx.y == 0)
-        for (int c = int(threadIdx.x); c < n_counters; c += int(blockDim.x)) counters[c] = 0ull;
+    if (blockIdx.x == 0 && blockIdx.y == 0) {
+        // a device-prepared instance whose input was refused walks no item
+        const unsigned long long c0 = (I.prep && I.prep->status != 0) ? (1ull << 62) : 0ull;
+        for (int c = int(threadIdx.x); c < n_counters; c += int(blockDim.x)) counters[c] = c0;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0 && I.gbest) {
         atomicExch(I.gbest, kNoEnergy);
         __threadfence();
@@ -201,6 +204,122 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
         I.K[kKC2Min + x] = m;
     }
     if (threadIdx.x >= 9 && threadIdx.x < 12) I.K[kKC2Min + threadIdx.x] = 0;
+}
+
+// ---------------------------------------------------------------- prepare
+
+// Canonicalisation of a lone instance held in device memory, with the host
+// planner's arithmetic: fold T_ii = Q_ii, T_ij = Q_ij + Q_ji (i < j; the
+// energy sums over all pairs); int32 input: sum |T| <= 2^30 - 1 proves every
+// partial sum the walk forms exact in int32; float32 input: all entries
+// finite, S = sum |T| in float64 accumulated i ascending then j ascending
+// (the host's order, so the same S), p = the largest exponent with
+// S 2^p <= 2^29, T~ = round-half-even(T 2^p).
+constexpr int kPrepThreads = 256;
+
+__device__ __forceinline__ int prep_scale_exponent(double S)
+{
+    // S = m 2^e, m in [0.5, 1): m 2^(e+p) <= 2^29 for e + p <= 29, and for
+    // e + p = 30 exactly when m = 0.5
+    if (!(S > 0.0)) return 0;
+    int e = 0;
+    const double m = frexp(S, &e);
+    return (m == 0.5 ? 30 : 29) - e;
+}
+
+__global__ __launch_bounds__(kPrepThreads) void prepare_kernel(const void *__restrict__ dQ, int n,
+                                                               int is_fp32, int32_t *__restrict__ T,
+                                                               PrepOut *__restrict__ out)
+{
+    __shared__ double sTd[kMaxVars * kMaxVars];   // folded float32 input in float64
+    __shared__ unsigned long long sSum;
+    __shared__ int sNnz, sBad;
+    __shared__ double sS;
+    const int tid = int(threadIdx.x), nn = n * n;
+    if (tid == 0) {
+        sSum = 0ull;
+        sNnz = 0;
+        sBad = 0;
+    }
+    __syncthreads();
+    uint64_t mySum = 0;
+    int myNnz = 0, myBad = 0;
+    if (!is_fp32) {
+        const int32_t *q = static_cast<const int32_t *>(dQ);
+        for (int e = tid; e < nn; e += kPrepThreads) {
+            const int i = e / n, j = e % n;
+            int32_t v = 0;
+            if (i <= j) {
+                const int64_t t = i == j ? int64_t(q[e]) : int64_t(q[e]) + int64_t(q[j * n + i]);
+                mySum += uint64_t(t < 0 ? -t : t);
+                v = int32_t(t);   // kept only if the bound holds (else T is zeroed)
+            }
+            T[e] = v;
+        }
+    } else {
+        const float *q = static_cast<const float *>(dQ);
+        for (int e = tid; e < nn; e += kPrepThreads) {
+            const int i = e / n, j = e % n;
+            double t = 0.0;
+            if (i <= j) {
+                const double a = double(q[e]), b = i == j ? 0.0 : double(q[j * n + i]);
+                if (!isfinite(a) || !isfinite(b)) myBad = 1;
+                t = a + b;
+                if (t != 0.0) myNnz++;
+            }
+            sTd[e] = t;
+        }
+    }
+    atomicAdd(&sSum, (unsigned long long)mySum);
+    atomicAdd(&sNnz, myNnz);
+    atomicOr(&sBad, myBad);
+    __syncthreads();
+    int32_t status = 0;
+    int p = 0;
+    int64_t sum = 0;
+    double eps = 0.0;
+    if (!is_fp32) {
+        sum = int64_t(sSum);
+        if (sum > kExactSumLimit) status = kPrepOverflow;
+    } else if (sBad) {
+        status = kPrepNonFinite;
+    } else {
+        if (tid == 0) {
+            double S = 0.0;
+            for (int i = 0; i < n; i++)
+                for (int j = i; j < n; j++) S += fabs(sTd[i * n + j]);
+            sS = S;
+            sSum = 0ull;
+        }
+        __syncthreads();
+        p = prep_scale_exponent(sS);
+        uint64_t s2 = 0;
+        for (int e = tid; e < nn; e += kPrepThreads) {
+            const int64_t t = int64_t(rint(ldexp(sTd[e], p)));   // ties to even
+            s2 += uint64_t(t < 0 ? -t : t);
+            T[e] = int32_t(t);
+        }
+        atomicAdd(&sSum, (unsigned long long)s2);
+        __syncthreads();
+        sum = int64_t(sSum);
+        if (sum > kExactSumLimit) status = kPrepInternal;
+        eps = double(sNnz) * ldexp(1.0, -p - 1);
+    }
+    if (status != 0)
+        for (int e = tid; e < nn; e += kPrepThreads) T[e] = 0;
+    if (tid == 0) {
+        PrepOut o;
+        o.status = status;
+        o.p = status ? 0 : p;
+        o.sum_abs = status ? 0 : sum;
+        o.eps_q = status ? 0.0 : eps;
+        int shift = 0;
+        while (((2 * o.sum_abs) >> shift) >= kTopkBins) shift++;
+        o.hist_lo = -o.sum_abs;
+        o.hist_shift = shift;
+        o.pad = 0;
+        *out = o;
+    }
 }
 
 // ---------------------------------------------------------------- finish
@@ -350,6 +469,15 @@ __global__ __launch_bounds__(kFinishThreads) void finish_kernel(const Inst *__re
 }
 
 // ---------------------------------------------------------------- launchers
+
+hipError_t launch_prepare(const void *dQ, int n, int is_fp32, int32_t *d_T, PrepOut *d_prep,
+                          hipStream_t stream)
+{
+    if (n < 1 || n > kMaxVars) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(kPrepThreads), 0, stream, dQ, n, is_fp32, d_T,
+                       d_prep);
+    return hipGetLastError();
+}
 
 hipError_t launch_tables(const Inst *d_insts, int n_inst, int max_A, unsigned long long *d_counters,
                          int n_counters, hipStream_t stream)

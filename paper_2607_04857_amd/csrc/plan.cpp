@@ -100,13 +100,20 @@ bool tune_valid(const TuneEntry &e, std::string *msg)
     return true;
 }
 
-qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_options_t *opt,
-                        Plan *out, std::string *msg, bool many)
+static_assert(kFpScaleTarget == 536870912.0, "fp_scale_exponent assumes the 2^29 target");
+
+int fp_scale_exponent(double S)
 {
-    if (!Q || !out) {
-        *msg = "null argument";
-        return QUBO_EINVAL;
-    }
+    // S = m 2^e with m in [0.5, 1): m 2^(e+p) <= 2^29 holds for e + p <= 29,
+    // and for e + p = 30 exactly when m = 0.5
+    if (!(S > 0.0)) return 0;
+    int e = 0;
+    const double m = std::frexp(S, &e);
+    return (m == 0.5 ? 30 : 29) - e;
+}
+
+static qubo_status_t check_args(int n, qubo_dtype_t dtype, std::string *msg)
+{
     if (n < 1 || n > kMaxN) {
         *msg = "n must be in [1, 60]";
         return QUBO_EINVAL;
@@ -115,6 +122,20 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
         *msg = "unknown dtype";
         return QUBO_EINVAL;
     }
+    return QUBO_OK;
+}
+
+static qubo_status_t plan_walk(const qubo_options_t *opt, Plan &P, std::string *msg, bool many);
+
+qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_options_t *opt,
+                        Plan *out, std::string *msg, bool many)
+{
+    if (!Q || !out) {
+        *msg = "null argument";
+        return QUBO_EINVAL;
+    }
+    qubo_status_t st = check_args(n, dtype, msg);
+    if (st != QUBO_OK) return st;
     Plan P;
     P.n = n;
     P.dtype = dtype;
@@ -159,11 +180,7 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
         }
         // Largest p with S * 2^p <= 2^29; every partial sum of T~ then stays
         // within 2^29 + nnz / 2 < 2^30 - 1.
-        int p = 0;
-        if (S > 0.0) {
-            p = int(std::floor(std::log2(kFpScaleTarget / S)));
-            while (std::ldexp(S, p) > kFpScaleTarget) p--;
-        }
+        const int p = fp_scale_exponent(S);
         int64_t sum = 0;
         for (size_t i = 0; i < nn; i++)
             for (size_t j = i; j < nn; j++) {
@@ -182,7 +199,35 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
         // state's energy sums at most nnz entries.
         P.eps_q = double(nnz) * std::ldexp(1.0, -p - 1);
     }
+    st = plan_walk(opt, P, msg, many);
+    if (st != QUBO_OK) return st;
+    *out = std::move(P);
+    return QUBO_OK;
+}
 
+qubo_status_t make_plan_shape(int n, qubo_dtype_t dtype, const qubo_options_t *opt, Plan *out,
+                              std::string *msg)
+{
+    if (!out) {
+        *msg = "null argument";
+        return QUBO_EINVAL;
+    }
+    qubo_status_t st = check_args(n, dtype, msg);
+    if (st != QUBO_OK) return st;
+    Plan P;
+    P.n = n;
+    P.dtype = dtype;
+    st = plan_walk(opt, P, msg, false);
+    if (st != QUBO_OK) return st;
+    *out = std::move(P);
+    return QUBO_OK;
+}
+
+// The walk plan of P (n and dtype set): split, tier, row cache, items.
+static qubo_status_t plan_walk(const qubo_options_t *opt, Plan &P, std::string *msg, bool many)
+{
+    const int n = P.n;
+    const qubo_dtype_t dtype = P.dtype;
     // A tuned choice applies when the caller overrides none of the walk knobs.
     TuneEntry tuned;
     const bool overridden = opt && (opt->B || opt->L || opt->tier || opt->vgpr_levels);
@@ -218,7 +263,6 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
         P.L = 0;
         P.items = 0;
         P.tier = 0;
-        *out = std::move(P);
         return QUBO_OK;
     }
     if (B > kMaxB) B = kMaxB;
@@ -277,7 +321,6 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
         P.item_first = uint64_t(opt->item_first);
         P.item_count = uint64_t(opt->item_count);
     }
-    *out = std::move(P);
     return QUBO_OK;
 }
 

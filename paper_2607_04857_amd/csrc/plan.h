@@ -77,4 +77,14 @@ bool tune_valid(const TuneEntry &e, std::string *msg);
 qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_options_t *opt,
                         Plan *out, std::string *msg, bool many = false);
 
+// The walk plan of an instance whose values are not on the host (a lone
+// solve of a device-resident Q): as make_plan, except that T, p, eps_q and
+// sum_abs are left for the device to fill (the plan does not depend on them).
+qubo_status_t make_plan_shape(int n, qubo_dtype_t dtype, const qubo_options_t *opt, Plan *out,
+                              std::string *msg);
+
+// Fixed-point exponent of a float32 input: the largest p with S 2^p <= 2^29
+// for S = sum |T_ij| > 0 (0 for S = 0), exactly (from S's binary exponent).
+int fp_scale_exponent(double S);
+
 }  // namespace qplan

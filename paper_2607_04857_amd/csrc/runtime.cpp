@@ -8,6 +8,7 @@
 #include <mutex>
 
 static_assert(qk::kMaxVars == qplan::kMaxN, "finish kernel LDS sized for the largest n");
+static_assert(qk::kExactSumLimit == qplan::kIntSumLimit, "one int32 exactness bound");
 
 namespace qrt {
 
@@ -17,7 +18,7 @@ thread_local std::string g_last_error;
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct JobOffsets {
-    size_t insts = 0, counter = 0, res = 0, out = 0, K = 0, gbest = 0;
+    size_t insts = 0, counter = 0, res = 0, out = 0, K = 0, gbest = 0, prep = 0;
     std::vector<size_t> T, Qf, M, EB, S, bits;
     // top-k (k > 1, one instance)
     size_t gthr = 0, hist = 0, lowbin = 0, candN = 0, candE = 0, candR = 0, listE = 0, listR = 0, listCount = 0, chunkE = 0, chunkR = 0, chunkCount = 0,
@@ -119,6 +120,8 @@ static JobOffsets compute_offsets(const Job &job, size_t *stage_bytes, size_t *b
     off = align_up(off + ni * sizeof(qk::FinalRes), 256);
     o.gbest = off;
     off = align_up(off + ni * sizeof(int32_t), 256);
+    o.prep = off;
+    off = align_up(off + sizeof(qk::PrepOut), 256);
     if (k > 1) {
         const qplan::Plan &P = job.plans[0];
         const size_t W = job.groups.empty() ? 0 : size_t(job.groups[0].waves);
@@ -216,6 +219,8 @@ qubo_status_t job_bind(Job *job, void *d_mem)
     job->d_res = reinterpret_cast<qk::ItemRes *>(base + o.res);
     job->d_out = reinterpret_cast<qk::FinalRes *>(base + o.out);
     job->d_k = reinterpret_cast<int32_t *>(base + o.K);
+    job->d_prep = job->dq ? reinterpret_cast<qk::PrepOut *>(base + o.prep) : nullptr;
+    job->d_T0 = reinterpret_cast<int32_t *>(base + o.T[0]);
     std::vector<qk::Inst> insts(job->plans.size());
     uint64_t item = 0;        // result slot of the instance's first item (whole job)
     // walk numbering restarts at 0 in every group
@@ -251,8 +256,15 @@ qubo_status_t job_bind(Job *job, void *d_mem)
         I.item_local0 = P.item_first;
         I.n_items = P.direct ? 0 : P.walk_items();
         I.gbest = reinterpret_cast<int32_t *>(base + o.gbest) + i;
+        I.prep = job->d_prep;
         const size_t nn = size_t(P.n) * P.n;
-        std::memcpy(job->stage.data() + o.T[i], P.T.data(), nn * sizeof(int32_t));
+        if (job->dq) {
+            // T is written by the prepare kernel; the float64 rescore reads
+            // the caller's matrix where it is
+            if (P.dtype == QUBO_FP32) I.Qf = static_cast<const float *>(job->dq);
+        } else {
+            std::memcpy(job->stage.data() + o.T[i], P.T.data(), nn * sizeof(int32_t));
+        }
         if (job->qf[i]) std::memcpy(job->stage.data() + o.Qf[i], job->qf[i], nn * sizeof(float));
     }
     std::memcpy(job->stage.data() + o.insts, insts.data(), insts.size() * sizeof(qk::Inst));
@@ -273,6 +285,7 @@ qubo_status_t job_bind(Job *job, void *d_mem)
         while ((span >> shift) >= qk::kTopkBins) shift++;
         t.walk.hist_lo = -job->plans[0].sum_abs;
         t.walk.hist_shift = shift;
+        t.walk.prep = job->d_prep;   // device-prepared: the bins from the preparation
         t.walk.k = job->topk;
         t.waves = job->groups.empty() ? 0 : job->groups[0].waves;
         t.candE = reinterpret_cast<int32_t *>(base + o.candE);
@@ -297,6 +310,10 @@ qubo_status_t job_enqueue_kernels(const Job &job, hipStream_t stream, hipEvent_t
                                   hipEvent_t walk_end)
 {
     const int ni = int(job.plans.size());
+    if (job.dq)
+        QRT_HIP(qk::launch_prepare(job.dq, job.plans[0].n, job.plans[0].dtype == QUBO_FP32 ? 1 : 0,
+                                   job.d_T0, job.d_prep, stream),
+                "prepare kernel");
     QRT_HIP(qk::launch_tables(job.d_insts, ni, job.max_A, job.d_counter, int(job.groups.size()),
                               stream),
             "tables kernel");
@@ -387,6 +404,7 @@ qubo_status_t solve_planned(qrt::Job &job, hipStream_t stream, int waves_per_cu,
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     qubo_status_t rs = QUBO_OK;
     qk::FinalRes fr{};
+    qk::PrepOut prep{};
     std::vector<qk::TopkState> tk_host;
     do {
         if ((rs = qrt::job_bind(&job, d_mem)) != QUBO_OK) break;
@@ -404,6 +422,11 @@ qubo_status_t solve_planned(qrt::Job &job, hipStream_t stream, int waves_per_cu,
         if ((e = hipMemcpyAsync(&fr, job.d_out, sizeof(fr), hipMemcpyDeviceToHost, stream)) !=
             hipSuccess) {
             rs = qrt::device_error("hipMemcpyAsync D2H", e);
+            break;
+        }
+        if (job.dq && (e = hipMemcpyAsync(&prep, job.d_prep, sizeof(prep), hipMemcpyDeviceToHost,
+                                          stream)) != hipSuccess) {
+            rs = qrt::device_error("hipMemcpyAsync D2H preparation", e);
             break;
         }
         if (job.topk > 1) {
@@ -425,6 +448,25 @@ qubo_status_t solve_planned(qrt::Job &job, hipStream_t stream, int waves_per_cu,
     if (rs != QUBO_OK) return rs;
     if (es != hipSuccess) return qrt::device_error("hipStreamSynchronize", es);
     if (ef != hipSuccess) return qrt::device_error("hipFreeAsync", ef);
+    if (job.dq) {
+        // the device preparation's verdict on the input, as the host planner's
+        switch (prep.status) {
+        case 0: break;
+        case qk::kPrepOverflow:
+            qrt::set_error("sum of |T_ij| exceeds 2^30 - 1: int32 walk not provably exact");
+            return QUBO_EOVERFLOW;
+        case qk::kPrepNonFinite:
+            qrt::set_error("non-finite entry in Q");
+            return QUBO_ENONFINITE;
+        default:
+            qrt::set_error("internal: scaled matrix exceeds the int32 bound");
+            return QUBO_EINTERNAL;
+        }
+        qplan::Plan &P = job.plans[0];
+        P.p = prep.p;
+        P.eps_q = prep.eps_q;
+        P.sum_abs = prep.sum_abs;
+    }
     st = qrt::job_result(job, 0, fr, out);
     if (st != QUBO_OK) return st;
     if (job.topk > 1 && topk) {
@@ -466,6 +508,24 @@ qubo_status_t check_k(int k, int n, qubo_state_t *topk)
     return QUBO_OK;
 }
 
+// The top-k walk keeps candidate lists (tier 3); the finish selects.
+void plan_topk(qrt::Job &job, int k, const qubo_options_t *opt)
+{
+    job.topk = k;
+    qplan::Plan &P = job.plans[0];
+    if (P.direct) return;
+    P.tier = 3;
+    // The list entries live in global memory and only their scalars in LDS,
+    // so the LDS row caches keep four waves per SIMD for any k.  With the
+    // seeded bound the default one ("4") is the fastest top-k walk (its one
+    // spilled register is reloaded once per super-block); "3" is next, and
+    // the VGPR row cache (three waves) is taken should neither fit four waves.
+    if ((P.vgpr_levels == 4 || P.vgpr_levels == 3) && !(opt && opt->vgpr_levels)) {
+        if (qk::walk_occupancy(P.mcols, 4, 3, k) >= 4 * 4) P.vgpr_levels = 4;
+        else P.vgpr_levels = qk::walk_occupancy(P.mcols, 3, 3, k) >= 4 * 4 ? 3 : 6;
+    }
+}
+
 qubo_status_t solve_host(const void *Q, int n, qubo_dtype_t dtype, int k, const qubo_options_t *opt,
                          hipStream_t stream, qubo_result_t *out, qubo_state_t *topk)
 {
@@ -485,24 +545,7 @@ qubo_status_t solve_host(const void *Q, int n, qubo_dtype_t dtype, int k, const 
         return st;
     }
     job.qf.push_back(dtype == QUBO_FP32 ? static_cast<const float *>(Q) : nullptr);
-    if (k > 1) {
-        // the top-k walk keeps candidate lists (tier 3); the finish selects
-        job.topk = k;
-        qplan::Plan &P = job.plans[0];
-        if (!P.direct) {
-            P.tier = 3;
-            // The list entries live in global memory and only their scalars
-            // in LDS, so the LDS row caches keep four waves per SIMD for any
-            // k.  With the seeded bound the default one ("4") is the fastest
-            // top-k walk (its one spilled register is reloaded once per
-            // super-block); "3" is next, and the VGPR row cache (three
-            // waves) is taken should neither fit four waves.
-            if ((P.vgpr_levels == 4 || P.vgpr_levels == 3) && !(opt && opt->vgpr_levels)) {
-                if (qk::walk_occupancy(P.mcols, 4, 3, k) >= 4 * 4) P.vgpr_levels = 4;
-                else P.vgpr_levels = qk::walk_occupancy(P.mcols, 3, 3, k) >= 4 * 4 ? 3 : 6;
-            }
-        }
-    }
+    if (k > 1) plan_topk(job, k, opt);
     st = solve_planned(job, stream, opt ? opt->waves_per_cu : 0, out, topk);
     if (st == QUBO_OK && k == 1 && topk) topk[0] = out->best;
     return st;
@@ -548,14 +591,30 @@ qubo_status_t qubo_solve_device(const void *dQ, int n, qubo_dtype_t dtype, int k
         }
         qubo_status_t st = check_k(k, n, topk);
         if (st != QUBO_OK) return st;
+        if (!out) {
+            qrt::set_error("null output");
+            return QUBO_EINVAL;
+        }
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
-        // The planner's fold and exactness proof run on the host over the
-        // n x n input (at most 14.4 KB), so fetch it first.
-        std::vector<uint32_t> hq(size_t(n) * n);
-        QRT_HIP(hipMemcpyAsync(hq.data(), dQ, hq.size() * 4, hipMemcpyDeviceToHost, s),
-                "hipMemcpyAsync Q D2H");
-        QRT_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
-        return solve_host(hq.data(), n, dtype, k, nullptr, s, out, topk);
+        // The plan depends on n, dtype and the tuning table only; the fold,
+        // the exactness proof and the float32 scaling run on the device, in
+        // stream order after whatever wrote dQ, and their outcome comes back
+        // with the answer (one synchronisation, at the end).
+        qrt::tune_autoload();
+        qrt::Job job;
+        job.plans.resize(1);
+        std::string msg;
+        st = qplan::make_plan_shape(n, dtype, nullptr, &job.plans[0], &msg);
+        if (st != QUBO_OK) {
+            qrt::set_error(msg);
+            return st;
+        }
+        job.qf.push_back(nullptr);
+        job.dq = dQ;
+        if (k > 1) plan_topk(job, k, nullptr);
+        st = solve_planned(job, s, 0, out, topk);
+        if (st == QUBO_OK && k == 1 && topk) topk[0] = out->best;
+        return st;
     } catch (const std::bad_alloc &) {
         qrt::set_error("host allocation failed");
         return QUBO_ENOMEM;

@@ -60,6 +60,12 @@ struct Job {
     qk::FinalRes *d_out = nullptr;
     int32_t *d_k = nullptr;              // all K tables, instance i at i * kKTable
 
+    // a lone instance whose Q is in device memory (qubo_solve_device): the
+    // prepare kernel folds and scales it into T on the device
+    const void *dq = nullptr;
+    qk::PrepOut *d_prep = nullptr;
+    int32_t *d_T0 = nullptr;             // instance 0's T
+
     // top-k (k > 1): one instance, walked at tier 3
     int topk = 0;
     qk::TopkBufs tkb{};

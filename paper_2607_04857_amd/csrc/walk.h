@@ -113,7 +113,7 @@ __device__ __forceinline__ void tk_init(const TopkWalk &tk)
         M[2] = kNoEnergy;
         M[3] = kNoEnergy;
         M[4] = tk.k;
-        M[5] = tk.hist_shift;
+        M[5] = tk.prep ? tk.prep->hist_shift : tk.hist_shift;
         P[0] = 0;
         P[1] = reinterpret_cast<uint64_t>(tk.gthr);
         P[2] = reinterpret_cast<uint64_t>(tk.listE);
@@ -121,7 +121,7 @@ __device__ __forceinline__ void tk_init(const TopkWalk &tk)
         P[4] = reinterpret_cast<uint64_t>(tk.listCount);
         P[5] = reinterpret_cast<uint64_t>(tk.hist);
         P[6] = reinterpret_cast<uint64_t>(tk.lowbin);
-        P[7] = uint64_t(tk.hist_lo);
+        P[7] = uint64_t(tk.prep ? tk.prep->hist_lo : tk.hist_lo);
     }
     __syncthreads();
 }

@@ -57,3 +57,15 @@ def check_fp32(orc, Q, got, E_star, idx_star=None):
     assert got.tol <= 1e-5 * scale, (got.tol, scale)
     if idx_star is not None and got.index != idx_star:
         assert e - E_star <= got.tol
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _torch_before_library(request):
+    """Sessions that run GPU tests initialise torch's HIP runtime before any
+    test loads the library: torch ships its own copy of the runtime, and that
+    copy finds no device when it starts after the library's."""
+    if any(item.get_closest_marker("gpu") for item in request.session.items):
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    yield

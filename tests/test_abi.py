@@ -87,6 +87,20 @@ def test_fp32_fixed_point_scale():
     assert info["eps_q"] * 2 <= 1e-5 * np.abs(Q.astype(np.float64)).sum()
 
 
+@pytest.mark.parametrize("S,p", [(2.0 ** 20, 9), (2.0 ** 20 + 1, 8), (2.0 ** 20 - 1, 9),
+                                 (0.75, 29), (0.5, 30), (2.0 ** 29, 0), (2.0 ** 29 + 64, -1)])
+def test_fp32_exponent_at_powers_of_two(S, p):
+    """p is the largest exponent with S 2^p <= 2^29 exactly, also where
+    2^29 / S is a power of two or one unit of rounding away from one (a
+    single float32 entry on the diagonal: S = |Q_00|)."""
+    Q = np.zeros((3, 3), dtype=np.float32)
+    Q[0, 0] = np.float32(-S)
+    assert float(Q[0, 0]) == -S
+    info = q.plan_info(Q)
+    assert info["p"] == p
+    assert S * 2.0 ** p <= 2 ** 29 < S * 2.0 ** (p + 1)
+
+
 @pytest.mark.parametrize("n,full", [(60, False), (60, True), (46, False), (20, True)])
 def test_fp32_tolerance_bound(n, full):
     """tol = 2 eps_q = nnz 2^-p, and p is the largest exponent with
