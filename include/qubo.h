@@ -194,6 +194,30 @@ qubo_status_t qubo_batch_results(qubo_batch_t *batch, qubo_result_t *out);
 qubo_status_t qubo_batch_stats(qubo_batch_t *batch, double *states, double *kernel_ms);
 void qubo_batch_destroy(qubo_batch_t *batch);
 
+/* Outer-bit reduction (Sec. III-C.1, straightforward parallelisation; used
+ * in Sec. IV-C beyond the kernel's size limit).  Fixing the first k variables
+ * to xf (variable i < k is bit k-1-i of xf, i.e. xf holds the top k bits of
+ * the index) leaves the QUBO of the other m = n - k variables
+ *     Qr = T_rr + diag(x_f T_fr),   c = x_f T_ff x_f^T,
+ * with T the folded upper-triangular form of Q, so that for every x_r
+ * E(x_f, x_r) = c + E_Qr(x_r).  Q: int32 n x n row-major (host); Qr:
+ * caller's m x m int32 buffer (upper-triangular on return); c: the constant.
+ * 2 <= n <= 64, 1 <= k < n, xf < 2^k (QUBO_EINVAL); QUBO_EOVERFLOW if an
+ * entry of Qr leaves int32. */
+qubo_status_t qubo_reduce_outer(const int32_t *Q, int n, int k, uint64_t xf,
+                                int32_t *Qr, int64_t *c);
+
+/* Solve by outer reduction: the 2^k reduced instances (qubo_reduce_outer)
+ * run as one batch, and the answer is the lexicographic minimum of
+ * (c(x_f) + E'_min, x_f 2^(n-k) + index'), the same (E, lowest index) as a
+ * direct solve.  Extends n to 64 (each reduced instance has n - k <= 60
+ * variables).  int32 input only (QUBO_EINVAL otherwise); 2 <= n <= 64,
+ * 1 <= k <= 12, 1 <= n - k <= 60.  out: the best state and the first
+ * reduced instance's plan fields; states = 2^n (saturated at n = 64);
+ * kernel_ms = the batch's walk time. */
+qubo_status_t qubo_solve_outer(const void *Q, int n, qubo_dtype_t dtype, int k,
+                               qubo_result_t *out);
+
 /* Continuous-batching server (see the serving notes in the docs):
  * requests are admitted into device slots as slots and the device-memory
  * budget allow; each scheduler tick launches one walk over pending work items

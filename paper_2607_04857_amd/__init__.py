@@ -90,6 +90,8 @@ _SIGS = {
     "qubo_solve_device": (_I, [_VP, _I, _I, _I, _VP, ctypes.POINTER(_Result),
                                ctypes.POINTER(_State)]),
     "qubo_solve_noalloc": (_I, [_VP, _I, _I, _VP, ctypes.POINTER(_Result)]),
+    "qubo_reduce_outer": (_I, [_VP, _I, _I, ctypes.c_uint64, _VP, ctypes.POINTER(ctypes.c_int64)]),
+    "qubo_solve_outer": (_I, [_VP, _I, _I, _I, ctypes.POINTER(_Result)]),
     "qubo_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     "qubo_solve_batch": (_I, [_I, ctypes.POINTER(_VP), ctypes.POINTER(_I), ctypes.POINTER(_I),
                               ctypes.POINTER(_Result)]),
@@ -249,6 +251,31 @@ def solve_device(Qt, k: int = 1, stream=None):
         pairs = [(t.energy if dt == QUBO_FP32 else t.energy_i, int(t.index)) for t in top]
         return res, pairs
     return res
+
+
+def reduce_outer(Q, k: int, xf: int):
+    """Fix the first k variables to the bits of xf (the index's top k bits):
+    returns (Qr, c), the int32 QUBO of the other n - k variables and the
+    constant, with E(xf, x_r) = c + E_Qr(x_r)."""
+    Qc, dt = _as_q(Q)
+    if dt != QUBO_INT32:
+        raise TypeError("reduce_outer takes an int32 matrix")
+    n = Qc.shape[0]
+    Qr = np.zeros((max(n - int(k), 0),) * 2, dtype=np.int32)
+    c = ctypes.c_int64()
+    _check(lib().qubo_reduce_outer(Qc.ctypes.data, n, int(k), ctypes.c_uint64(int(xf)),
+                                   Qr.ctypes.data, ctypes.byref(c)))
+    return Qr, c.value
+
+
+def solve_outer(Q, k: int) -> Result:
+    """Solve an int32 QUBO of up to 64 variables as the batch of its 2^k
+    outer-bit reductions."""
+    Qc, dt = _as_q(Q)
+    n = Qc.shape[0]
+    out = _Result()
+    _check(lib().qubo_solve_outer(Qc.ctypes.data, n, dt, int(k), ctypes.byref(out)))
+    return _result(out, n)
 
 
 def solve_noalloc(Q, stream=None) -> Result:

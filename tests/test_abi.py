@@ -207,3 +207,42 @@ def test_header_is_plain_c(tmp_path):
                    "  (void)r; (void)c; (void)e; return (int)sizeof(qubo_options_t) == 32 ? 0 : 1; }\n")
     subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-fsyntax-only",
                     "-I", os.path.join(ROOT, "include"), str(src)], check=True)
+
+
+@pytest.mark.parametrize("n,k,seed", [(9, 3, 1), (11, 1, 2), (12, 5, 3)])
+def test_outer_reduction_identity(orc, n, k, seed):
+    """E(x_f, x_r) = c(x_f) + E_Qr(x_r) for every outer assignment and every
+    x_r, by the oracle's direct energy of both sides (full matrix input, so
+    the fold is exercised); and on upper-triangular input Qr is the paper's
+    Q_rr + diag(x_f Q_fr)."""
+    rng = np.random.default_rng(seed)
+    Q = rng.integers(-50, 51, (n, n)).astype(np.int32)
+    m = n - k
+    for xf in range(1 << k):
+        Qr, c = q.reduce_outer(Q, k, xf)
+        assert np.all(np.tril(Qr, -1) == 0)
+        for xr in range(1 << m):
+            assert orc.energy(Q, (xf << m) | xr) == c + orc.energy(Qr, xr)
+    U = np.triu(Q)
+    for xf in (0, (1 << k) - 1, 1 % (1 << k)):
+        x_f = np.array([(xf >> (k - 1 - i)) & 1 for i in range(k)], dtype=np.int64)
+        Qr, c = q.reduce_outer(U, k, xf)
+        want = U[k:, k:].astype(np.int64) + np.diag(x_f @ U[:k, k:].astype(np.int64))
+        assert np.array_equal(Qr, want)
+        assert c == int(x_f @ U[:k, :k].astype(np.int64) @ x_f)
+
+
+def test_outer_reduction_arguments():
+    Q = inputs.uniform_int(10, -9, 9, 1)
+    for bad in (dict(k=0, xf=0), dict(k=10, xf=0), dict(k=3, xf=8)):
+        with pytest.raises(q.QuboError) as e:
+            q.reduce_outer(Q, **bad)
+        assert e.value.status == -1
+    big = np.zeros((4, 4), dtype=np.int32)
+    big[0, 3] = 2 ** 31 - 1
+    big[1, 3] = 2 ** 31 - 1        # x_0 = x_1 = 1 puts 2^32 - 2 on Qr's diagonal
+    with pytest.raises(q.QuboError) as e:
+        q.reduce_outer(big, 2, 3)
+    assert e.value.status == -2
+    with pytest.raises(TypeError):
+        q.reduce_outer(Q.astype(np.float32), 2, 0)
