@@ -423,8 +423,9 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                 for (int j = 0; j < MC; j++) E[j] += trow(M, v)[j * kWave + ulane];
             }
         }
-        // F: field of every prefix variable from the non-low ones (levels >= 4,
-        // variables 0..A-5), plus its diagonal; one lane per variable.
+        // F: field of every prefix variable from the non-low ones (levels >=
+        // kLowLevels, variables 0..A-1-kLowLevels), plus its diagonal; one
+        // lane per variable.
         const int32_t diagl = lane < A ? Tm[lane * nT + lane] : 0;   // T[l][l], lane l < A
         int32_t F = diagl;
         for (int w = 0; w <= A - 1 - kLowLevels; w++)
