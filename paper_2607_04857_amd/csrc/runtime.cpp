@@ -449,7 +449,7 @@ qubo_status_t solve_planned(qrt::Job &job, hipStream_t stream, int waves_per_cu,
     if (es != hipSuccess) return qrt::device_error("hipStreamSynchronize", es);
     if (ef != hipSuccess) return qrt::device_error("hipFreeAsync", ef);
     if (job.dq) {
-        // the device preparation's verdict on the input, as the host planner's
+        // the device preparation's outcome for the input, as the host planner's
         switch (prep.status) {
         case 0: break;
         case qk::kPrepOverflow:
