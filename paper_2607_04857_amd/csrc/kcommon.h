@@ -67,6 +67,39 @@ __device__ __forceinline__ int32_t tree_min(const int32_t *e)
     }
 }
 
+// Minimum of the 2N energies packed in E[0..N) (two biased 16-bit halves per
+// word, the tier-4 layout): packed 16-bit minima level by level
+// (v_pk_min_u16; the biased halves compare as unsigned), then the smaller
+// half, unbiased.
+using u16x2 = unsigned short __attribute__((ext_vector_type(2)));
+template <int N>
+__device__ __forceinline__ u16x2 pk_tree_min(const u16x2 *e)
+{
+    if constexpr (N == 1) {
+        return e[0];
+    } else {
+        constexpr int H = N / 2;
+        u16x2 t[H + N % 2];
+        static_for<0, H>([&](auto gc) {
+            constexpr int g = decltype(gc)::value;
+            t[g] = __builtin_elementwise_min(e[2 * g], e[2 * g + 1]);
+        });
+        if constexpr (N % 2) t[H] = e[N - 1];
+        return pk_tree_min<H + N % 2>(t);
+    }
+}
+template <int N>
+__device__ __forceinline__ int32_t tree_min_packed(const int32_t *e)
+{
+    u16x2 w[N];
+    static_for<0, N>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        w[j] = __builtin_bit_cast(u16x2, e[j]);
+    });
+    const uint32_t x = __builtin_bit_cast(uint32_t, pk_tree_min<N>(w));
+    return int32_t(min(x & 0xffffu, x >> 16)) - kPackBias;
+}
+
 // Wave-wide minimum: DPP butterflies inside each row of 16 lanes, then the
 // four row results through the scalar unit.
 __device__ __forceinline__ int32_t wave_min(int32_t v)

@@ -90,10 +90,12 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
     // M_int[v][s] = sum over the set suffix bits t of s of T[v][A + t]
     // (Sec. II-C; bit t of the suffix row is (s >> (B-1-t)) & 1), as the sum
     // of two partial sums built first in LDS: part[v][s & 31] over the five
-    // lowest bits of s and part[v][32 + (s >> 5)] over the others.
-    __shared__ int32_t part[kMaxPrefixRows][64];
-    for (uint32_t e = threadIdx.x; e < uint32_t(A) * 64u; e += blockDim.x) {
-        const int v = int(e / 64u), x = int(e % 64u);
+    // lowest bits of s and part[v][32 + (s >> 5)] over the others (B <= 11).
+    constexpr int kPartW = 32 + 64;
+    __shared__ int32_t part[kMaxPrefixRows][kPartW];
+    const uint32_t pw = 32u + (NS >> 5);
+    for (uint32_t e = threadIdx.x; e < uint32_t(A) * pw; e += blockDim.x) {
+        const int v = int(e / pw), x = int(e % pw);
         int32_t acc = 0;
         if (x < 32) {
             for (int u = 0; u < 5; u++)
@@ -106,24 +108,36 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
         part[v][x] = acc;
     }
     __syncthreads();
-    // rows A..2A-1 hold -M_int: a flip whose direction is known only at
-    // run time then adds one row or the other, without a branch
-    for (uint32_t e = tid; e < uint32_t(A) * NS; e += stride) {
-        const int v = int(e >> B);
-        const uint32_t s = e & (NS - 1);
-        const int32_t m = part[v][s & 31u] + part[v][32u + (s >> 5)];
-        I.M[e] = m;
-        I.M[uint32_t(A) * NS + e] = -m;
-    }
+    auto mval = [&](int v, uint32_t s) { return part[v][s & 31u] + part[v][32u + (s >> 5)]; };
     // E_s(U_B)[s] = sum_{t <= u, both set} T[A+t][A+u] (Sec. III-A, step 2)
-    for (uint32_t s = tid; s < NS; s += stride) {
+    auto esuf = [&](uint32_t s) {
         int32_t acc = 0;
         for (int t = 0; t < B; t++) {
             if (!((s >> (B - 1 - t)) & 1u)) continue;
             for (int u = t; u < B; u++)
                 if ((s >> (B - 1 - u)) & 1u) acc += T[(A + t) * n + A + u];
         }
-        I.EB[s] = acc;
+        return acc;
+    };
+    // rows A..2A-1 hold -M_int: a flip whose direction is known only at
+    // run time then adds one row or the other, without a branch.  Packed:
+    // word c of a row is m(c) + m(c + NW) 2^16 and its negation the
+    // negated word (both mod 2^32, the packed map being additive).
+    const int lw = I.packed ? B - 1 : B;
+    const uint32_t NW = 1u << lw;   // words per row
+    for (uint32_t e = tid; e < uint32_t(A) * NW; e += stride) {
+        const int v = int(e >> lw);
+        const uint32_t c = e & (NW - 1);
+        uint32_t m = uint32_t(mval(v, c));
+        if (I.packed) m += uint32_t(mval(v, c + NW)) << 16;
+        I.M[e] = int32_t(m);
+        I.M[uint32_t(A) * NW + e] = int32_t(0u - m);
+    }
+    for (uint32_t c = tid; c < NW; c += stride) {
+        if (I.packed)
+            I.EB[c] = int32_t(uint32_t(esuf(c) + kPackBias) + (uint32_t(esuf(c + NW) + kPackBias) << 16));
+        else
+            I.EB[c] = esuf(c);
     }
     // prefix couplings, one lane per variable
     for (uint32_t e = tid; e < uint32_t(A) * kWave; e += stride) {
@@ -156,8 +170,9 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
     constexpr int NQ = 3 * kPatterns;
     __shared__ int32_t red[256 / kWave][NQ];
     __shared__ int32_t c2s[NQ];
-    int32_t mcol[4][kLowLevels + 1];   // M rows of levels 0..kLowLevels at this thread's columns
-    for (int k = 0; k < 4; k++) {
+    constexpr int kCols = 2048 / 256;  // columns per thread (B <= 11)
+    int32_t mcol[kCols][kLowLevels + 1];   // M rows of levels 0..kLowLevels at this thread's columns
+    for (int k = 0; k < kCols; k++) {
         const uint32_t col = threadIdx.x + 256u * uint32_t(k);
         for (int t = 0; t <= kLowLevels; t++)
             mcol[k][t] = col < NS ? part[A - 1 - t][col & 31u] + part[A - 1 - t][32u + (col >> 5)] : 0;
@@ -169,7 +184,7 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
         const int o = tab == 0 ? oo : kPatterns + oo;
         const int pat = (o ^ (o >> 1)) & (kPatterns - 1);
         int32_t mn = INT32_MAX;
-        for (int k = 0; k < 4; k++) {
+        for (int k = 0; k < kCols; k++) {
             if (threadIdx.x + 256u * uint32_t(k) >= NS) continue;
             int32_t v = cm * mcol[k][kLowLevels];
             for (int t = 0; t < kLowLevels; t++)
@@ -497,6 +512,11 @@ hipError_t launch_tables(const Inst *d_insts, int n_inst, int max_A, unsigned lo
 // in VGPRs, four waves per SIMD), and "3": G = 5 with levels 3 and 4 in LDS
 // (levels 0-2 in VGPRs; every flip of level 5 or above reads its signed row
 // from L2).
+bool walk_packed_exists(int mcols, int vgpr_levels)
+{
+    return mcols >= 4 && walk_variant_exists(mcols, vgpr_levels);
+}
+
 bool walk_variant_exists(int mcols, int vgpr_levels)
 {
     if (vgpr_levels == 12) return mcols == 1 || mcols == 2 || mcols == 4 || mcols == 8 || mcols == 16;

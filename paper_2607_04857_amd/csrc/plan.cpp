@@ -125,10 +125,23 @@ static qubo_status_t check_args(int n, qubo_dtype_t dtype, std::string *msg)
     return QUBO_OK;
 }
 
-static qubo_status_t plan_walk(const qubo_options_t *opt, Plan &P, std::string *msg, bool many);
+static qubo_status_t plan_walk(const qubo_options_t *opt, Plan &P, std::string *msg, bool many,
+                               bool packed_ok);
+
+int64_t suffix_sum_abs(const Plan &P, int A)
+{
+    const size_t nn = size_t(P.n);
+    int64_t s = 0;
+    for (size_t j = size_t(A); j < nn; j++)
+        for (size_t i = 0; i <= j; i++) {
+            const int64_t t = P.T[i * nn + j];
+            s += t < 0 ? -t : t;
+        }
+    return s;
+}
 
 qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_options_t *opt,
-                        Plan *out, std::string *msg, bool many)
+                        Plan *out, std::string *msg, bool many, bool packed_ok)
 {
     if (!Q || !out) {
         *msg = "null argument";
@@ -199,7 +212,7 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
         // state's energy sums at most nnz entries.
         P.eps_q = double(nnz) * std::ldexp(1.0, -p - 1);
     }
-    st = plan_walk(opt, P, msg, many);
+    st = plan_walk(opt, P, msg, many, packed_ok && dtype == QUBO_INT32);
     if (st != QUBO_OK) return st;
     *out = std::move(P);
     return QUBO_OK;
@@ -217,14 +230,17 @@ qubo_status_t make_plan_shape(int n, qubo_dtype_t dtype, const qubo_options_t *o
     Plan P;
     P.n = n;
     P.dtype = dtype;
-    st = plan_walk(opt, P, msg, false);
+    st = plan_walk(opt, P, msg, false, false);
     if (st != QUBO_OK) return st;
     *out = std::move(P);
     return QUBO_OK;
 }
 
-// The walk plan of P (n and dtype set): split, tier, row cache, items.
-static qubo_status_t plan_walk(const qubo_options_t *opt, Plan &P, std::string *msg, bool many)
+// The walk plan of P (n and dtype set; T too when packed_ok): split, tier,
+// row cache, items.  packed_ok: the packed tier may be chosen (int32 input
+// whose suffix-column sum fits, best state only).
+static qubo_status_t plan_walk(const qubo_options_t *opt, Plan &P, std::string *msg, bool many,
+                               bool packed_ok)
 {
     const int n = P.n;
     const qubo_dtype_t dtype = P.dtype;
@@ -234,16 +250,23 @@ static qubo_status_t plan_walk(const qubo_options_t *opt, Plan &P, std::string *
     const bool use_tune = !overridden && n > kDirectMaxN &&
                           tune_get(n, dtype, many ? kScopeBatch : kScopeSingle, &tuned);
 
-    int B = (opt && opt->B) ? opt->B : (use_tune ? tuned.B : kDefaultB);
-    if (opt && opt->B && (opt->B < kMinB || opt->B > kMaxB)) {
+    if (opt && (opt->tier < 0 || opt->tier > 4 || opt->tier == 3)) {
+        *msg = "option tier must be 0 (default), 1, 2 or 4";
+        return QUBO_EINVAL;
+    }
+    const bool force_pk = opt && opt->tier == 4;
+    if (opt && opt->B && !force_pk && (opt->B < kMinB || opt->B > kMaxB)) {
         *msg = "option B must be in [6, 10]";
         return QUBO_EINVAL;
     }
-    if (opt && (opt->tier < 0 || opt->tier > 2)) {
-        *msg = "option tier must be 0 (default), 1 or 2";
+    if (opt && opt->B && force_pk && (opt->B < kMinB + 3 || opt->B > kMaxB + 1)) {
+        *msg = "option B must be in [9, 11] for tier 4";
         return QUBO_EINVAL;
     }
-    const int tier = (opt && opt->tier) ? opt->tier : (use_tune ? tuned.tier : kDefaultTier);
+    // B of the int32 walk (tier 4 is then planned one suffix bit wider, the
+    // same words per lane holding two columns each)
+    int B = (opt && opt->B) ? (force_pk ? opt->B - 1 : opt->B) : (use_tune ? tuned.B : kDefaultB);
+    int tier = (opt && opt->tier && !force_pk) ? opt->tier : (use_tune ? tuned.tier : kDefaultTier);
     int vgpr_levels = (opt && opt->vgpr_levels) ? opt->vgpr_levels : (use_tune ? tuned.vgpr_levels : 0);
     if (vgpr_levels != 0 && vgpr_levels != 12 && vgpr_levels != 8 && vgpr_levels != 6 &&
         vgpr_levels != 5 && vgpr_levels != 4 && vgpr_levels != 3) {
@@ -275,10 +298,37 @@ static qubo_status_t plan_walk(const qubo_options_t *opt, Plan &P, std::string *
     // suffixes.
     if (vgpr_levels == 0) vgpr_levels = P.mcols == 16 ? 4 : 12;
     if ((vgpr_levels == 8 && P.mcols < 8) || (vgpr_levels <= 6 && vgpr_levels && P.mcols != 16)) {
-        *msg = "vgpr_levels 8 needs B = 9 or 10, vgpr_levels 3, 4, 5 and 6 need B = 10";
+        *msg = force_pk ? "tier 4: vgpr_levels 8 needs B = 10 or 11, vgpr_levels 3, 4, 5 and 6 need B = 11"
+                        : "vgpr_levels 8 needs B = 9 or 10, vgpr_levels 3, 4, 5 and 6 need B = 10";
         return QUBO_EINVAL;
     }
     P.vgpr_levels = vgpr_levels;
+
+    // Packed tier (two 16-bit chunk energies per word, one add per two
+    // states): for int32 input whose chunk energies provably fit 16 bits at
+    // the wider split, chosen by default where it applies, or forced.
+    {
+        const int Bp = B + 1, Ap = n - Bp;
+        const char *why = nullptr;
+        if (force_pk && !packed_ok)
+            why = "tier 4 needs an int32 matrix on the host and k <= 1";
+        else if (P.mcols < 4 || !variant_built(P.mcols, vgpr_levels))
+            why = "tier 4 needs B = 9, 10 or 11 with a built row cache";
+        else if (Ap < kSuper)
+            why = "tier 4 needs n - B >= 6";
+        else if (packed_ok && suffix_sum_abs(P, Ap) > kPackSumLimit)
+            why = "tier 4 needs the sum of |T_ij| over the suffix columns j >= A to be at most 32767";
+        if (force_pk && why) {
+            *msg = why;
+            return QUBO_EINVAL;
+        }
+        const bool auto_pk = !overridden && packed_ok;
+        if (!why && (force_pk || auto_pk)) {
+            P.B = Bp;
+            P.A = Ap;
+            P.tier = 4;
+        }
+    }
 
     // Work items: 2^L consecutive Gray steps each.  Default 2^14 steps (the
     // per-item set-up, about A*MC adds plus the prefix fields, stays below
@@ -296,6 +346,8 @@ static qubo_status_t plan_walk(const qubo_options_t *opt, Plan &P, std::string *
         }
     } else if (use_tune && tuned.L && !many && tuned.B == P.B) {
         L = tuned.L;
+    } else if (use_tune && tuned.L && !many && P.tier == 4 && tuned.B + 1 == P.B) {
+        L = std::min(std::max(tuned.L - 1, kSuper), P.A);   // the tuned number of items
     } else {
         L = P.A < 14 ? P.A : 14;
         // An instance sharing the GPU (batch, server) gets up to 64 items

@@ -24,6 +24,7 @@ constexpr int kMaxN = 60;
 constexpr int kDirectMaxN = 14;    // n at or below this: direct evaluation, no walk
 constexpr int64_t kIntSumLimit = (int64_t(1) << 30) - 1;   // sum |T| bound, int32 input
 constexpr double kFpScaleTarget = double(int64_t(1) << 29); // sum |T~| target, fp32 input
+constexpr int64_t kPackSumLimit = (int64_t(1) << 15) - 1;    // suffix-column sum |T|, tier 4
 
 struct Plan {
     int n = 0;
@@ -32,7 +33,8 @@ struct Plan {
     int A = 0, B = 0;      // prefix / suffix bits
     int mcols = 0;         // suffix columns per lane = 2^B / 64
     int L = 0;             // log2 Gray steps per work item
-    int tier = 0;          // 0 direct; 1: exact lane-min each step; 2: block lower bound
+    int tier = 0;          // 0 direct; 1: exact lane-min each step; 2: block lower bound;
+                           // 4: tier 2 on packed 16-bit chunk energies
     int vgpr_levels = 0;   // Gray levels whose M_int rows are VGPR-resident
     int p = 0;             // fixed-point exponent (fp32)
     double eps_q = 0.0;    // per-state quantisation bound (fp32)
@@ -73,9 +75,14 @@ bool tune_valid(const TuneEntry &e, std::string *msg);
 // Build a plan from a host Q.  Returns QUBO_OK or an error with msg set.
 // `many`: the instance shares its walk launch with others (batch, server),
 // so it needs no item-level parallelism of its own (a tuned L is then
-// ignored: it was measured for a lone instance).
+// ignored: it was measured for a lone instance).  `packed_ok`: the plan may
+// take the packed tier (4) where the input allows it (false for top-k).
 qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_options_t *opt,
-                        Plan *out, std::string *msg, bool many = false);
+                        Plan *out, std::string *msg, bool many = false, bool packed_ok = true);
+
+// Sum of |T_ij| over the columns j >= A (i <= j): a bound on |E_sd| of every
+// chunk of the split at A, which tier 4 needs within kPackSumLimit.
+int64_t suffix_sum_abs(const Plan &P, int A);
 
 // The walk plan of an instance whose values are not on the host (a lone
 // solve of a device-resident Q): as make_plan, except that T, p, eps_q and

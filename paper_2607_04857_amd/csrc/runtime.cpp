@@ -9,6 +9,7 @@
 
 static_assert(qk::kMaxVars == qplan::kMaxN, "finish kernel LDS sized for the largest n");
 static_assert(qk::kExactSumLimit == qplan::kIntSumLimit, "one int32 exactness bound");
+static_assert(qk::kPackSumLimit == qplan::kPackSumLimit, "one packed-tier bound");
 
 namespace qrt {
 
@@ -96,7 +97,9 @@ static JobOffsets compute_offsets(const Job &job, size_t *stage_bytes, size_t *b
     off = align_up(off + std::max<size_t>(1, job.groups.size()) * sizeof(unsigned long long), 256);
     for (size_t i = 0; i < ni; i++) {
         const qplan::Plan &P = job.plans[i];
-        const size_t A = P.direct ? 0 : size_t(P.A), NS = P.direct ? 0 : (size_t(1) << P.B);
+        // words per M_int row: 2^B, or 2^(B-1) packed (two columns a word)
+        const size_t A = P.direct ? 0 : size_t(P.A),
+                     NS = P.direct ? 0 : (size_t(1) << (P.tier == 4 ? P.B - 1 : P.B));
         // M_int and the prefix couplings, each followed by its negation
         o.M.push_back(off);
         off = align_up(off + 2 * A * NS * sizeof(int32_t), 256);
@@ -250,6 +253,7 @@ qubo_status_t job_bind(Job *job, void *d_mem)
         I.L = P.L;
         I.direct = P.direct ? 1 : 0;
         I.kslot = int(i);
+        I.packed = P.tier == 4 ? 1 : 0;
         I.item_begin = group_base[i];
         I.item_end = group_base[i] + (P.direct ? 0 : P.walk_items());
         item += P.direct ? 0 : P.walk_items();
@@ -539,7 +543,7 @@ qubo_status_t solve_host(const void *Q, int n, qubo_dtype_t dtype, int k, const 
     qrt::Job job;
     job.plans.resize(1);
     std::string msg;
-    st = qplan::make_plan(Q, n, dtype, opt, &job.plans[0], &msg);
+    st = qplan::make_plan(Q, n, dtype, opt, &job.plans[0], &msg, false, k <= 1);
     if (st != QUBO_OK) {
         qrt::set_error(msg);
         return st;

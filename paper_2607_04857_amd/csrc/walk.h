@@ -35,6 +35,11 @@ __device__ __forceinline__ int32_t wave_min_bcast(int32_t v)
 //         lm0 against an upper bound of its 32 thresholds (one vector
 //         compare); only when a lane passes are W0 and the exact thresholds
 //         formed and tested, step by step.
+// TIER 4: tier 2 on the packed layout: each of the MC words of a lane holds
+//         two chunk energies (columns c and c + 2^(B-1) of the chunk), so one
+//         32-bit add per word and step moves two states (Eq.
+//         incremental_update at 16-bit precision); only the lane minimum
+//         differs (packed 16-bit minima, then the unbiased smaller half).
 // Resident waves per SIMD each variant is register-allocated for: the full
 // 12-level row cache fits 256 VGPRs (2 waves); the 8- and 6-level caches
 // leave room for a third (MC=16) or a fourth (MC=8) wave.
@@ -286,7 +291,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
     const Inst *__restrict__ insts, int n_inst, uint64_t total_items,
     unsigned long long *__restrict__ counter, const int32_t *__restrict__ kall, TopkWalk tk)
 {
-    static_assert(TIER >= 1 && TIER <= 3, "tier");
+    static_assert(TIER >= 1 && TIER <= 4, "tier");
     static_assert(G >= kLowLevels && G <= kMaxVgprLevels, "VGPR-resident levels");
     // steps per bound-test segment: tier 3's looser threshold takes the
     // exact path more often, where shorter segments and SGPR thresholds pay
@@ -296,6 +301,11 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
     const uint32_t ulane = threadIdx.x;
     // row v of a lane-major [rows][MC*64] table: uniform base pointer
     auto trow = [](const gint32 *t, int v) { return t + size_t(v) * (MC * kWave); };
+    // this lane's chunk minimum (tier 4: over both halves of every word)
+    auto lane_min = [](const int32_t(&e)[MC]) {
+        if constexpr (TIER == 4) return tree_min_packed<MC>(e);
+        else return tree_min<MC>(e);
+    };
     // LR: rows of levels 3 and 4 after the (tier-3) list in dynamic LDS
     int32_t *const ldsR = reinterpret_cast<int32_t *>(
         reinterpret_cast<char *>(tk_lds) + lds_rows_offset(TIER, tk.k));
@@ -647,7 +657,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
             const uint32_t nsb = uint32_t(sbEnd - sb0);
             for (uint32_t ks = 0; ks < nsb; ks++) {
                 const uint64_t sb = sb0 + ks;
-                lm0 = tree_min<MC>(E);
+                lm0 = lane_min(E);
                 tab2 = 0;
                 // NSEG segments of SEG steps (tier 2: the two halves around
                 // the level-5 flip), each with (cold) or without the per-step
@@ -726,7 +736,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                                 if (W0 <= tp) {
                                     const int32_t thr =
                                         tp + kall[kbase + (3 + tab2) * kPatterns + (o & (kPatterns - 1))];
-                                    candidate(tree_min<MC>(E), thr, (sb << kSuperLog) | uint64_t(o));
+                                    candidate(lane_min(E), thr, (sb << kSuperLog) | uint64_t(o));
                                 }
                                 step_flip(oc);
                             });
@@ -790,6 +800,11 @@ static hipError_t launch_walk_g(const WalkLaunch &w)
         hipLaunchKernelGGL((walk_kernel<MC, G, 2, LR>), dim3(w.waves), dim3(kWave),
                            (walk_lds_bytes<MC, G, LR>(2, 0)), w.stream, w.insts, w.n_inst,
                            w.total_items, w.counter, w.k, none);
+    } else if (w.tier == 4 && MC >= 4) {
+        if constexpr (MC >= 4)
+            hipLaunchKernelGGL((walk_kernel<MC, G, 4, LR>), dim3(w.waves), dim3(kWave),
+                               (walk_lds_bytes<MC, G, LR>(4, 0)), w.stream, w.insts, w.n_inst,
+                               w.total_items, w.counter, w.k, none);
     } else if (w.tier == 3) {
         if (!w.tk || w.tk->k < 2 || w.n_inst != 1) return hipErrorInvalidValue;
         hipLaunchKernelGGL((walk_kernel<MC, G, 3, LR>), dim3(w.waves), dim3(kWave),
@@ -805,13 +820,18 @@ template <int MC, int G, bool LR = false>
 static int occupancy_g(int tier, int topk_k)
 {
     int blocks = 0;
-    hipError_t e;
+    hipError_t e = hipErrorInvalidValue;
     if (tier == 3)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, G, 3, LR>, kWave,
                                                          walk_lds_bytes<MC, G, LR>(3, topk_k));
     else if (tier == 2)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, G, 2, LR>, kWave,
                                                          walk_lds_bytes<MC, G, LR>(2, 0));
+    else if (tier == 4 && MC >= 4) {
+        if constexpr (MC >= 4)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, G, 4, LR>, kWave,
+                                                             walk_lds_bytes<MC, G, LR>(4, 0));
+    }
     else
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, G, 1, LR>, kWave,
                                                          walk_lds_bytes<MC, G, LR>(1, 0));

@@ -68,6 +68,25 @@ def edge_int(n: int, total: int, seed: int) -> np.ndarray:
     return Q.astype(np.int32)
 
 
+def suffix_edge_int(n: int, a: int, total: int, sign: int, seed: int,
+                    lo: int = -1000, hi: int = 1000) -> np.ndarray:
+    """Upper-triangular int32 Q whose entries in columns j >= a have
+    sum |Q_ij| == total, all of sign ``sign`` (+1 or -1; 0: random signs);
+    the entries of columns j < a are uniform in [lo, hi]."""
+    rng = np.random.default_rng(seed)
+    Q = np.triu(rng.integers(lo, hi, size=(n, n), endpoint=True, dtype=np.int64))
+    Q[:, a:] = 0
+    iu = [(i, j) for j in range(a, n) for i in range(j + 1)]
+    w = rng.random(len(iu)) + 0.05
+    mag = np.floor(w / w.sum() * total).astype(np.int64)
+    mag[rng.choice(len(iu), size=int(total - mag.sum()), replace=False)] += 1
+    sg = rng.choice([-1, 1], size=len(iu)) if sign == 0 else np.full(len(iu), sign)
+    for (i, j), m, s in zip(iu, mag, sg):
+        Q[i, j] = s * m
+    assert int(np.abs(Q[:, a:]).sum()) == total
+    return Q.astype(np.int32)
+
+
 def full_int(n: int, lo: int, hi: int, seed: int) -> np.ndarray:
     """Dense int32 Q with BOTH triangles populated (exercises the fold)."""
     rng = np.random.default_rng(seed)

@@ -95,8 +95,15 @@ static int run_plan()
             if (P.direct) {
                 CHECK(n <= qplan::kDirectMaxN);
             } else {
-                CHECK(P.A + P.B == n && P.B >= 6 && P.B <= 10 && P.L >= 5 && P.L <= P.A);
+                CHECK(P.A + P.B == n && P.B >= 6 && P.B <= (P.tier == 4 ? 11 : 10) && P.L >= 6 &&
+                      P.L <= P.A);
                 CHECK(P.items == (uint64_t(1) << (P.A - P.L)));
+                // the packed tier only where every chunk energy fits 16 bits
+                if (P.tier == 4)
+                    CHECK(!fp && P.B >= 9 && qplan::suffix_sum_abs(P, P.A) <= qplan::kPackSumLimit);
+                else
+                    CHECK(fp || P.B < 8 || P.A - 1 < qplan::kSuper ||
+                          qplan::suffix_sum_abs(P, P.A - 1) > qplan::kPackSumLimit);
             }
             if (kind == 2) {   // one more unit of |T| is refused
                 int32_t &e = qi[size_t(n - 1) * n + (n - 1)];

@@ -39,11 +39,65 @@ def test_version_and_last_error():
 
 def test_plan_fold_identity_on_upper_triangular():
     Q = inputs.uniform_int(20, -100, 100, 1)
-    info = q.plan_info(Q)
+    info = q.plan_info(Q, tier=2)
     assert np.array_equal(info["T"], Q)
     assert info["sum_abs_t"] == int(np.abs(Q.astype(np.int64)).sum())
     assert info["A"] + info["B"] == 20 and info["B"] == 10
     assert info["items"] == 2 ** (info["A"] - info["L"])
+
+
+def _suffix_sum(T, A):
+    return int(np.abs(T.astype(np.int64)[:, A:]).sum())
+
+
+def test_packed_tier_eligibility():
+    """Tier 4 (two 16-bit chunk energies per word) is planned one suffix bit
+    wider than the int32 walk, and only where the sum of |T_ij| over the
+    suffix columns bounds every chunk energy within 16 bits."""
+    # n = 24, U[-100, 100]: eligible; forced and default plans agree
+    Q = inputs.uniform_int(24, -100, 100, 1)
+    f = q.plan_info(Q, tier=4)
+    assert (f["tier"], f["B"], f["A"]) == (4, 11, 13)
+    assert _suffix_sum(f["T"], f["A"]) <= 32767
+    d = q.plan_info(Q)
+    assert d["tier"] in (1, 2, 4) and d["A"] + d["B"] == 24
+    # forced widths: B in [9, 11] for tier 4
+    assert q.plan_info(Q, tier=4, B=10)["B"] == 10
+    assert q.plan_info(Q, tier=4, B=9, vgpr_levels=12)["B"] == 9
+    for bad in (dict(tier=4, B=8), dict(tier=4, B=12), dict(tier=3)):
+        with pytest.raises(q.QuboError) as e:
+            q.plan_info(Q, **bad)
+        assert e.value.status == -1
+    # the headline instance's suffix sum is far above the bound: int32 walk
+    H = inputs.uniform_int(44, -10000, 10000, 4)
+    assert q.plan_info(H)["tier"] == 2
+    with pytest.raises(q.QuboError):
+        q.plan_info(H, tier=4)
+    # float32 input never packs
+    F = inputs.normal_fp32(24, 3)
+    assert q.plan_info(F)["tier"] != 4
+    with pytest.raises(q.QuboError):
+        q.plan_info(F, tier=4)
+    # too few prefix bits for the wider split
+    with pytest.raises(q.QuboError):
+        q.plan_info(inputs.uniform_int(16, -100, 100, 2), tier=4)
+
+
+@pytest.mark.parametrize("sign", [1, -1, 0])
+def test_packed_tier_bound_is_exact(sign):
+    """Suffix-column sum 32767 plans tier 4; 32768 falls back to the int32
+    walk (forced: refused)."""
+    n, B = 22, 11
+    Q = inputs.suffix_edge_int(n, n - B, 32767, sign, 30 + sign)
+    info = q.plan_info(Q, tier=4)
+    assert (info["tier"], info["A"]) == (4, n - B)
+    assert _suffix_sum(info["T"], n - B) == 32767
+    Q2 = inputs.suffix_edge_int(n, n - B, 32768, sign, 30 + sign)
+    assert _suffix_sum(q.plan_info(Q2, tier=2)["T"], n - B) == 32768
+    with pytest.raises(q.QuboError) as e:
+        q.plan_info(Q2, tier=4)
+    assert e.value.status == -1
+    assert q.plan_info(Q2)["tier"] != 4
 
 
 def test_plan_fold_moves_lower_triangle_up():

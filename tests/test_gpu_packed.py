@@ -1,0 +1,153 @@
+"""GPU parity of the packed walk (tier 4: two 16-bit chunk energies per
+32-bit word, Sec. IV-B "Data types") against the CPU oracle.
+
+Every int32 result must equal the oracle's (E*, lowest index) exactly.  The
+edge cases put the chunk energies at the ends of the 16-bit range: a
+suffix-column sum |T| of exactly 32767 with every suffix entry positive
+(E_sd reaches +32767), negative (-32767) or mixed.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from conftest import GOLDEN
+from paper_2607_04857_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def q():
+    import paper_2607_04857_amd as q
+    q.lib()
+    return q
+
+
+def _check(q, orc, Q, tier=4, **kw):
+    got = q.solve(Q, tier=tier, **kw)
+    exp = orc.solve(Q, k=1)[0]
+    print(f"n={Q.shape[0]} tier={tier} {kw} got=({got.energy_i},{got.index}) exp={exp} "
+          f"plan=(A={got.A},B={got.B},L={got.L},tier={got.tier},G={got.vgpr_levels})", flush=True)
+    assert (got.energy_i, got.index) == exp
+    assert got.states == 2 ** Q.shape[0]
+    return got
+
+
+@pytest.mark.parametrize("n", [17, 18, 20, 23, 26])
+def test_packed_sizes(q, orc, n):
+    got = _check(q, orc, inputs.uniform_int(n, -100, 100, 4000 + n))
+    assert got.tier == 4 and got.B == 11 and got.A == n - 11
+
+
+@pytest.mark.parametrize("B,G", [(11, 4), (11, 3), (11, 5), (11, 6), (11, 8), (11, 12),
+                                 (10, 8), (10, 12), (9, 12)])
+@pytest.mark.parametrize("L", [6, 9, 0])
+def test_packed_variants(q, orc, B, G, L):
+    Q = inputs.uniform_int(23, -300, 300, 79)
+    got = _check(q, orc, Q, B=B, L=L, vgpr_levels=G)
+    assert (got.tier, got.B, got.vgpr_levels) == (4, B, G)
+
+
+@pytest.mark.parametrize("sign", [1, -1, 0])
+@pytest.mark.parametrize("n", [19, 24])
+def test_packed_16bit_range_edge(q, orc, n, sign):
+    """Suffix-column sum 32767: the largest input the packed layout takes;
+    with all suffix entries of one sign some chunk energy reaches +-32767."""
+    Q = inputs.suffix_edge_int(n, n - 11, 32767, sign, 50 + n + sign)
+    got = _check(q, orc, Q)
+    assert got.tier == 4
+
+
+def test_packed_ties(q, orc):
+    _check(q, orc, np.zeros((18, 18), dtype=np.int32))
+    rng = np.random.default_rng(6)
+    d = rng.integers(-3, 3, size=21, endpoint=True)
+    d[::3] = 0
+    _check(q, orc, np.diag(d).astype(np.int32))
+    _check(q, orc, -np.ones((19, 19), dtype=np.int32) * np.tri(19, 19, dtype=np.int32).T)
+
+
+def _gray(c):
+    return c ^ (c >> 1)
+
+
+def test_packed_item_ranges(q, orc):
+    """Restricted item ranges start from no shared best (the thresholds
+    start at the no-energy sentinel): each range equals the oracle over its
+    contiguous index span."""
+    Q = inputs.uniform_int(30, -100, 100, 81)
+    info = q.plan_info(Q, tier=4, L=9)
+    A, B, L, items = info["A"], info["B"], info["L"], info["items"]
+    assert (info["tier"], A, B, L) == (4, 19, 11, 9)
+    span = 1 << (L + B)
+    for c0 in (0, 7, items - 3):
+        got = q.solve(Q, tier=4, L=9, item_first=c0, item_count=3)
+        exp = min(orc.solve_range(Q, _gray(c) * span, span, k=1)[0] for c in range(c0, c0 + 3))
+        print(f"items [{c0}, {c0 + 3}): {got.energy_i} @ {got.index} (oracle {exp})", flush=True)
+        assert (got.energy_i, got.index) == exp
+
+
+def _golden():
+    with open(os.path.join(GOLDEN, "oracle_results.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", ["n24_int_u100_s1", "n33_int_u100_s12"])
+def test_packed_stored_oracle_results(q, name):
+    """The stored oracle answers of the U[-100, 100] instances (the n = 24
+    one is the small single-instance workload) in the default plan, which
+    packs them, and in forced tier 4."""
+    e = _golden()[name]
+    Q = getattr(inputs, e["generator"])(**e["kwargs"])
+    for kw in ({}, {"tier": 4}):
+        got = q.solve(Q, **kw)
+        print(name, kw, got.energy_i, got.index, e["best"], got.tier, f"{got.kernel_ms:.3f} ms",
+              flush=True)
+        assert got.tier == 4
+        assert [got.energy_i, got.index] == e["best"]
+
+
+def test_packed_planted_n40(q, orc):
+    """2^40 states with a planted unique ground state, small entries."""
+    Q, xstar = inputs.planted(40, -20, 20, 12)
+    got = q.solve(Q, tier=4)
+    istar = orc.index_of(xstar)
+    print("planted40", got.energy_i, got.index, istar, got.tier, f"{got.kernel_ms:.1f} ms",
+          flush=True)
+    assert got.tier == 4
+    assert got.index == istar and got.energy_i == orc.energy(Q, istar)
+
+
+def test_packed_matches_int32_walk(q):
+    """The same instance through tier 4 and tier 2: equal answers (n = 34,
+    beyond the oracle's quick range)."""
+    Q = inputs.uniform_int(34, -100, 100, 91)
+    a = q.solve(Q, tier=4)
+    b = q.solve(Q, tier=2)
+    print("n34", a.energy_i, a.index, a.kernel_ms, b.energy_i, b.index, b.kernel_ms, flush=True)
+    assert a.tier == 4 and b.tier == 2
+    assert (a.energy_i, a.index) == (b.energy_i, b.index)
+
+
+def test_packed_in_batch(q, orc):
+    """A batch mixing packable instances (U[-100, 100]) with ones that are
+    not (U[-10^4, 10^4]): each result equals the oracle, and the packable
+    ones ran tier 4."""
+    Qs = []
+    for i, n in enumerate([18, 20, 21, 22, 24, 19, 23, 20]):
+        lo = -10000 if i % 3 == 2 else -100
+        Qs.append(inputs.uniform_int(n, lo, -lo, 600 + i))
+    b = q.Batch(Qs)
+    b.run()
+    res = b.results()
+    for Q, r in zip(Qs, res):
+        exp = orc.solve(Q, k=1)[0]
+        packable = int(np.abs(Q).max()) <= 100
+        print(Q.shape[0], packable, r.tier, (r.energy_i, r.index), exp, flush=True)
+        assert (r.energy_i, r.index) == exp
+        if not packable:
+            assert r.tier != 4
+    assert any(r.tier == 4 for r in res)
+    b.close()

@@ -85,7 +85,7 @@ def test_k1_and_k0_unchanged(orc):
     for k in (0, 1):
         r = q.solve(Q, k=k)
         r = r[0] if isinstance(r, tuple) else r
-        assert (r.energy_i, r.index) == (E, idx) and r.tier == 2
+        assert (r.energy_i, r.index) == (E, idx) and r.tier in (2, 4)   # no list walk
 
 
 def test_full_size_properties(orc):

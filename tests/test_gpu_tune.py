@@ -40,6 +40,18 @@ def _check(orc, Q, r):
         check_fp32(orc, Q, r, E, idx)
 
 
+def _base(r):
+    """(B, tier, vgpr_levels) of the int32 plan a result ran: a packed
+    (tier-4) result is its plan one suffix bit wider, so its tier is
+    reported as None (the tuned tier is not observable)."""
+    return (r.B - 1, None, r.vgpr_levels) if r.tier == 4 else (r.B, r.tier, r.vgpr_levels)
+
+
+def _same_plan(r, e):
+    b = _base(r)
+    return (b[0], b[2]) == (e["B"], e["vgpr_levels"]) and b[1] in (None, e["tier"])
+
+
 def test_autotune_writes_cache_and_drives_solves(q, orc, tmp_path):
     path = str(tmp_path / "tune.json")
     won = q.autotune(20, 22, "int32", reps=1, cache_path=path)
@@ -54,7 +66,7 @@ def test_autotune_writes_cache_and_drives_solves(q, orc, tmp_path):
         assert q.tune_lookup(e["n"]) == e
         Q = inputs.uniform_int(e["n"], -1000, 1000, 40 + e["n"])
         r = q.solve(Q)
-        assert (r.B, r.tier, r.vgpr_levels) == (e["B"], e["tier"], e["vgpr_levels"])
+        assert _same_plan(r, e)
         _check(orc, Q, r)
         print(f"tuned n={e['n']}: {e}", flush=True)
     # a second run merges into the same file
@@ -78,7 +90,7 @@ def test_batch_with_mixed_variants(q, orc):
             n = Q.shape[0]
             if n > 14:
                 e = q.tune_lookup(n, "fp32" if Q.dtype == np.float32 else "int32", "batch")
-                assert (r.B, r.tier, r.vgpr_levels) == (e["B"], e["tier"], e["vgpr_levels"])
+                assert _same_plan(r, e)
             _check(orc, Q, r)
         print(f"mixed-variant batch replay {rep}: {len(res)} ok", flush=True)
     b.close()
@@ -95,7 +107,7 @@ def test_server_with_mixed_variants(q, orc):
         r = srv.wait(t, timeout_ms=60000)
         assert r is not None
         e = q.tune_lookup(Q.shape[0], "fp32" if Q.dtype == np.float32 else "int32", "batch")
-        assert (r.B, r.tier, r.vgpr_levels) == (e["B"], e["tier"], e["vgpr_levels"])
+        assert _same_plan(r, e)
         _check(orc, Q, r)
     srv.close()
     print(f"mixed-variant server: {len(Qs)} ok", flush=True)
@@ -107,14 +119,14 @@ def test_single_scope_entries_do_not_steer_batches(q, orc):
                 {"n": 23, "B": 8, "L": 0, "tier": 1, "vgpr_levels": 12, "scope": "batch"}])
     Q22, Q23 = inputs.uniform_int(22, -100, 100, 901), inputs.uniform_int(23, -100, 100, 902)
     lone22, lone23 = q.solve(Q22), q.solve(Q23)
-    assert (lone22.B, lone22.tier) == (7, 1)
-    assert (lone23.B, lone23.vgpr_levels) == (10, 4)
+    assert (lone22.B, lone22.tier) == (7, 1)      # no packed variant at B = 7
+    assert _base(lone23)[::2] == (10, 4)
     b = q.Batch([Q22, Q23])
     b.run()
     r22, r23 = b.results()
     b.close()
-    assert (r22.B, r22.vgpr_levels) == (10, 4)
-    assert (r23.B, r23.tier) == (8, 1)
+    assert _base(r22)[::2] == (10, 4)
+    assert _base(r23)[0] == 8 and _base(r23)[1] in (None, 1)
     for Q, r in ((Q22, r22), (Q23, r23), (Q22, lone22), (Q23, lone23)):
         _check(orc, Q, r)
 
@@ -133,7 +145,7 @@ def test_batch_autotune(q, orc, tmp_path):
     b.run()
     for Q, r in zip(Qs, b.results()):
         e = q.tune_lookup(Q.shape[0], "int32", "batch")
-        assert (r.B, r.tier, r.vgpr_levels) == (e["B"], e["tier"], e["vgpr_levels"])
+        assert _same_plan(r, e)
         _check(orc, Q, r)
     b.close()
     print(f"batch-tuned: {won}", flush=True)

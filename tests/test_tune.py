@@ -18,7 +18,22 @@ def q():
 
 
 def _plan(q, n, **kw):
-    return q.plan_info(inputs.uniform_int(n, -50, 50, 900 + n), **kw)
+    # entries up to 5000: too large for the packed tier, so these plans are
+    # the int32 walk's
+    return q.plan_info(inputs.uniform_int(n, -5000, 5000, 900 + n), **kw)
+
+
+def test_tuned_entry_then_packed(q):
+    """A packable instance takes the tuned int32 plan one suffix bit wider
+    in tier 4, with the tuned number of items."""
+    q.tune_set([{"n": 30, "B": 9, "L": 12, "tier": 1, "vgpr_levels": 8}])
+    d = q.plan_info(inputs.uniform_int(30, -50, 50, 930))
+    assert (d["B"], d["A"], d["L"], d["tier"], d["vgpr_levels"]) == (10, 20, 11, 4, 8)
+    assert d["items"] == 2 ** (21 - 12)
+    # mcols 2 (B = 7) has no packed variant: the tuned int32 plan stays
+    q.tune_set([{"n": 30, "B": 7, "L": 12, "tier": 2, "vgpr_levels": 12}])
+    d = q.plan_info(inputs.uniform_int(30, -50, 50, 930))
+    assert (d["B"], d["tier"]) == (7, 2)
 
 
 def test_empty_table_gives_defaults(q):
@@ -198,5 +213,8 @@ def test_shipped_cache_loads_whole(q):
     assert kinds == {("single", "int32"), ("single", "fp32"), ("batch", "int32"), ("batch", "fp32")}
     e = q.tune_lookup(40)
     assert e is not None
-    info = q.plan_info(inputs.uniform_int(40, -100, 100, 40))
+    info = q.plan_info(inputs.uniform_int(40, -10000, 10000, 40))
     assert (info["B"], info["tier"], info["vgpr_levels"]) == (e["B"], e["tier"], e["vgpr_levels"])
+    # a packable instance of the same n: the entry one suffix bit wider
+    info = q.plan_info(inputs.uniform_int(40, -100, 100, 40))
+    assert (info["B"], info["tier"], info["vgpr_levels"]) == (e["B"] + 1, 4, e["vgpr_levels"])
