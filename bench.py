@@ -20,7 +20,15 @@ cpu_baseline     = the CPU oracle (direct evaluation) timed on this host over a
                    bounded contiguous index range of the same instance.
 batched          = 4096 instances, n ~ U{20..34}, int32 U[-100,100] (seed 5):
                    aggregate states/s of one graph replay; batched_fp32 the
-                   same with float32 N(0,1) entries (seed 6).
+                   same with float32 N(0,1) entries (seed 6).  Instances whose
+                   chunk energies fit 16 bits run the packed walk (tier 4, two
+                   states per int32 add); frac_of_valu_peak compares the rate
+                   with the peak of the batch's own mix of tiers (78.64 T
+                   states/s for an int32 walk, twice that packed).
+single_packed    = one lone solve of a dense n=44 int32 QUBO with entries
+                   U[-20,20] (seed 4), small enough for the packed walk: the
+                   same kernel template as the headline with two 16-bit chunk
+                   energies per word, against twice the int32 add peak.
 topk             = the k = 1024 lowest-energy states of a dense n = 40 int32
                    instance (U[-10000,10000], seed 3): walk (tier 3) and
                    end-to-end time.
@@ -64,7 +72,7 @@ def kernel_hash():
 def kernel_name(r):
     """Template instance of the walk kernel a plan runs (row caches "4" and
     "3" are G = 6 and G = 5 with the rows of levels 3 and 4 in LDS)."""
-    mc = 2 ** (r.B - 6)
+    mc = 2 ** (r.B - 7 if r.tier == 4 else r.B - 6)    # words per lane
     if r.vgpr_levels in (3, 4):
         return "walk_kernel<%d,%d,%d,true>" % (mc, r.vgpr_levels + 2, r.tier)
     return "walk_kernel<%d,%d,%d>" % (mc, r.vgpr_levels, r.tier)
@@ -154,12 +162,43 @@ def batched(q, steps=2, kind="int"):
         b.run()
     dt = (time.perf_counter() - t0) / steps
     states, kms = b.stats()
+    res = b.results()
     b.close()
+    # states by walk tier; the peak of this mix: int32 walks at one state per
+    # lane-op, packed (tier 4) at two, direct evaluation counted as int32
+    by_tier = {}
+    for r in res:
+        by_tier[str(r.tier)] = by_tier.get(str(r.tier), 0.0) + float(r.states)
+    peak_s = sum(st / (VALU_PEAK_OPS * (2 if t == "4" else 1)) for t, st in by_tier.items())
     what = "int32 U[-100,100], seed 5" if kind == "int" else "float32 N(0,1), seed 6"
     return {"workload": f"4096 dense QUBOs, n~U{{20..34}}, {what}",
             "plans": "autotuned (batch scope)" if tuned else "built-in",
             "states_per_s": states / dt, "ms_per_replay": dt * 1e3,
-            "states": states, "graph_ms": kms}
+            "states": states, "graph_ms": kms,
+            "states_by_tier": by_tier,
+            "mix_peak_states_per_s": states / peak_s,
+            "frac_of_valu_peak": (states / dt) / (states / peak_s)}
+
+
+def single_packed(q, steps=3):
+    """Lone solves of an n = 44 instance whose chunk energies fit 16 bits."""
+    from paper_2607_04857_amd import inputs
+    Q = inputs.uniform_int(44, -20, 20, 4)
+    r = q.solve(Q)                            # warm-up
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = q.solve(Q)
+        kms.append(r.kernel_ms)
+    dt = (time.perf_counter() - t0) / steps
+    walk_ms = sum(kms) / len(kms)
+    walk_rate = 2.0 ** 44 / (walk_ms / 1e3)
+    return {"workload": "single dense QUBO n=44, int32 U[-20,20], seed 4 (host input)",
+            "tier": r.tier, "A": r.A, "B": r.B, "L": r.L, "vgpr_levels": r.vgpr_levels,
+            "kernel": kernel_name(r), "result": [r.energy_i, r.index],
+            "ms_per_solve": dt * 1e3, "states_per_s": 2.0 ** 44 / dt, "walk_ms": walk_ms,
+            "walk_states_per_s": walk_rate, "peak_states_per_s": 2 * VALU_PEAK_OPS,
+            "frac": walk_rate / (2 * VALU_PEAK_OPS)}
 
 
 def topk(q, torch, n=40, k=1024, steps=2):
@@ -247,6 +286,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-topk", action="store_true")
+    ap.add_argument("--no-packed", action="store_true")
+    ap.add_argument("--only-packed", action="store_true",
+                    help="only the packed n=44 lone solves (profiling the packed walk alone)")
     ap.add_argument("--skip-single", action="store_true",
                     help="skip the n=44 solves (profiling the batched or served kernels alone)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -289,6 +331,9 @@ def main():
     stream = torch.cuda.current_stream()
     n = Q.shape[0]
 
+    if args.only_packed:
+        print(json.dumps({"single_packed": single_packed(q)}), flush=True)
+        return
     if args.skip_single:
         out = {}
         if not args.no_batch:
@@ -341,6 +386,8 @@ def main():
     probe, _ = q.probe_valu("add", 8, 2048)
     line["roofline"]["probe_peak"] = probe / 1e12       # measured v_add_u32 lane-ops/s
     line["roofline"]["frac_of_probe"] = achieved / probe
+    if not args.no_packed:
+        line["single_packed"] = single_packed(q)
     if not args.no_batch:
         line["batched"] = batched(q)
         line["batched_fp32"] = batched(q, kind="fp32")

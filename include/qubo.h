@@ -81,7 +81,9 @@ typedef struct {
     int L;               /* log2 Gray steps per work item                          */
     int tier;            /* 0 direct evaluation (n <= 14); 1 exact lane-min every
                             Gray step; 2 block lower bound, exact min on demand;
-                            3 tier 2's test against a top-k threshold (k > 1)  */
+                            3 tier 2's test against a top-k threshold (k > 1);
+                            4 tier 2 on packed 16-bit chunk energies, two per
+                            32-bit word (Sec. IV-B "Data types")         */
     int vgpr_levels;     /* Gray levels with VGPR-resident rows (0 when direct)    */
     uint64_t states;     /* states evaluated = 2^n                                 */
     double kernel_ms;    /* GPU time of the walk kernel (HIP events)               */
@@ -89,10 +91,18 @@ typedef struct {
 } qubo_result_t;
 
 /* Plan overrides, mainly for tests and the autotuner.  Zero-initialise for the
- * defaults.  B: suffix bits in [6, 10] (0 = default 10); L: log2 Gray steps per
- * work item in [6, A] (0 = default); tier: 0 = default, 1 or 2 to force that
- * walk tier; waves_per_cu: resident walk waves per compute unit (0 = the
- * occupancy limit); vgpr_levels: see below.
+ * defaults.  B: suffix bits in [6, 10] (0 = default 10; [9, 11] with tier 4);
+ * L: log2 Gray steps per work item in [6, A] (0 = default); tier: 0 = default,
+ * 1, 2 or 4 to force that walk tier; waves_per_cu: resident walk waves per
+ * compute unit (0 = the occupancy limit); vgpr_levels: see below.
+ * Tier 4 (packed) holds two 16-bit chunk energies in each 32-bit word, so one
+ * int32 add moves two states.  It is exact whenever S = sum of |T_ij| over
+ * the suffix columns j >= A is at most 32767 (every chunk energy then fits a
+ * signed 16-bit value), and needs int32 input given in host memory, k <= 1,
+ * n - B >= 6 and B - 7 = log2 of a built words-per-lane count (4, 8 or 16).
+ * The default plan (no override) takes it wherever that holds, one suffix
+ * bit wider than the int32 plan; forcing it where it does not hold returns
+ * QUBO_EINVAL.
  * item_first, item_count: walk only work items [item_first, item_first +
  * item_count) of the plan (item_count 0 = all).  Work item c covers the prefix
  * rows of Gray steps [c 2^L, (c+1) 2^L), which are the aligned block of rows
@@ -144,8 +154,10 @@ qubo_status_t qubo_solve_ex(const void *Q, int n, qubo_dtype_t dtype, int k,
  * (a hipStream_t; NULL = the null stream).  Q is read only on the device:
  * the fold, the int32 exactness proof and the float32 fixed-point scaling run
  * in a kernel ordered after whatever wrote dQ on that stream, with the same
- * arithmetic (and so the same plan, T, p and answer) as qubo_solve on a host
- * copy.  Returns after the result has been copied back (the stream is
+ * arithmetic (and so the same T, p and answer) as qubo_solve on a host copy.
+ * The plan is made from n and dtype alone, before any value is read, so it
+ * is qubo_solve's except that it never takes the packed tier (4), whose
+ * eligibility depends on the values.  Returns after the result has been copied back (the stream is
  * synchronised once, at the end); input errors (QUBO_EOVERFLOW,
  * QUBO_ENONFINITE) are detected on the device and reported then, after a
  * walk that skips every item. */

@@ -131,6 +131,22 @@ def test_packed_matches_int32_walk(q):
     assert (a.energy_i, a.index) == (b.energy_i, b.index)
 
 
+def test_packed_n44_bench_instance(q, orc):
+    """The packed bench leg's instance (n = 44, U[-20, 20], seed 4) in its
+    default plan (tier 4) and in the int32 walk: the same answer, whose
+    energy the oracle confirms and which no single flip improves."""
+    Q = inputs.uniform_int(44, -20, 20, 4)
+    a = q.solve(Q)
+    b = q.solve(Q, tier=2)
+    print("n44 packed", a.energy_i, a.index, a.tier, a.B, f"{a.kernel_ms:.1f} ms",
+          "int32", b.energy_i, b.index, f"{b.kernel_ms:.1f} ms", flush=True)
+    assert a.tier == 4 and a.states == 2 ** 44
+    assert (a.energy_i, a.index) == (b.energy_i, b.index)
+    assert orc.energy(Q, a.index) == a.energy_i
+    for v in range(44):
+        assert orc.energy(Q, a.index ^ (1 << v)) >= a.energy_i
+
+
 def test_packed_in_batch(q, orc):
     """A batch mixing packable instances (U[-100, 100]) with ones that are
     not (U[-10^4, 10^4]): each result equals the oracle, and the packable
