@@ -84,3 +84,23 @@ def test_resume_keeps_the_recorded_plan(tmp_path):
     d = q.checkpoint_info(f)
     assert (r.B, d["B"], d["items"]) == (whole.B, whole.B, items)
     assert (r.energy_i, r.index) == (whole.energy_i, whole.index)
+
+
+def test_packed_plan_interrupted_and_resumed(tmp_path):
+    """A packable instance: the recorded plan is the packed one (tier 4, one
+    suffix bit wider), and the resumed slices run it again."""
+    import paper_2607_04857_amd as q
+    Q = inputs.uniform_int(36, -50, 50, 37)
+    whole = q.solve(Q)
+    assert whole.tier == 4
+    f = str(tmp_path / "p36.ckpt")
+    items = q.plan_info(Q)["items"]
+    per = items // 5 + 1
+    assert q.solve_checkpointed(Q, f, items_per_slice=per, max_slices=2) is None
+    d = q.checkpoint_info(f)
+    assert (d["tier"], d["B"], d["next_item"]) == (4, whole.B, 2 * per)
+    r = q.solve_checkpointed(Q, f, items_per_slice=per)
+    print(f"n=36 packed sliced: ({r.energy_i},{r.index}) whole: ({whole.energy_i},{whole.index})",
+          flush=True)
+    assert (r.energy_i, r.index) == (whole.energy_i, whole.index)
+    assert (r.tier, r.A, r.B, r.L) == (whole.tier, whole.A, whole.B, whole.L)
