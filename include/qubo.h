@@ -96,10 +96,14 @@ typedef struct {
  * 1, 2 or 4 to force that walk tier; waves_per_cu: resident walk waves per
  * compute unit (0 = the occupancy limit); vgpr_levels: see below.
  * Tier 4 (packed) holds two 16-bit chunk energies in each 32-bit word, so one
- * int32 add moves two states.  It is exact whenever S = sum of |T_ij| over
- * the suffix columns j >= A is at most 32767 (every chunk energy then fits a
- * signed 16-bit value), and needs int32 input given in host memory, k <= 1,
- * n - B >= 6 and B - 7 = log2 of a built words-per-lane count (4, 8 or 16).
+ * int32 add moves two states.  It is exact whenever the chunk energies
+ * E_sd(s, x_p) of the split, over every prefix x_p and suffix column s, span
+ * at most 65536 consecutive values (they are then shifted by a constant c
+ * into the signed 16-bit range; the planner proves it from the sum of |T_ij|
+ * over the suffix columns j >= A, at most 32767, or from the exact extremes),
+ * and sum |T| + |c| <= 2^30 - 1.  It needs int32 input given in host memory,
+ * k <= 1, n - B >= 6 and B - 7 = log2 of a built words-per-lane count (4, 8
+ * or 16).
  * The default plan (no override) takes it wherever that holds, one suffix
  * bit wider than the int32 plan; forcing it where it does not hold returns
  * QUBO_EINVAL.
@@ -326,6 +330,10 @@ typedef struct {
     double eps_q;
     int64_t sum_abs_t;   /* sum |T~_ij| over i <= j */
     uint64_t items;      /* walk work items */
+    int pack_shift;      /* tier 4: the constant c added to every chunk energy
+                            (taken off every prefix energy) so that each fits
+                            a signed 16-bit value; 0 otherwise */
+    int reserved;
 } qubo_plan_info_t;
 qubo_status_t qubo_plan_info(const void *Q, int n, qubo_dtype_t dtype,
                              const qubo_options_t *opt, qubo_plan_info_t *info,

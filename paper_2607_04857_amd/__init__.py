@@ -63,7 +63,7 @@ class _PlanInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("A", ctypes.c_int), ("B", ctypes.c_int),
                 ("L", ctypes.c_int), ("tier", ctypes.c_int), ("direct", ctypes.c_int),
                 ("vgpr_levels", ctypes.c_int), ("p", ctypes.c_int), ("eps_q", ctypes.c_double), ("sum_abs_t", ctypes.c_int64),
-                ("items", ctypes.c_uint64)]
+                ("items", ctypes.c_uint64), ("pack_shift", ctypes.c_int), ("reserved", ctypes.c_int)]
 
 
 class _Checkpoint(ctypes.Structure):

@@ -61,9 +61,10 @@ constexpr int kMaxPrefixRows = 60 - 6;   // A = n - B <= 60 - 6
 // row word = m_lo + m_hi 2^16 (mod 2^32): the map is additive mod 2^32, so a
 // 32-bit add of a row word adds m_lo and m_hi to the two halves however the
 // intermediate carries fall, and a word decodes exactly whenever both biased
-// halves lie in [0, 2^16).  Every chunk energy E_sd is bounded by the sum of
-// |T_ij| over the suffix columns j >= A, so that sum <= kPackSumLimit makes
-// every word the walk reads decodable.
+// halves lie in [0, 2^16).  The planner proves every chunk energy E_sd + c
+// (c = Inst::pack_shift, a constant per instance) a signed 16-bit value:
+// from the sum of |T_ij| over the suffix columns (at most kPackSumLimit,
+// c = 0) or from the exact extremes of E_sd over all prefixes and columns.
 constexpr int32_t kPackBias = 1 << 15;
 constexpr int64_t kPackSumLimit = (int64_t(1) << 15) - 1;
 
@@ -104,7 +105,9 @@ struct Inst {
     int direct;            // 1: no walk, direct evaluation of all 2^n states
     int kslot;             // index of the K table in the launch's K array
     int packed;            // 1: M and EB in the packed 16-bit layout (tier 4)
-    int pad;
+    int32_t pack_shift;    // tier 4: c added to every chunk energy in EB and
+                           // taken off the prefix energy, so that every
+                           // E_sd + c is a signed 16-bit value
     uint64_t item_begin;   // this launch's walk-item range [item_begin, item_end)
     uint64_t item_end;
     uint64_t item_local0;  // the instance's own item number of launch item item_begin

@@ -134,8 +134,10 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
         I.M[uint32_t(A) * NW + e] = int32_t(0u - m);
     }
     for (uint32_t c = tid; c < NW; c += stride) {
-        if (I.packed)
-            I.EB[c] = int32_t(uint32_t(esuf(c) + kPackBias) + (uint32_t(esuf(c + NW) + kPackBias) << 16));
+        if (I.packed) {
+            const int32_t b = I.pack_shift + kPackBias;
+            I.EB[c] = int32_t(uint32_t(esuf(c) + b) + (uint32_t(esuf(c + NW) + b) << 16));
+        }
         else
             I.EB[c] = esuf(c);
     }

@@ -140,6 +140,62 @@ int64_t suffix_sum_abs(const Plan &P, int A)
     return s;
 }
 
+void chunk_energy_range(const Plan &P, int A, int64_t *lo, int64_t *hi)
+{
+    const size_t nn = size_t(P.n);
+    const int B = P.n - A;
+    const size_t NS = size_t(1) << B;
+    // E_sd(s, x_p) = E_s(s) + sum_v x_v M[v][s]; over all prefixes x_p its
+    // extremes are E_s(s) + the sums of the negative / positive M[v][s].
+    // Column s is a subset of the suffix variables (bit b <-> variable
+    // A + B-1-b); each array is filled from s with its lowest bit cleared.
+    std::vector<int64_t> es(NS, 0), neg(NS, 0), pos(NS, 0), m(NS, 0);
+    auto var = [&](size_t s) { return A + B - 1 - __builtin_ctzll(uint64_t(s)); };
+    for (size_t s = 1; s < NS; s++) {
+        const size_t r = s & (s - 1);
+        const size_t w = size_t(var(s));
+        int64_t e = es[r] + P.T[w * nn + w];
+        for (size_t q = r; q; q &= q - 1) {
+            const size_t u = size_t(var(q));
+            e += u < w ? P.T[u * nn + w] : P.T[w * nn + u];
+        }
+        es[s] = e;
+    }
+    for (int v = 0; v < A; v++) {
+        m[0] = 0;
+        for (size_t s = 1; s < NS; s++) {
+            m[s] = m[s & (s - 1)] + P.T[size_t(v) * nn + size_t(var(s))];
+            (m[s] < 0 ? neg[s] : pos[s]) += m[s];
+        }
+    }
+    int64_t l = INT64_MAX, h = INT64_MIN;
+    for (size_t s = 0; s < NS; s++) {
+        l = std::min(l, es[s] + neg[s]);
+        h = std::max(h, es[s] + pos[s]);
+    }
+    *lo = l;
+    *hi = h;
+}
+
+bool packed_shift(const Plan &P, int A, int32_t *shift)
+{
+    // every chunk energy lies in [-S, S] for S the suffix-column sum: no shift
+    if (suffix_sum_abs(P, A) <= kPackSumLimit) {
+        *shift = 0;
+        return true;
+    }
+    int64_t lo = 0, hi = 0;
+    chunk_energy_range(P, A, &lo, &hi);
+    if (hi - lo > 2 * kPackSumLimit + 1) return false;
+    // shifted chunk energies E_sd + c span [-2^15, hi - lo - 2^15]
+    const int64_t c = -(kPackSumLimit + 1) - lo;
+    // the prefix energies (and the thresholds formed from them) move by -c:
+    // they stay within the int32 bound's reach
+    if (P.sum_abs + (c < 0 ? -c : c) > kIntSumLimit) return false;
+    *shift = int32_t(c);
+    return true;
+}
+
 qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_options_t *opt,
                         Plan *out, std::string *msg, bool many, bool packed_ok)
 {
@@ -310,14 +366,15 @@ static qubo_status_t plan_walk(const qubo_options_t *opt, Plan &P, std::string *
     {
         const int Bp = B + 1, Ap = n - Bp;
         const char *why = nullptr;
+        int32_t shift = 0;
         if (force_pk && !packed_ok)
             why = "tier 4 needs an int32 matrix on the host and k <= 1";
         else if (P.mcols < 4 || !variant_built(P.mcols, vgpr_levels))
             why = "tier 4 needs B = 9, 10 or 11 with a built row cache";
         else if (Ap < kSuper)
             why = "tier 4 needs n - B >= 6";
-        else if (packed_ok && suffix_sum_abs(P, Ap) > kPackSumLimit)
-            why = "tier 4 needs the sum of |T_ij| over the suffix columns j >= A to be at most 32767";
+        else if (packed_ok && !packed_shift(P, Ap, &shift))
+            why = "tier 4 needs every chunk energy of the split within a 16-bit range (max - min <= 65535)";
         if (force_pk && why) {
             *msg = why;
             return QUBO_EINVAL;
@@ -327,6 +384,7 @@ static qubo_status_t plan_walk(const qubo_options_t *opt, Plan &P, std::string *
             P.B = Bp;
             P.A = Ap;
             P.tier = 4;
+            P.pack_shift = shift;
         }
     }
 

@@ -36,6 +36,8 @@ struct Plan {
     int tier = 0;          // 0 direct; 1: exact lane-min each step; 2: block lower bound;
                            // 4: tier 2 on packed 16-bit chunk energies
     int vgpr_levels = 0;   // Gray levels whose M_int rows are VGPR-resident
+    int32_t pack_shift = 0;   // tier 4: c added to every chunk energy (and
+                              // subtracted from every prefix energy)
     int p = 0;             // fixed-point exponent (fp32)
     double eps_q = 0.0;    // per-state quantisation bound (fp32)
     int64_t sum_abs = 0;   // sum |T| over i <= j (of the int32 matrix solved)
@@ -81,8 +83,19 @@ qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_opt
                         Plan *out, std::string *msg, bool many = false, bool packed_ok = true);
 
 // Sum of |T_ij| over the columns j >= A (i <= j): a bound on |E_sd| of every
-// chunk of the split at A, which tier 4 needs within kPackSumLimit.
+// chunk of the split at A.
 int64_t suffix_sum_abs(const Plan &P, int A);
+
+// Exact extremes, over every prefix and suffix column, of the chunk energies
+// E_sd of the split at A (P.T set).
+void chunk_energy_range(const Plan &P, int A, int64_t *lo, int64_t *hi);
+
+// Whether the split at A can run the packed tier, and the shift c that
+// centres its chunk energies: every E_sd + c must be a signed 16-bit value
+// (shift 0 when the suffix-column sum is at most kPackSumLimit, else from the
+// exact range), and P.sum_abs + |c| must stay within kIntSumLimit (the
+// prefix energies move by -c).
+bool packed_shift(const Plan &P, int A, int32_t *shift);
 
 // The walk plan of an instance whose values are not on the host (a lone
 // solve of a device-resident Q): as make_plan, except that T, p, eps_q and

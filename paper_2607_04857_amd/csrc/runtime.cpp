@@ -254,6 +254,7 @@ qubo_status_t job_bind(Job *job, void *d_mem)
         I.direct = P.direct ? 1 : 0;
         I.kslot = int(i);
         I.packed = P.tier == 4 ? 1 : 0;
+        I.pack_shift = P.tier == 4 ? P.pack_shift : 0;
         I.item_begin = group_base[i];
         I.item_end = group_base[i] + (P.direct ? 0 : P.walk_items());
         item += P.direct ? 0 : P.walk_items();
@@ -655,6 +656,8 @@ qubo_status_t qubo_plan_info(const void *Q, int n, qubo_dtype_t dtype, const qub
         info->eps_q = P.eps_q;
         info->sum_abs_t = P.sum_abs;
         info->items = P.items;
+        info->pack_shift = P.tier == 4 ? P.pack_shift : 0;
+        info->reserved = 0;
         if (T_out) std::memcpy(T_out, P.T.data(), P.T.size() * sizeof(int32_t));
         return QUBO_OK;
     } catch (...) {

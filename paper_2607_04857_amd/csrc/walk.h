@@ -443,6 +443,9 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
         // E_nl = energy of the non-low prefix bits = (sum_set F_w + T_ww) / 2
         const bool lbit = lane <= A - 1 - kLowLevels && ((row0 >> (A - 1 - lane)) & 1);
         int32_t Enl = int32_t(wave_sum64(lbit ? int64_t(F) + diagl : 0) / 2);
+        // tier 4: the chunk energies carry the instance's shift c, the
+        // prefix energy the opposite one, so every sum is the true energy
+        if constexpr (TIER == 4) Enl -= insts[cur].pack_shift;
         Enl = sread(Enl);
         int32_t H[kLowLevels];
         static_for<0, kLowLevels>([&](auto tc) {

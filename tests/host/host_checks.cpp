@@ -99,11 +99,16 @@ static int run_plan()
                       P.L <= P.A);
                 CHECK(P.items == (uint64_t(1) << (P.A - P.L)));
                 // the packed tier only where every chunk energy fits 16 bits
-                if (P.tier == 4)
-                    CHECK(!fp && P.B >= 9 && qplan::suffix_sum_abs(P, P.A) <= qplan::kPackSumLimit);
-                else
-                    CHECK(fp || P.B < 8 || P.A - 1 < qplan::kSuper ||
-                          qplan::suffix_sum_abs(P, P.A - 1) > qplan::kPackSumLimit);
+                int32_t c = 0;
+                if (P.tier == 4) {
+                    CHECK(!fp && P.B >= 9 && qplan::packed_shift(P, P.A, &c) && c == P.pack_shift);
+                    int64_t lo = 0, hi = 0;
+                    qplan::chunk_energy_range(P, P.A, &lo, &hi);
+                    CHECK(lo + c >= -32768 && hi + c <= 32767);
+                    CHECK(P.sum_abs + (c < 0 ? -int64_t(c) : int64_t(c)) <= qplan::kIntSumLimit);
+                } else {
+                    CHECK(fp || P.B < 8 || P.A - 1 < qplan::kSuper || !qplan::packed_shift(P, P.A - 1, &c));
+                }
             }
             if (kind == 2) {   // one more unit of |T| is refused
                 int32_t &e = qi[size_t(n - 1) * n + (n - 1)];

@@ -84,20 +84,95 @@ def test_packed_tier_eligibility():
 
 
 @pytest.mark.parametrize("sign", [1, -1, 0])
-def test_packed_tier_bound_is_exact(sign):
-    """Suffix-column sum 32767 plans tier 4; 32768 falls back to the int32
-    walk (forced: refused)."""
+def test_packed_tier_suffix_sum_bound(sign):
+    """Suffix-column sum 32767 plans tier 4 with no shift, whatever the
+    signs (every chunk energy lies in [-32767, 32767])."""
     n, B = 22, 11
     Q = inputs.suffix_edge_int(n, n - B, 32767, sign, 30 + sign)
     info = q.plan_info(Q, tier=4)
-    assert (info["tier"], info["A"]) == (4, n - B)
+    assert (info["tier"], info["A"], info["pack_shift"]) == (4, n - B, 0)
     assert _suffix_sum(info["T"], n - B) == 32767
-    Q2 = inputs.suffix_edge_int(n, n - B, 32768, sign, 30 + sign)
-    assert _suffix_sum(q.plan_info(Q2, tier=2)["T"], n - B) == 32768
-    with pytest.raises(q.QuboError) as e:
-        q.plan_info(Q2, tier=4)
-    assert e.value.status == -1
-    assert q.plan_info(Q2)["tier"] != 4
+
+
+def _suffix_diagonal(n, A, d, seed):
+    rng = np.random.default_rng(seed)
+    Q = np.triu(rng.integers(-1000, 1000, size=(n, n), endpoint=True)).astype(np.int64)
+    Q[:, A:] = 0
+    for t, v in enumerate(d):
+        Q[A + t, A + t] = v
+    return Q.astype(np.int32)
+
+
+@pytest.mark.parametrize("signs", ["pos", "neg", "mixed"])
+def test_packed_tier_exact_range_edge(signs):
+    """Only the suffix diagonal is set: the chunk energies then span exactly
+    the sum of |d_t|.  65535 is the widest range a 16-bit value holds: it
+    packs, with the shift that puts the lowest energy at -32768; 65536 does
+    not."""
+    n, B = 20, 11
+    A = n - B
+    for total, ok in ((65535, True), (65536, False)):
+        d = np.full(B, total // B)
+        d[0] += total - d.sum()
+        if signs == "neg":
+            d = -d
+        elif signs == "mixed":
+            d[1::2] *= -1
+        Q = _suffix_diagonal(n, A, d, 7)
+        lo = int(d[d < 0].sum())
+        if ok:
+            info = q.plan_info(Q, tier=4)
+            assert (info["tier"], info["A"]) == (4, A)
+            assert info["pack_shift"] == -32768 - lo
+            assert q.plan_info(Q)["tier"] == 4
+        else:
+            with pytest.raises(q.QuboError) as e:
+                q.plan_info(Q, tier=4)
+            assert e.value.status == -1
+            assert q.plan_info(Q)["tier"] != 4
+
+
+def _chunk_range_brute(T, A):
+    """Extremes of E_sd(s, x_p) over every prefix and suffix column, by
+    enumeration: E_sd = E(x) - E(x_p alone), from the oracle's own energy
+    definition applied to all 2^n states."""
+    n = T.shape[0]
+    B = n - A
+    idx = np.arange(1 << n, dtype=np.int64)
+    x = ((idx[:, None] >> (n - 1 - np.arange(n))[None, :]) & 1).astype(np.int64)
+    E = np.einsum("si,ij,sj->s", x, T.astype(np.int64), x)
+    xp = x.copy()
+    xp[:, A:] = 0
+    Ep = np.einsum("si,ij,sj->s", xp, T.astype(np.int64), xp)
+    esd = E - Ep
+    return int(esd.min()), int(esd.max())
+
+
+@pytest.mark.parametrize("R,seed", [(120, 1), (600, 1), (3000, 1), (3000, 2), (3300, 1),
+                                    (5000, 5)])
+def test_packed_tier_matches_brute_force_range(R, seed):
+    """Tier 4 is planned exactly when the brute-force range of the chunk
+    energies (n = 17, all 2^17 states) fits 16 bits, with the shift that
+    maps it into [-32768, 32767]."""
+    n = 17
+    Q = inputs.uniform_int(n, -R, R, 600 + seed)       # ranges 2403 ... 120639
+    T = q.plan_info(Q, tier=2)["T"]
+    A = n - 11
+    lo, hi = _chunk_range_brute(T, A)
+    fits = hi - lo <= 65535
+    if fits:
+        info = q.plan_info(Q, tier=4)
+        assert info["A"] == A
+        c = info["pack_shift"]
+        if _suffix_sum(T, A) <= 32767:
+            assert c == 0
+        else:
+            assert c == -32768 - lo
+        assert -32768 <= lo + c and hi + c <= 32767
+    else:
+        with pytest.raises(q.QuboError):
+            q.plan_info(Q, tier=4)
+
 
 
 def test_plan_fold_moves_lower_triangle_up():

@@ -67,9 +67,10 @@ def test_planted_n46_in_slices(tmp_path, orc):
 
 def test_resume_keeps_the_recorded_plan(tmp_path):
     """A tuning entry installed between two calls does not change the plan of
-    a solve already in progress: the resumed slices run the recorded one."""
+    a solve already in progress: the resumed slices run the recorded one.
+    (Entries to 10^4: the int32 walk, whose tuned B the planner takes as is.)"""
     import paper_2607_04857_amd as q
-    Q = inputs.uniform_int(36, -1000, 1000, 36)
+    Q = inputs.uniform_int(36, -10000, 10000, 36)
     whole = q.solve(Q)
     f = str(tmp_path / "n36.ckpt")
     items = q.plan_info(Q)["items"]

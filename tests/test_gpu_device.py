@@ -38,7 +38,7 @@ def _same(a, b):
 @pytest.mark.parametrize("n,seed", [(1, 1), (9, 2), (14, 3), (15, 4), (20, 5), (26, 6), (33, 7)])
 def test_int32_equals_host_and_oracle(env, orc, n, seed):
     q, torch = env
-    Q = inputs.uniform_int(n, -1000, 1000, 900 + seed)
+    Q = inputs.uniform_int(n, -10000, 10000, 900 + seed)
     dev = q.solve_device(torch.from_numpy(Q).cuda())
     host = q.solve(Q)
     print(f"n={n} device ({dev.energy_i}, {dev.index}) host ({host.energy_i}, {host.index})",
@@ -66,7 +66,7 @@ def test_lower_triangle_is_folded(env):
     """A full (not upper-triangular) matrix: the device fold adds Q_ji to Q_ij."""
     q, torch = env
     rng = np.random.default_rng(5)
-    Q = rng.integers(-500, 501, (22, 22)).astype(np.int32)
+    Q = rng.integers(-5000, 5001, (22, 22)).astype(np.int32)
     _same(q.solve_device(torch.from_numpy(Q).cuda()), q.solve(Q))
     Qf = rng.standard_normal((22, 22)).astype(np.float32)
     _same(q.solve_device(torch.from_numpy(Qf).cuda()), q.solve(Qf))
@@ -115,9 +115,9 @@ def test_input_errors_and_recovery(env):
     with pytest.raises(q.QuboError) as ef:
         q.solve_device(torch.from_numpy(inf).cuda())
     assert ef.value.status == -3
-    # (entries to 1000: a host solve of smaller ones would take the packed
+    # (entries to 10^4: a host solve of smaller ones could take the packed
     # tier, which the shape-only device plan does not)
-    ok = inputs.uniform_int(24, -1000, 1000, 11)
+    ok = inputs.uniform_int(24, -10000, 10000, 11)
     _same(q.solve_device(torch.from_numpy(ok).cuda()), q.solve(ok))
 
 
@@ -125,7 +125,7 @@ def test_stream_order(env):
     """The matrix is written by a kernel on a side stream and solved on that
     stream with no synchronisation in between."""
     q, torch = env
-    Q = inputs.uniform_int(28, -1000, 1000, 77)
+    Q = inputs.uniform_int(28, -10000, 10000, 77)
     src = torch.from_numpy(Q).cuda()
     torch.cuda.synchronize()
     s = torch.cuda.Stream()

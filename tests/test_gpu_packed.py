@@ -4,7 +4,8 @@
 Every int32 result must equal the oracle's (E*, lowest index) exactly.  The
 edge cases put the chunk energies at the ends of the 16-bit range: a
 suffix-column sum |T| of exactly 32767 with every suffix entry positive
-(E_sd reaches +32767), negative (-32767) or mixed.
+(E_sd reaches +32767), negative (-32767) or mixed, and chunk energies
+spanning exactly 65536 values, shifted so that they fill [-32768, 32767].
 """
 import json
 import os
@@ -60,6 +61,45 @@ def test_packed_16bit_range_edge(q, orc, n, sign):
     assert got.tier == 4
 
 
+def _suffix_diagonal(n, A, d, seed):
+    rng = np.random.default_rng(seed)
+    Q = np.triu(rng.integers(-1000, 1000, size=(n, n), endpoint=True)).astype(np.int64)
+    Q[:, A:] = 0
+    for t, v in enumerate(d):
+        Q[A + t, A + t] = v
+    return Q.astype(np.int32)
+
+
+@pytest.mark.parametrize("signs", ["pos", "neg", "mixed"])
+def test_packed_shifted_range_edge(q, orc, signs):
+    """Only the suffix diagonal is set, with sum |d_t| = 65535: the chunk
+    energies span exactly the 16-bit range after the instance's shift, and
+    both its ends are reached."""
+    n, B = 20, 11
+    d = np.full(B, 65535 // B)
+    d[0] += 65535 - d.sum()
+    if signs == "neg":
+        d = -d
+    elif signs == "mixed":
+        d[1::2] *= -1
+    Q = _suffix_diagonal(n, n - B, d, 8)
+    info = q.plan_info(Q, tier=4)
+    assert info["pack_shift"] == -32768 - int(d[d < 0].sum())
+    got = _check(q, orc, Q)
+    assert got.tier == 4
+
+
+@pytest.mark.parametrize("n,R,seed", [(17, 3000, 601), (24, 1000, 5), (28, 1500, 6)])
+def test_packed_shifted_random(q, orc, n, R, seed):
+    """Entries too large for the suffix-sum bound whose exact chunk-energy
+    range still fits 16 bits: packed with a nonzero shift."""
+    Q = inputs.uniform_int(n, -R, R, seed)
+    info = q.plan_info(Q, tier=4)
+    assert info["pack_shift"] != 0
+    got = _check(q, orc, Q)
+    assert got.tier == 4
+
+
 def test_packed_ties(q, orc):
     _check(q, orc, np.zeros((18, 18), dtype=np.int32))
     rng = np.random.default_rng(6)
@@ -94,11 +134,13 @@ def _golden():
         return json.load(f)
 
 
-@pytest.mark.parametrize("name", ["n24_int_u100_s1", "n33_int_u100_s12"])
+@pytest.mark.parametrize("name", ["n24_int_u100_s1", "n33_int_u100_s12", "n30_int_u1000_s10",
+                                  "n32_int_u1000_s14", "n36_int_u1000_s2"])
 def test_packed_stored_oracle_results(q, name):
-    """The stored oracle answers of the U[-100, 100] instances (the n = 24
-    one is the small single-instance workload) in the default plan, which
-    packs them, and in forced tier 4."""
+    """The stored oracle answers of the U[-100, 100] and U[-1000, 1000]
+    instances (the n = 24 one is the small single-instance workload, the
+    n = 36 one the mid-size one) in the default plan, which packs them (the
+    U[-1000, 1000] ones with a shift), and in forced tier 4."""
     e = _golden()[name]
     Q = getattr(inputs, e["generator"])(**e["kwargs"])
     for kw in ({}, {"tier": 4}):
