@@ -247,19 +247,28 @@ def serving(q, count=600, rate_hz=150.0):
         th = threading.Thread(target=submitter)
         th.start()
         th.join()
+        res = []
         for t in tickets:
-            assert srv.wait(t, timeout_ms=600000) is not None
+            res.append(srv.wait(t, timeout_ms=600000))
+            assert res[-1] is not None
         wall = time.perf_counter() - t0
         st = srv.stats()
         info = srv.info()
+        info["results"] = res
         srv.close()
         return st, info, wall
 
     reqs = mix(rate_hz)
     states = sum(2.0 ** Q.shape[0] for _, Q in reqs)
     st, info, wall = run(reqs, True)
-    sat, _, sat_wall = run(reqs, False)
+    sat, sinfo, sat_wall = run(reqs, False)
     capacity = count / sat_wall                      # requests/s at saturation
+    # the served mix's own peak: packed (tier 4) requests at two states per
+    # int32 lane-op, the others at one
+    by_tier = {}
+    for r in sinfo["results"]:
+        by_tier[str(r.tier)] = by_tier.get(str(r.tier), 0.0) + float(r.states)
+    peak_s = sum(v / (VALU_PEAK_OPS * (2 if t == "4" else 1)) for t, v in by_tier.items())
     half_rate = 0.5 * capacity
     reqs_h = mix(half_rate)
     hst, hinfo, hwall = run(reqs_h, True)
@@ -269,6 +278,8 @@ def serving(q, count=600, rate_hz=150.0):
             "offered_states_per_s": states / reqs[-1][0], "ticks": info["ticks"],
             "mem_peak_bytes": info["mem_peak"],
             "saturation_states_per_s": states / sat_wall,
+            "states_by_tier": by_tier, "mix_peak_states_per_s": states / peak_s,
+            "saturation_frac_of_mix_peak": (states / sat_wall) / (states / peak_s),
             "saturation_p50_ms": sat["p50_ms"], "saturation_p99_ms": sat["p99_ms"],
             "capacity_req_per_s": capacity,
             "half_load": {"rate_req_per_s": half_rate, "p50_ms": hst["p50_ms"],
