@@ -72,7 +72,7 @@ def kernel_hash():
 def kernel_name(r):
     """Template instance of the walk kernel a plan runs (row caches "4" and
     "3" are G = 6 and G = 5 with the rows of levels 3 and 4 in LDS)."""
-    mc = 2 ** (r.B - 7 if r.tier == 4 else r.B - 6)    # words per lane
+    mc = 2 ** (r.B - 7 if r.tier >= 4 else r.B - 6)    # words per lane
     if r.vgpr_levels in (3, 4):
         return "walk_kernel<%d,%d,%d,true>" % (mc, r.vgpr_levels + 2, r.tier)
     return "walk_kernel<%d,%d,%d>" % (mc, r.vgpr_levels, r.tier)

@@ -83,7 +83,8 @@ typedef struct {
                             Gray step; 2 block lower bound, exact min on demand;
                             3 tier 2's test against a top-k threshold (k > 1);
                             4 tier 2 on packed 16-bit chunk energies, two per
-                            32-bit word (Sec. IV-B "Data types")         */
+                            32-bit word (Sec. IV-B "Data types"); 5 tier 3
+                            on the packed layout (k > 1)                   */
     int vgpr_levels;     /* Gray levels with VGPR-resident rows (0 when direct)    */
     uint64_t states;     /* states evaluated = 2^n                                 */
     double kernel_ms;    /* GPU time of the walk kernel (HIP events)               */
@@ -102,8 +103,8 @@ typedef struct {
  * into the signed 16-bit range; the planner proves it from the sum of |T_ij|
  * over the suffix columns j >= A, at most 32767, or from the exact extremes),
  * and sum |T| + |c| <= 2^30 - 1.  It needs int32 input given in host memory,
- * k <= 1, n - B >= 6 and B - 7 = log2 of a built words-per-lane count (4, 8
- * or 16).
+ * n - B >= 6 and B - 7 = log2 of a built words-per-lane count (4, 8 or 16);
+ * with k > 1 the packed plan runs the top-k walk as tier 5.
  * The default plan (no override) takes it wherever that holds, one suffix
  * bit wider than the int32 plan; forcing it where it does not hold returns
  * QUBO_EINVAL.
@@ -136,9 +137,10 @@ typedef struct {
  * (topk may be NULL).  k > 1 (the k lowest energies, an extension the paper
  * names in Sec. VI): additionally the k lexicographically smallest
  * (E, index) pairs into topk[0..k-1], ascending (2 <= k <= 1024, k <= 2^n),
- * and out->best = topk[0].  The walk then runs tier 3 (per-wave candidate
- * lists of chunk keys; a selection of the k smallest chunks, their rescan
- * and a selection of the k smallest states finish it).  int32: exact.
+ * and out->best = topk[0].  The walk then runs tier 3, or tier 5 on the
+ * packed layout (per-wave candidate lists of chunk keys; a selection of the
+ * k smallest chunks, their rescan and a selection of the k smallest states
+ * finish it).  int32: exact.
  * float32: the k smallest scaled integer energies, reported with their
  * float64 energies and ordered by (energy, index); the i-th reported energy
  * is within out->tol of the exact i-th smallest energy.  Batches and the

@@ -294,7 +294,7 @@ qubo_status_t make_plan_shape(int n, qubo_dtype_t dtype, const qubo_options_t *o
 
 // The walk plan of P (n and dtype set; T too when packed_ok): split, tier,
 // row cache, items.  packed_ok: the packed tier may be chosen (int32 input
-// whose suffix-column sum fits, best state only).
+// whose values are on the host).
 static qubo_status_t plan_walk(const qubo_options_t *opt, Plan &P, std::string *msg, bool many,
                                bool packed_ok)
 {
@@ -368,7 +368,7 @@ static qubo_status_t plan_walk(const qubo_options_t *opt, Plan &P, std::string *
         const char *why = nullptr;
         int32_t shift = 0;
         if (force_pk && !packed_ok)
-            why = "tier 4 needs an int32 matrix on the host and k <= 1";
+            why = "tier 4 needs an int32 matrix given in host memory";
         else if (P.mcols < 4 || !variant_built(P.mcols, vgpr_levels))
             why = "tier 4 needs B = 9, 10 or 11 with a built row cache";
         else if (Ap < kSuper)

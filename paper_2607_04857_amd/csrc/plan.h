@@ -34,7 +34,9 @@ struct Plan {
     int mcols = 0;         // suffix columns per lane = 2^B / 64
     int L = 0;             // log2 Gray steps per work item
     int tier = 0;          // 0 direct; 1: exact lane-min each step; 2: block lower bound;
-                           // 4: tier 2 on packed 16-bit chunk energies
+                           // 4: tier 2 on packed 16-bit chunk energies;
+                           // 3 / 5: top-k lists on the int32 / packed walk
+                           // (set by the top-k planning)
     int vgpr_levels = 0;   // Gray levels whose M_int rows are VGPR-resident
     int32_t pack_shift = 0;   // tier 4: c added to every chunk energy (and
                               // subtracted from every prefix energy)
@@ -78,7 +80,7 @@ bool tune_valid(const TuneEntry &e, std::string *msg);
 // `many`: the instance shares its walk launch with others (batch, server),
 // so it needs no item-level parallelism of its own (a tuned L is then
 // ignored: it was measured for a lone instance).  `packed_ok`: the plan may
-// take the packed tier (4) where the input allows it (false for top-k).
+// take the packed tier (4) where the input allows it.
 qubo_status_t make_plan(const void *Q, int n, qubo_dtype_t dtype, const qubo_options_t *opt,
                         Plan *out, std::string *msg, bool many = false, bool packed_ok = true);
 

@@ -99,7 +99,7 @@ static JobOffsets compute_offsets(const Job &job, size_t *stage_bytes, size_t *b
         const qplan::Plan &P = job.plans[i];
         // words per M_int row: 2^B, or 2^(B-1) packed (two columns a word)
         const size_t A = P.direct ? 0 : size_t(P.A),
-                     NS = P.direct ? 0 : (size_t(1) << (P.tier == 4 ? P.B - 1 : P.B));
+                     NS = P.direct ? 0 : (size_t(1) << (P.tier >= 4 ? P.B - 1 : P.B));
         // M_int and the prefix couplings, each followed by its negation
         o.M.push_back(off);
         off = align_up(off + 2 * A * NS * sizeof(int32_t), 256);
@@ -190,8 +190,9 @@ qubo_status_t job_layout(Job *job, int waves_per_cu)
         if (P.A > job->max_A) job->max_A = P.A;
         job->total_items += P.walk_items();
     }
-    if (job->topk > 1 && (job->plans.size() != 1 || (!job->groups.empty() && job->groups[0].tier != 3))) {
-        set_error("internal: top-k jobs hold one instance planned for tier 3");
+    if (job->topk > 1 && (job->plans.size() != 1 ||
+                          (!job->groups.empty() && job->groups[0].tier != 3 && job->groups[0].tier != 5))) {
+        set_error("internal: top-k jobs hold one instance planned for tier 3 or 5");
         return QUBO_EINTERNAL;
     }
     for (WalkGroup &g : job->groups) {
@@ -253,8 +254,8 @@ qubo_status_t job_bind(Job *job, void *d_mem)
         I.L = P.L;
         I.direct = P.direct ? 1 : 0;
         I.kslot = int(i);
-        I.packed = P.tier == 4 ? 1 : 0;
-        I.pack_shift = P.tier == 4 ? P.pack_shift : 0;
+        I.packed = (P.tier == 4 || P.tier == 5) ? 1 : 0;
+        I.pack_shift = I.packed ? P.pack_shift : 0;
         I.item_begin = group_base[i];
         I.item_end = group_base[i] + (P.direct ? 0 : P.walk_items());
         item += P.direct ? 0 : P.walk_items();
@@ -513,21 +514,23 @@ qubo_status_t check_k(int k, int n, qubo_state_t *topk)
     return QUBO_OK;
 }
 
-// The top-k walk keeps candidate lists (tier 3); the finish selects.
+// The top-k walk keeps candidate lists (tier 3, or 5 on the packed layout);
+// the finish selects.
 void plan_topk(qrt::Job &job, int k, const qubo_options_t *opt)
 {
     job.topk = k;
     qplan::Plan &P = job.plans[0];
     if (P.direct) return;
-    P.tier = 3;
+    P.tier = P.tier == 4 ? 5 : 3;
+    const int t = P.tier;
     // The list entries live in global memory and only their scalars in LDS,
     // so the LDS row caches keep four waves per SIMD for any k.  With the
     // seeded bound the default one ("4") is the fastest top-k walk (its one
     // spilled register is reloaded once per super-block); "3" is next, and
     // the VGPR row cache (three waves) is taken should neither fit four waves.
     if ((P.vgpr_levels == 4 || P.vgpr_levels == 3) && !(opt && opt->vgpr_levels)) {
-        if (qk::walk_occupancy(P.mcols, 4, 3, k) >= 4 * 4) P.vgpr_levels = 4;
-        else P.vgpr_levels = qk::walk_occupancy(P.mcols, 3, 3, k) >= 4 * 4 ? 3 : 6;
+        if (qk::walk_occupancy(P.mcols, 4, t, k) >= 4 * 4) P.vgpr_levels = 4;
+        else P.vgpr_levels = qk::walk_occupancy(P.mcols, 3, t, k) >= 4 * 4 ? 3 : 6;
     }
 }
 
@@ -544,7 +547,7 @@ qubo_status_t solve_host(const void *Q, int n, qubo_dtype_t dtype, int k, const 
     qrt::Job job;
     job.plans.resize(1);
     std::string msg;
-    st = qplan::make_plan(Q, n, dtype, opt, &job.plans[0], &msg, false, k <= 1);
+    st = qplan::make_plan(Q, n, dtype, opt, &job.plans[0], &msg);
     if (st != QUBO_OK) {
         qrt::set_error(msg);
         return st;
@@ -656,7 +659,7 @@ qubo_status_t qubo_plan_info(const void *Q, int n, qubo_dtype_t dtype, const qub
         info->eps_q = P.eps_q;
         info->sum_abs_t = P.sum_abs;
         info->items = P.items;
-        info->pack_shift = P.tier == 4 ? P.pack_shift : 0;
+        info->pack_shift = P.tier >= 4 ? P.pack_shift : 0;
         info->reserved = 0;
         if (T_out) std::memcpy(T_out, P.T.data(), P.T.size() * sizeof(int32_t));
         return QUBO_OK;

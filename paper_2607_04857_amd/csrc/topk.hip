@@ -260,14 +260,12 @@ __global__ __launch_bounds__(256) void topk_rescan_kernel(const Inst *__restrict
         __syncthreads();
     }
     const int32_t Ep = int32_t(red[0]);
-    // NS is a multiple of 64: every lane of a wave that enters runs each pass
-    for (uint32_t s = threadIdx.x; s < NS; s += blockDim.x) {
-        int32_t e = Ep + I.EB[s];
-        for (int v = 0; v < A; v++)
-            if ((row >> (A - 1 - v)) & 1) e += I.M[uint32_t(v) * NS + s];
+    // state (row, s) of energy e: kept when at most the bound (the whole
+    // wave calls this together)
+    auto offer = [&](int32_t e, uint32_t s) {
         const bool keep = e <= bound;
         const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
-        if (!m) continue;
+        if (!m) return;
         int base = 0;
         if (lane == 0) base = atomicAdd(stCount, int(__builtin_popcountll(m)));
         base = __builtin_amdgcn_readfirstlane(base);
@@ -275,6 +273,28 @@ __global__ __launch_bounds__(256) void topk_rescan_kernel(const Inst *__restrict
             const int p = base + int(__builtin_popcountll(m & ((1ull << lane) - 1)));
             stE[p] = e;
             stI[p] = (row << B) | s;
+        }
+    };
+    // NS (and NS / 2) is a multiple of 64: every lane of a wave that enters
+    // runs each pass
+    if (I.packed) {
+        // the walk's own arithmetic: the packed words of the chunk summed mod
+        // 2^32, then both 16-bit halves decoded (columns c and c + NS / 2)
+        const uint32_t NW = NS / 2;
+        const int32_t off = kPackBias + I.pack_shift;
+        for (uint32_t c = threadIdx.x; c < NW; c += blockDim.x) {
+            uint32_t w = uint32_t(I.EB[c]);
+            for (int v = 0; v < A; v++)
+                if ((row >> (A - 1 - v)) & 1) w += uint32_t(I.M[uint32_t(v) * NW + c]);
+            offer(Ep + int32_t(w & 0xffffu) - off, c);
+            offer(Ep + int32_t(w >> 16) - off, c + NW);
+        }
+    } else {
+        for (uint32_t s = threadIdx.x; s < NS; s += blockDim.x) {
+            int32_t e = Ep + I.EB[s];
+            for (int v = 0; v < A; v++)
+                if ((row >> (A - 1 - v)) & 1) e += I.M[uint32_t(v) * NS + s];
+            offer(e, s);
         }
     }
 }

@@ -35,11 +35,12 @@ __device__ __forceinline__ int32_t wave_min_bcast(int32_t v)
 //         lm0 against an upper bound of its 32 thresholds (one vector
 //         compare); only when a lane passes are W0 and the exact thresholds
 //         formed and tested, step by step.
-// TIER 4: tier 2 on the packed layout: each of the MC words of a lane holds
-//         two chunk energies (columns c and c + 2^(B-1) of the chunk), so one
-//         32-bit add per word and step moves two states (Eq.
+// TIER 4, 5: tiers 2 and 3 on the packed layout: each of the MC words of a
+//         lane holds two chunk energies (columns c and c + 2^(B-1) of the
+//         chunk), so one 32-bit add per word and step moves two states (Eq.
 //         incremental_update at 16-bit precision); only the lane minimum
-//         differs (packed 16-bit minima, then the unbiased smaller half).
+//         (packed 16-bit minima, then the unbiased smaller half) and the
+//         prefix energy's shift differ.
 // Resident waves per SIMD each variant is register-allocated for: the full
 // 12-level row cache fits 256 VGPRs (2 waves); the 8- and 6-level caches
 // leave room for a third (MC=16) or a fourth (MC=8) wave.
@@ -53,11 +54,12 @@ constexpr int walk_waves_per_simd()
 // (G = 6 and 8 with MC = 16 target 3 waves, G = 5 four; 8 and 5 spill a few
 // values outside the unrolled steps.)
 
-// Bytes of dynamic LDS ahead of the LDS rows (the tier-3 list), 16-aligned.
+// Bytes of dynamic LDS ahead of the LDS rows (the tier-3 / tier-5 list),
+// 16-aligned.
 __host__ __device__ inline size_t lds_rows_offset(int tier, int k)
 {
     (void)k;
-    return tier == 3 ? (topk_lds_bytes() + 15) & ~size_t(15) : 0;
+    return (tier == 3 || tier == 5) ? (topk_lds_bytes() + 15) & ~size_t(15) : 0;
 }
 template <int MC>
 constexpr size_t lds_rows_bytes()
@@ -291,11 +293,14 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
     const Inst *__restrict__ insts, int n_inst, uint64_t total_items,
     unsigned long long *__restrict__ counter, const int32_t *__restrict__ kall, TopkWalk tk)
 {
-    static_assert(TIER >= 1 && TIER <= 4, "tier");
+    static_assert(TIER >= 1 && TIER <= 5, "tier");
     static_assert(G >= kLowLevels && G <= kMaxVgprLevels, "VGPR-resident levels");
+    // packed layout (tiers 4 and 5) and the test it runs (2: best, 3: top-k)
+    constexpr bool PK = TIER >= 4;
+    constexpr int BT = PK ? TIER - 2 : TIER;
     // steps per bound-test segment: tier 3's looser threshold takes the
     // exact path more often, where shorter segments and SGPR thresholds pay
-    constexpr int SEG = TIER == 3 ? kSegStepsTopk : kSegSteps;
+    constexpr int SEG = BT == 3 ? kSegStepsTopk : kSegSteps;
     constexpr int NSEG = (1 << kSuperLog) / SEG;
     const int lane = int(threadIdx.x);
     const uint32_t ulane = threadIdx.x;
@@ -303,7 +308,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
     auto trow = [](const gint32 *t, int v) { return t + size_t(v) * (MC * kWave); };
     // this lane's chunk minimum (tier 4: over both halves of every word)
     auto lane_min = [](const int32_t(&e)[MC]) {
-        if constexpr (TIER == 4) return tree_min_packed<MC>(e);
+        if constexpr (PK) return tree_min_packed<MC>(e);
         else return tree_min<MC>(e);
     };
     // LR: rows of levels 3 and 4 after the (tier-3) list in dynamic LDS
@@ -327,7 +332,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
     int32_t best = kNoEnergy;     // tier 3: the current top-k threshold
     uint64_t bestRow = ~0ull;
 
-    if constexpr (TIER == 3) tk_init(tk);
+    if constexpr (BT == 3) tk_init(tk);
 
     for (;;) {
         uint64_t g = 0;
@@ -400,7 +405,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
             });
             best = kNoEnergy;
             bestRow = ~0ull;
-            if constexpr (TIER != 3) gbest = I.gbest;
+            if constexpr (BT != 3) gbest = I.gbest;
         }
 
         // Best energy found by any wave for this instance (published at the
@@ -408,7 +413,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
         // key is at most that.  (A chunk tying it with an unknown row is still
         // recorded: bestRow restarts at the largest row whenever the shared
         // value lowers best.)
-        if constexpr (TIER != 3) {
+        if constexpr (BT != 3) {
             const int32_t g0 = sread(__hip_atomic_load(gbest, __ATOMIC_RELAXED,
                                                        __HIP_MEMORY_SCOPE_AGENT));
             if (g0 < best) {
@@ -445,14 +450,14 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
         int32_t Enl = int32_t(wave_sum64(lbit ? int64_t(F) + diagl : 0) / 2);
         // tier 4: the chunk energies carry the instance's shift c, the
         // prefix energy the opposite one, so every sum is the true energy
-        if constexpr (TIER == 4) Enl -= insts[cur].pack_shift;
+        if constexpr (PK) Enl -= insts[cur].pack_shift;
         Enl = sread(Enl);
         int32_t H[kLowLevels];
         static_for<0, kLowLevels>([&](auto tc) {
             constexpr int t = decltype(tc)::value;
             H[t] = __builtin_amdgcn_readlane(F, A - 1 - t);
         });
-        if constexpr (TIER == 3) best = tk_threshold();
+        if constexpr (BT == 3) best = tk_threshold();
 
         // TIER 1: THR[p] = best - E_p(low pattern p): the chunk holds a
         // candidate when its minimum E_sd is <= THR of the current pattern.
@@ -495,7 +500,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
             });
         };
         // Tier-3 thresholds of the current segment, kept in SGPRs.
-        int32_t TP[TIER == 3 ? SEG : 1];
+        int32_t TP[BT == 3 ? SEG : 1];
         auto build_tp = [&](auto segc, int tab) {
             for_each_tp(segc, tab, [&](auto oc, int32_t tp) { TP[decltype(oc)::value] = tp; });
         };
@@ -553,7 +558,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                     const int32_t nb = sread(tk_insert(Ec, i ^ (i >> 1)));
                     const int32_t d = nb - best;
                     best = nb;
-                    if constexpr (TIER == 3)
+                    if constexpr (BT == 3)
                         static_for<0, SEG>([&](auto pc) { TP[decltype(pc)::value] += d; });
                 }
             }
@@ -687,7 +692,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                     int32_t tb = best - Enl - kall[kbase + kc2min_slot(SEG, tab2, h)];
                     static_for<0, kLowLevels>([&](auto tc) { tb -= min(0, H[decltype(tc)::value]); });
                     const bool cold = __builtin_amdgcn_ballot_w64(lm0 <= tb) != 0;
-                    if constexpr (TIER == 3) {
+                    if constexpr (BT == 3) {
                         if (__builtin_expect(cold, 0)) {
                             // exact tests against the segment's SGPR thresholds
                             W0 = wave_min_bcast(lm0);
@@ -698,7 +703,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
                                 if (W0 <= TP[o2]) {
                                     const int32_t thr =
                                         TP[o2] + kall[kbase + (3 + tab2) * kPatterns + (o & (kPatterns - 1))];
-                                    candidate3(tree_min<MC>(E), thr, (sb << kSuperLog) | uint64_t(o));
+                                    candidate3(lane_min(E), thr, (sb << kSuperLog) | uint64_t(o));
                                 }
                                 step_flip(oc);
                             });
@@ -764,7 +769,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
             }
         }
 
-        if (TIER != 3 && found && lane == 0) {
+        if (BT != 3 && found && lane == 0) {
             // Only items that found a candidate leave a record, marked in the
             // instance's bitmap (the record and bitmap pointers are read from
             // the descriptor here, on this rare path, rather than held in
@@ -782,7 +787,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
             atomicMin(gbest, itemE);
         }
     }
-    if constexpr (TIER == 3) tk_flush();
+    if constexpr (BT == 3) tk_flush();
 }
 
 template <int MC, int G, bool LR = false>
@@ -813,6 +818,12 @@ static hipError_t launch_walk_g(const WalkLaunch &w)
         hipLaunchKernelGGL((walk_kernel<MC, G, 3, LR>), dim3(w.waves), dim3(kWave),
                            (walk_lds_bytes<MC, G, LR>(3, w.tk->k)), w.stream, w.insts, w.n_inst,
                            w.total_items, w.counter, w.k, *w.tk);
+    } else if (w.tier == 5 && MC >= 4) {
+        if (!w.tk || w.tk->k < 2 || w.n_inst != 1) return hipErrorInvalidValue;
+        if constexpr (MC >= 4)
+            hipLaunchKernelGGL((walk_kernel<MC, G, 5, LR>), dim3(w.waves), dim3(kWave),
+                               (walk_lds_bytes<MC, G, LR>(5, w.tk->k)), w.stream, w.insts,
+                               w.n_inst, w.total_items, w.counter, w.k, *w.tk);
     } else {
         return hipErrorInvalidValue;
     }
@@ -834,6 +845,10 @@ static int occupancy_g(int tier, int topk_k)
         if constexpr (MC >= 4)
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, G, 4, LR>, kWave,
                                                              walk_lds_bytes<MC, G, LR>(4, 0));
+    } else if (tier == 5 && MC >= 4) {
+        if constexpr (MC >= 4)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, G, 5, LR>, kWave,
+                                                             walk_lds_bytes<MC, G, LR>(5, topk_k));
     }
     else
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, walk_kernel<MC, G, 1, LR>, kWave,

@@ -75,7 +75,7 @@ def test_lower_triangle_is_folded(env):
 @pytest.mark.parametrize("kind,n,k", [("int", 12, 16), ("int", 26, 64), ("fp32", 23, 32)])
 def test_topk_equals_host(env, kind, n, k):
     q, torch = env
-    Q = inputs.uniform_int(n, -300, 300, 970 + n) if kind == "int" else inputs.normal_fp32(n, 970 + n)
+    Q = inputs.uniform_int(n, -10000, 10000, 970 + n) if kind == "int" else inputs.normal_fp32(n, 970 + n)
     dev, dl = q.solve_device(torch.from_numpy(Q).cuda(), k=k)
     host, hl = q.solve(Q, k=k)
     _same(dev, host)

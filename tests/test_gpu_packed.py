@@ -209,3 +209,35 @@ def test_packed_in_batch(q, orc):
             assert r.tier != 4
     assert any(r.tier == 4 for r in res)
     b.close()
+
+
+@pytest.mark.parametrize("n,k,R", [(17, 2, 100), (18, 64, 100), (20, 1024, 100), (22, 300, 1000),
+                                   (24, 1024, 1000), (26, 512, 100)])
+def test_packed_topk(q, orc, n, k, R):
+    """Top-k on the packed layout (tier 5): the whole list equals the
+    oracle's k smallest (E, index) pairs; R = 1000 packs with a shift."""
+    Q = inputs.uniform_int(n, -R, R, 1500 + n)
+    res, pairs = q.solve(Q, k=k)
+    ref = orc.solve(Q, k=k)
+    print(f"packed top-k n={n} k={k} tier {res.tier} B {res.B} "
+          f"shift {q.plan_info(Q)['pack_shift']}", flush=True)
+    assert res.tier == 5
+    assert pairs == [(int(e), int(i)) for e, i in ref]
+    assert (res.energy_i, res.index) == pairs[0]
+
+
+def test_packed_topk_ties_and_forced(q, orc):
+    """All-zero and {-1, 0, 1} matrices (ties everywhere) and every packed
+    row cache, forced."""
+    res, pairs = q.solve(np.zeros((18, 18), dtype=np.int32), k=1024)
+    assert res.tier == 5 and pairs == [(0, i) for i in range(1024)]
+    rng = np.random.default_rng(78)
+    Q = np.triu(rng.integers(-1, 2, (20, 20))).astype(np.int32)
+    ref = [(int(e), int(i)) for e, i in orc.solve(Q, k=1024)]
+    assert q.solve(Q, k=1024)[1] == ref
+    Q = inputs.uniform_int(21, -200, 200, 1601)
+    ref = [(int(e), int(i)) for e, i in orc.solve(Q, k=100)]
+    for B, G in [(11, 4), (11, 3), (11, 5), (11, 6), (11, 8), (11, 12), (10, 8), (10, 12), (9, 12)]:
+        res, pairs = q.solve(Q, k=100, tier=4, B=B, vgpr_levels=G)
+        assert (res.tier, res.B, res.vgpr_levels) == (5, B, G)
+        assert pairs == ref, (B, G)

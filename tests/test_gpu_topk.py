@@ -31,8 +31,8 @@ def test_walk_sizes(orc, n, k):
     import paper_2607_04857_amd as q
     Q = inputs.uniform_int(n, -1000, 1000, 1100 + n)
     res, _ = _exact(orc, q, Q, k)
-    assert res.tier == 3
-    print(f"top-k n={n} k={k} ok ({res.kernel_ms:.3f} ms walk)", flush=True)
+    assert res.tier in (3, 5)          # 5: the packed layout (entries to 1000 mostly fit it)
+    print(f"top-k n={n} k={k} tier {res.tier} ok ({res.kernel_ms:.3f} ms walk)", flush=True)
 
 
 @pytest.mark.parametrize("B,G", [(6, 12), (7, 12), (8, 12), (9, 12), (9, 8), (10, 12), (10, 8),
