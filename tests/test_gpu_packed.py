@@ -194,21 +194,50 @@ def test_packed_in_batch(q, orc):
     not (U[-10^4, 10^4]): each result equals the oracle, and the packable
     ones ran tier 4."""
     Qs = []
-    for i, n in enumerate([18, 20, 21, 22, 24, 19, 23, 20]):
-        lo = -10000 if i % 3 == 2 else -100
+    for i, n in enumerate([18, 20, 21, 22, 24, 19, 23, 20, 22, 24]):
+        lo = (-10000, -100, -1000)[i % 3]
         Qs.append(inputs.uniform_int(n, lo, -lo, 600 + i))
     b = q.Batch(Qs)
-    b.run()
-    res = b.results()
-    for Q, r in zip(Qs, res):
-        exp = orc.solve(Q, k=1)[0]
-        packable = int(np.abs(Q).max()) <= 100
-        print(Q.shape[0], packable, r.tier, (r.energy_i, r.index), exp, flush=True)
-        assert (r.energy_i, r.index) == exp
-        if not packable:
-            assert r.tier != 4
-    assert any(r.tier == 4 for r in res)
+    for rep in range(2):
+        b.run()
+        res = b.results()
+        for Q, r in zip(Qs, res):
+            exp = orc.solve(Q, k=1)[0]
+            lim = int(np.abs(Q).max())
+            print(rep, Q.shape[0], lim, r.tier, (r.energy_i, r.index), exp, flush=True)
+            assert (r.energy_i, r.index) == exp
+            if lim > 1000:
+                assert r.tier != 4
+        assert any(r.tier == 4 for r in res)
     b.close()
+
+
+def test_packed_in_server(q, orc):
+    """Served requests with entries to 100 (packed, no shift), to 1000
+    (packed with a shift) and to 10^4 (int32 walk), submitted together:
+    each result equals its lone solve and, for n <= 24, the oracle."""
+    Qs = []
+    for i, n in enumerate([17, 20, 22, 24, 26, 28, 30, 21, 23]):
+        lo = (-100, -1000, -10000)[i % 3]
+        Qs.append(inputs.uniform_int(n, lo, -lo, 700 + i))
+    srv = q.Server(mem_budget_bytes=1 << 30, max_slots=16)
+    tickets = [srv.submit(Q) for Q in Qs]
+    tiers = []
+    for Q, t in zip(Qs, tickets):
+        r = srv.wait(t, timeout_ms=60000)
+        alone = q.solve(Q)
+        lim = int(np.abs(Q).max())
+        print(Q.shape[0], lim, r.tier, alone.tier, (r.energy_i, r.index), flush=True)
+        assert (r.energy_i, r.index) == (alone.energy_i, alone.index)
+        if Q.shape[0] <= 24:
+            assert (r.energy_i, r.index) == orc.solve(Q, k=1)[0]
+        if lim <= 100:
+            assert r.tier == 4
+        if lim > 1000:
+            assert r.tier != 4
+        tiers.append((lim, r.tier))
+    srv.close()
+    assert (1000, 4) in tiers            # a request packed with a shift
 
 
 @pytest.mark.parametrize("n,k,R", [(17, 2, 100), (18, 64, 100), (20, 1024, 100), (22, 300, 1000),
