@@ -193,17 +193,16 @@ def test_packed_in_batch(q, orc):
     """A batch mixing packable instances (U[-100, 100]) with ones that are
     not (U[-10^4, 10^4]): each result equals the oracle, and the packable
     ones ran tier 4."""
-    Qs = []
+    Qs, lims = [], []
     for i, n in enumerate([18, 20, 21, 22, 24, 19, 23, 20, 22, 24]):
-        lo = (-10000, -100, -1000)[i % 3]
-        Qs.append(inputs.uniform_int(n, lo, -lo, 600 + i))
+        lims.append((10000, 100, 1000)[i % 3])
+        Qs.append(inputs.uniform_int(n, -lims[-1], lims[-1], 600 + i))
     b = q.Batch(Qs)
     for rep in range(2):
         b.run()
         res = b.results()
-        for Q, r in zip(Qs, res):
+        for Q, r, lim in zip(Qs, res, lims):
             exp = orc.solve(Q, k=1)[0]
-            lim = int(np.abs(Q).max())
             print(rep, Q.shape[0], lim, r.tier, (r.energy_i, r.index), exp, flush=True)
             assert (r.energy_i, r.index) == exp
             if lim > 1000:
@@ -216,17 +215,16 @@ def test_packed_in_server(q, orc):
     """Served requests with entries to 100 (packed, no shift), to 1000
     (packed with a shift) and to 10^4 (int32 walk), submitted together:
     each result equals its lone solve and, for n <= 24, the oracle."""
-    Qs = []
+    Qs, lims = [], []
     for i, n in enumerate([17, 20, 22, 24, 26, 28, 30, 21, 23]):
-        lo = (-100, -1000, -10000)[i % 3]
-        Qs.append(inputs.uniform_int(n, lo, -lo, 700 + i))
+        lims.append((100, 1000, 10000)[i % 3])
+        Qs.append(inputs.uniform_int(n, -lims[-1], lims[-1], 700 + i))
     srv = q.Server(mem_budget_bytes=1 << 30, max_slots=16)
     tickets = [srv.submit(Q) for Q in Qs]
     tiers = []
-    for Q, t in zip(Qs, tickets):
+    for Q, t, lim in zip(Qs, tickets, lims):
         r = srv.wait(t, timeout_ms=60000)
         alone = q.solve(Q)
-        lim = int(np.abs(Q).max())
         print(Q.shape[0], lim, r.tier, alone.tier, (r.energy_i, r.index), flush=True)
         assert (r.energy_i, r.index) == (alone.energy_i, alone.index)
         if Q.shape[0] <= 24:
