@@ -363,19 +363,6 @@ __device__ void block_lexmin(int64_t &bE, uint64_t &bI, int64_t *sE, uint64_t *s
     __syncthreads();
 }
 
-// Energy of U_N row idx from T staged in LDS, one lane per variable (the
-// whole wave must call it): the same sum as energy_int.
-__device__ int64_t wave_energy(const int32_t *T, int n, uint64_t idx)
-{
-    const int l = int(threadIdx.x) % kWave;
-    int64_t part = 0;
-    if (l < n && ((idx >> (n - 1 - l)) & 1)) {
-        for (int j = l; j < n; j++)
-            if ((idx >> (n - 1 - j)) & 1) part += T[l * n + j];
-    }
-    return wave_sum64(part);
-}
-
 constexpr int kFinishThreads = 1024;
 
 __global__ __launch_bounds__(kFinishThreads) void finish_kernel(const Inst *__restrict__ insts,
@@ -435,21 +422,26 @@ __global__ __launch_bounds__(kFinishThreads) void finish_kernel(const Inst *__re
             // sum_{t < u in s} T[A+t][A+u] (Sec. II-C), where c_t = T[A+t][A+t]
             // + sum over the set prefix variables v of T[v][A+t].
             const int A = I.A, B = I.B;
-            if (threadIdx.x < kWave) {
-                const int l = int(threadIdx.x);
-                int64_t part = 0;
-                if (l < A && ((rowstar >> (A - 1 - l)) & 1)) {
-                    for (int j = l; j < A; j++)
-                        if ((rowstar >> (A - 1 - j)) & 1) part += sT[l * n + j];
-                }
-                part = wave_sum64(part);
-                if (l == 0) sEp = part;
-                if (l < B) {
-                    int64_t c = sT[(A + l) * n + (A + l)];
-                    for (int v = 0; v < A; v++)
-                        if ((rowstar >> (A - 1 - v)) & 1) c += sT[v * n + A + l];
-                    sC[l] = c;
-                }
+            const int w = int(threadIdx.x) / kWave, l = int(threadIdx.x) % kWave;
+            auto set = [&](int v) { return ((rowstar >> (A - 1 - v)) & 1) != 0; };
+            // E_p(row*): the pairs i <= j < A of set prefix variables, spread
+            // over the block (a few per thread), one LDS add per wave
+            if (threadIdx.x == 0) sEp = 0;
+            __syncthreads();
+            int64_t part = 0;
+            for (int e = int(threadIdx.x); e < A * A; e += int(blockDim.x)) {
+                const int i = e / A, j = e % A;
+                if (j >= i && set(i) && set(j)) part += sT[i * n + j];
+            }
+            part = wave_sum64(part);
+            if (l == 0 && part != 0) atomicAdd(reinterpret_cast<unsigned long long *>(&sEp),
+                                               static_cast<unsigned long long>(part));
+            // c_t: wave t sums the couplings of suffix variable A+t with the
+            // set prefix variables, one lane per prefix variable (A < 64)
+            if (w < B) {
+                int64_t c = (l < A && set(l)) ? int64_t(sT[l * n + A + w]) : 0;
+                c = wave_sum64(c);
+                if (l == 0) sC[w] = c + sT[(A + w) * n + (A + w)];
             }
             __syncthreads();
             bE = INT64_MAX;
@@ -468,9 +460,22 @@ __global__ __launch_bounds__(kFinishThreads) void finish_kernel(const Inst *__re
             block_lexmin(bE, bI, sE, sI);
             if (bE != Estar) {
                 status = 3;   // the walk claimed an energy the chunk lacks
-            } else if (threadIdx.x < kWave) {
-                // the winner evaluated in full from T must agree
-                if (wave_energy(sT, n, bI) != Estar) status = 3;
+            } else {
+                // the winner evaluated in full from T must agree: its pairs
+                // i <= j < n spread over the block as above
+                if (threadIdx.x == 0) sEp = 0;
+                __syncthreads();
+                int64_t full = 0;
+                for (int e = int(threadIdx.x); e < n * n; e += int(blockDim.x)) {
+                    const int i = e / n, j = e % n;
+                    if (j >= i && ((bI >> (n - 1 - i)) & 1) && ((bI >> (n - 1 - j)) & 1))
+                        full += sT[i * n + j];
+                }
+                full = wave_sum64(full);
+                if (l == 0 && full != 0) atomicAdd(reinterpret_cast<unsigned long long *>(&sEp),
+                                                   static_cast<unsigned long long>(full));
+                __syncthreads();
+                if (sEp != Estar) status = 3;
             }
         }
     }
