@@ -7,7 +7,7 @@
 //                     stored at s = j*64 + lane so lane `lane` owns columns
 //                     {j*64 + lane}, j < 2^B/64 (column-wise split, Sec. III-C.2)
 //   EB  [2^B]         suffix energies E_s(U_B) (Sec. III-A, preprocessing 2)
-//                     Packed instances (tier 4) store 2^(B-1) words per row:
+//                     Packed instances (tiers 4, 5) store 2^(B-1) words per row:
 //                     word c holds column c in its low 16 bits and column
 //                     c + 2^(B-1) (suffix variable A set) in its high 16
 //                     bits, EB biased by kPackBias in each half, so one
@@ -56,9 +56,10 @@ constexpr int kMaxVgprLevels = 12;    // at most Gray levels 0..11 keep their M_
 constexpr int32_t kNoEnergy = 1 << 30;  // above every energy the walk can meet
 constexpr int kMaxVars = 60;          // largest n the planner accepts
 constexpr int kMaxPrefixRows = 60 - 6;   // A = n - B <= 60 - 6
-// Packed walk (tier 4, the int16 energies of Sec. IV-B "Data types" at two
-// per 32-bit word).  Word = (E_lo + kPackBias) + (E_hi + kPackBias) 2^16 and a
-// row word = m_lo + m_hi 2^16 (mod 2^32): the map is additive mod 2^32, so a
+// Packed walk (tiers 4 and 5, the int16 energies of Sec. IV-B "Data types"
+// at two per 32-bit word).  Word = (E_lo + c + kPackBias) + (E_hi + c +
+// kPackBias) 2^16 and a row word = m_lo + m_hi 2^16 (mod 2^32), with c the
+// instance's shift below: the map is additive mod 2^32, so a
 // 32-bit add of a row word adds m_lo and m_hi to the two halves however the
 // intermediate carries fall, and a word decodes exactly whenever both biased
 // halves lie in [0, 2^16).  The planner proves every chunk energy E_sd + c
@@ -104,8 +105,8 @@ struct Inst {
     int n, A, B, L;
     int direct;            // 1: no walk, direct evaluation of all 2^n states
     int kslot;             // index of the K table in the launch's K array
-    int packed;            // 1: M and EB in the packed 16-bit layout (tier 4)
-    int32_t pack_shift;    // tier 4: c added to every chunk energy in EB and
+    int packed;            // 1: M and EB in the packed 16-bit layout (tiers 4, 5)
+    int32_t pack_shift;    // tiers 4, 5: c added to every chunk energy in EB and
                            // taken off the prefix energy, so that every
                            // E_sd + c is a signed 16-bit value
     uint64_t item_begin;   // this launch's walk-item range [item_begin, item_end)
@@ -195,16 +196,16 @@ hipError_t launch_tables(const Inst *d_insts, int n_inst, int max_A, unsigned lo
 // Persistent Gray walk over all items; `waves` resident wavefronts.  d_k is
 // the contiguous array of K tables (instance i's at insts[i].kslot*kKTable).
 // Variant: mcols words per lane (B = 6 + log2 mcols, 7 + log2 mcols for
-// tier 4), the M_int rows of Gray levels below vgpr_levels cached in VGPRs
-// (higher ones from L2), tier.
-// Tier 3 (top-k lists) needs `tk` and exactly one instance; tiers 1 and 2
-// ignore it (may be null).
+// tiers 4 and 5), the M_int rows of Gray levels below vgpr_levels cached in
+// VGPRs (higher ones from L2), tier.
+// Tiers 3 and 5 (top-k lists) need `tk` and exactly one instance; tiers 1,
+// 2 and 4 ignore it (may be null).
 hipError_t launch_walk(int mcols, int vgpr_levels, int tier, const Inst *d_insts, int n_inst,
                        uint64_t total_items, unsigned long long *d_counter, const int32_t *d_k,
                        int waves, hipStream_t stream, const TopkWalk *tk = nullptr);
 
 // Whether a (mcols, vgpr_levels) walk variant is compiled in, and whether
-// its packed form (tier 4: 2 mcols 64 suffix columns) is.
+// its packed form (tiers 4 and 5: 2 mcols 64 suffix columns) is.
 bool walk_variant_exists(int mcols, int vgpr_levels);
 bool walk_packed_exists(int mcols, int vgpr_levels);
 

@@ -38,7 +38,7 @@ struct Plan {
                            // 3 / 5: top-k lists on the int32 / packed walk
                            // (set by the top-k planning)
     int vgpr_levels = 0;   // Gray levels whose M_int rows are VGPR-resident
-    int32_t pack_shift = 0;   // tier 4: c added to every chunk energy (and
+    int32_t pack_shift = 0;   // tiers 4, 5: c added to every chunk energy (and
                               // subtracted from every prefix energy)
     int p = 0;             // fixed-point exponent (fp32)
     double eps_q = 0.0;    // per-state quantisation bound (fp32)

@@ -306,7 +306,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
     const uint32_t ulane = threadIdx.x;
     // row v of a lane-major [rows][MC*64] table: uniform base pointer
     auto trow = [](const gint32 *t, int v) { return t + size_t(v) * (MC * kWave); };
-    // this lane's chunk minimum (tier 4: over both halves of every word)
+    // this lane's chunk minimum (packed: over both halves of every word)
     auto lane_min = [](const int32_t(&e)[MC]) {
         if constexpr (PK) return tree_min_packed<MC>(e);
         else return tree_min<MC>(e);
@@ -448,7 +448,7 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
         // E_nl = energy of the non-low prefix bits = (sum_set F_w + T_ww) / 2
         const bool lbit = lane <= A - 1 - kLowLevels && ((row0 >> (A - 1 - lane)) & 1);
         int32_t Enl = int32_t(wave_sum64(lbit ? int64_t(F) + diagl : 0) / 2);
-        // tier 4: the chunk energies carry the instance's shift c, the
+        // packed: the chunk energies carry the instance's shift c, the
         // prefix energy the opposite one, so every sum is the true energy
         if constexpr (PK) Enl -= insts[cur].pack_shift;
         Enl = sread(Enl);
