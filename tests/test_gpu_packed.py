@@ -189,6 +189,29 @@ def test_packed_n44_bench_instance(q, orc):
         assert orc.energy(Q, a.index ^ (1 << v)) >= a.energy_i
 
 
+def test_packed_n44_sampled_items(q, orc):
+    """The packed bench leg's plan (n = 44, entries U[-20, 20]: tier 4,
+    B = 11, L = 15, 2^18 items) on sampled work items, each the contiguous
+    index range [g(c) 2^(L+B), (g(c)+1) 2^(L+B)) of 2^26 states that the
+    oracle evaluates exhaustively: the first and last item pairs and four
+    random ones; each range is walked without the shared best (thresholds
+    from the no-energy sentinel)."""
+    Q = inputs.uniform_int(44, -20, 20, 4)
+    info = q.plan_info(Q)
+    L, B, items = info["L"], info["B"], info["items"]
+    assert (info["tier"], info["A"], B, L, items) == (4, 33, 11, 15, 1 << 18)
+    span = 1 << (L + B)
+    rng = np.random.default_rng(45)
+    firsts = [0, items - 2] + [int(c) for c in rng.integers(0, items - 2, 4)]
+    for c0 in firsts:
+        got = q.solve(Q, item_first=c0, item_count=2, tier=4, L=L)
+        assert (got.tier, got.B, got.L) == (4, B, L)
+        exp = min(orc.solve_range(Q, _gray(c) * span, span, k=1)[0] for c in range(c0, c0 + 2))
+        print(f"packed items [{c0}, {c0 + 2}): {got.energy_i} @ {got.index} (oracle {exp})",
+              flush=True)
+        assert (got.energy_i, got.index) == exp
+
+
 def test_packed_in_batch(q, orc):
     """A batch mixing packable instances (U[-100, 100]) with ones that are
     not (U[-10^4, 10^4]): each result equals the oracle, and the packable
