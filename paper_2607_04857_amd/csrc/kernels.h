@@ -106,9 +106,11 @@ struct Inst {
     int direct;            // 1: no walk, direct evaluation of all 2^n states
     int kslot;             // index of the K table in the launch's K array
     int packed;            // 1: M and EB in the packed 16-bit layout (tiers 4, 5)
-    int32_t pack_shift;    // tiers 4, 5: c added to every chunk energy in EB and
-                           // taken off the prefix energy, so that every
-                           // E_sd + c is a signed 16-bit value
+    int32_t pack_shift;    // c added to every chunk energy in EB and taken
+                           // off the prefix energy: tiers 4, 5 make every
+                           // E_sd + c a signed 16-bit value, the int32 walk
+                           // makes it non-negative (written by prepare_kernel
+                           // for a device-prepared instance)
     uint64_t item_begin;   // this launch's walk-item range [item_begin, item_end)
     uint64_t item_end;
     uint64_t item_local0;  // the instance's own item number of launch item item_begin
@@ -183,9 +185,11 @@ struct FinalRes {
 // Fold, check and (float32) scale the caller's device matrix dQ (n x n,
 // row-major, int32 or float32) into the instance's upper-triangular int32 T
 // (d_T, n x n), exactly as the host planner does, and write the outcome to
-// *d_prep.  On an input error T is left zero and the status says why.
+// *d_prep and the walk's chunk-energy shift to d_inst->pack_shift (the
+// descriptor's split A, B already set; int32 walk only).  On an input error
+// T is left zero and the status says why.
 hipError_t launch_prepare(const void *dQ, int n, int is_fp32, int32_t *d_T, PrepOut *d_prep,
-                          hipStream_t stream);
+                          Inst *d_inst, hipStream_t stream);
 
 // Builds M, EB, S, K for every instance, clears each instance's item bitmap
 // and shared best, and zeroes n_counters item counters (for a device-prepared

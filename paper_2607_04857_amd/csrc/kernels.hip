@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
             I.EB[c] = int32_t(uint32_t(esuf(c) + b) + (uint32_t(esuf(c + NW) + b) << 16));
         }
         else
-            I.EB[c] = esuf(c);
+            I.EB[c] = esuf(c) + I.pack_shift;
     }
     // prefix couplings, one lane per variable
     for (uint32_t e = tid; e < uint32_t(A) * kWave; e += stride) {
@@ -246,9 +246,12 @@ __device__ __forceinline__ int prep_scale_exponent(double S)
 
 __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(const void *__restrict__ dQ, int n,
                                                                int is_fp32, int32_t *__restrict__ T,
-                                                               PrepOut *__restrict__ out)
+                                                               PrepOut *__restrict__ out,
+                                                               Inst *__restrict__ inst)
 {
     __shared__ double sTd[kMaxVars * kMaxVars];   // folded float32 input in float64
+    __shared__ int32_t sTi[kMaxVars * kMaxVars];  // the int32 T written to T
+    __shared__ long long sLo;
     __shared__ unsigned long long sSum;
     __shared__ int sNnz, sBad;
     __shared__ double sS;
@@ -272,6 +275,7 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(const void *__res
                 v = int32_t(t);   // kept only if the bound holds (else T is zeroed)
             }
             T[e] = v;
+            sTi[e] = v;
         }
     } else {
         const float *q = static_cast<const float *>(dQ);
@@ -315,6 +319,7 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(const void *__res
             const int64_t t = int64_t(rint(ldexp(sTd[e], p)));   // ties to even
             s2 += uint64_t(t < 0 ? -t : t);
             T[e] = int32_t(t);
+            sTi[e] = int32_t(t);
         }
         atomicAdd(&sSum, (unsigned long long)s2);
         __syncthreads();
@@ -324,6 +329,38 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(const void *__res
     }
     if (status != 0)
         for (int e = tid; e < nn; e += kPrepThreads) T[e] = 0;
+    // The int32 walk's shift c = -(least chunk energy of the split): every
+    // E_sd(s, x_p) = E_s(s) + sum_v x_v M[v][s] is at least E_s(s) + the
+    // negative M[v][s], so the least is the minimum of that over the 2^B
+    // columns (the host planner's rule, with the same int32 bound).
+    const int A = inst->A, B = inst->B;
+    const bool walked = !inst->direct && status == 0;
+    if (tid == 0) sLo = LLONG_MAX;
+    __syncthreads();
+    if (walked) {
+        long long lo = LLONG_MAX;
+        for (uint32_t c = uint32_t(tid); c < (1u << B); c += kPrepThreads) {
+            int64_t e = 0;
+            for (int t = 0; t < B; t++) {
+                if (!((c >> (B - 1 - t)) & 1u)) continue;
+                for (int u = t; u < B; u++)
+                    if ((c >> (B - 1 - u)) & 1u) e += sTi[(A + t) * n + A + u];
+            }
+            for (int v = 0; v < A; v++) {
+                int64_t m = 0;
+                for (int t = 0; t < B; t++)
+                    if ((c >> (B - 1 - t)) & 1u) m += sTi[v * n + A + t];
+                if (m < 0) e += m;
+            }
+            lo = e < lo ? e : lo;
+        }
+        atomicMin(&sLo, lo);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const int64_t lo = walked ? int64_t(sLo) : 0;
+        inst->pack_shift = sum + (lo < 0 ? -lo : lo) <= kExactSumLimit ? int32_t(-lo) : 0;
+    }
     if (tid == 0) {
         PrepOut o;
         o.status = status;
@@ -493,11 +530,11 @@ __global__ __launch_bounds__(kFinishThreads) void finish_kernel(const Inst *__re
 // ---------------------------------------------------------------- launchers
 
 hipError_t launch_prepare(const void *dQ, int n, int is_fp32, int32_t *d_T, PrepOut *d_prep,
-                          hipStream_t stream)
+                          Inst *d_inst, hipStream_t stream)
 {
     if (n < 1 || n > kMaxVars) return hipErrorInvalidValue;
     hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(kPrepThreads), 0, stream, dQ, n, is_fp32, d_T,
-                       d_prep);
+                       d_prep, d_inst);
     return hipGetLastError();
 }
 

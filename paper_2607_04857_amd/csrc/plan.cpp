@@ -177,6 +177,13 @@ void chunk_energy_range(const Plan &P, int A, int64_t *lo, int64_t *hi)
     *hi = h;
 }
 
+int32_t nonneg_shift(const Plan &P, int A)
+{
+    int64_t lo = 0, hi = 0;
+    chunk_energy_range(P, A, &lo, &hi);
+    return P.sum_abs + (lo < 0 ? -lo : lo) <= kIntSumLimit ? int32_t(-lo) : 0;
+}
+
 bool packed_shift(const Plan &P, int A, int32_t *shift)
 {
     // every chunk energy lies in [-S, S] for S the suffix-column sum: no shift
@@ -385,6 +392,8 @@ static qubo_status_t plan_walk(const qubo_options_t *opt, Plan &P, std::string *
             P.A = Ap;
             P.tier = 4;
             P.pack_shift = shift;
+        } else if (!P.T.empty()) {
+            P.pack_shift = nonneg_shift(P, P.A);
         }
     }
 

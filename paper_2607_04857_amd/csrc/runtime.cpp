@@ -255,7 +255,7 @@ qubo_status_t job_bind(Job *job, void *d_mem)
         I.direct = P.direct ? 1 : 0;
         I.kslot = int(i);
         I.packed = (P.tier == 4 || P.tier == 5) ? 1 : 0;
-        I.pack_shift = I.packed ? P.pack_shift : 0;
+        I.pack_shift = P.direct ? 0 : P.pack_shift;   // device-prepared: set by prepare_kernel
         I.item_begin = group_base[i];
         I.item_end = group_base[i] + (P.direct ? 0 : P.walk_items());
         item += P.direct ? 0 : P.walk_items();
@@ -318,7 +318,7 @@ qubo_status_t job_enqueue_kernels(const Job &job, hipStream_t stream, hipEvent_t
     const int ni = int(job.plans.size());
     if (job.dq)
         QRT_HIP(qk::launch_prepare(job.dq, job.plans[0].n, job.plans[0].dtype == QUBO_FP32 ? 1 : 0,
-                                   job.d_T0, job.d_prep, stream),
+                                   job.d_T0, job.d_prep, job.d_insts, stream),
                 "prepare kernel");
     QRT_HIP(qk::launch_tables(job.d_insts, ni, job.max_A, job.d_counter, int(job.groups.size()),
                               stream),
@@ -659,7 +659,7 @@ qubo_status_t qubo_plan_info(const void *Q, int n, qubo_dtype_t dtype, const qub
         info->eps_q = P.eps_q;
         info->sum_abs_t = P.sum_abs;
         info->items = P.items;
-        info->pack_shift = P.tier >= 4 ? P.pack_shift : 0;
+        info->pack_shift = P.direct ? 0 : P.pack_shift;
         info->reserved = 0;
         if (T_out) std::memcpy(T_out, P.T.data(), P.T.size() * sizeof(int32_t));
         return QUBO_OK;

@@ -291,7 +291,7 @@ __global__ __launch_bounds__(256) void topk_rescan_kernel(const Inst *__restrict
         }
     } else {
         for (uint32_t s = threadIdx.x; s < NS; s += blockDim.x) {
-            int32_t e = Ep + I.EB[s];
+            int32_t e = Ep - I.pack_shift + I.EB[s];   // E_s carries the walk's shift
             for (int v = 0; v < A; v++)
                 if ((row >> (A - 1 - v)) & 1) e += I.M[uint32_t(v) * NS + s];
             offer(e, s);

@@ -448,9 +448,10 @@ __global__ __launch_bounds__(kWave, (walk_waves_per_simd<MC, G, LR>())) void wal
         // E_nl = energy of the non-low prefix bits = (sum_set F_w + T_ww) / 2
         const bool lbit = lane <= A - 1 - kLowLevels && ((row0 >> (A - 1 - lane)) & 1);
         int32_t Enl = int32_t(wave_sum64(lbit ? int64_t(F) + diagl : 0) / 2);
-        // packed: the chunk energies carry the instance's shift c, the
-        // prefix energy the opposite one, so every sum is the true energy
-        if constexpr (PK) Enl -= insts[cur].pack_shift;
+        // the chunk energies carry the instance's shift c (packed: into the
+        // 16-bit range; int32: non-negative), the prefix energy the opposite
+        // one, so every sum is the true energy
+        Enl -= insts[cur].pack_shift;
         Enl = sread(Enl);
         int32_t H[kLowLevels];
         static_for<0, kLowLevels>([&](auto tc) {

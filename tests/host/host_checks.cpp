@@ -108,6 +108,12 @@ static int run_plan()
                     CHECK(P.sum_abs + (c < 0 ? -int64_t(c) : int64_t(c)) <= qplan::kIntSumLimit);
                 } else {
                     CHECK(fp || P.B < 8 || P.A - 1 < qplan::kSuper || !qplan::packed_shift(P, P.A - 1, &c));
+                    // the int32 walk's chunk energies start at 0 (or no shift
+                    // where the int32 bound would not hold it)
+                    int64_t lo = 0, hi = 0;
+                    qplan::chunk_energy_range(P, P.A, &lo, &hi);
+                    const int64_t a = lo < 0 ? -lo : lo;
+                    CHECK(P.pack_shift == (P.sum_abs + a <= qplan::kIntSumLimit ? -lo : 0));
                 }
             }
             if (kind == 2) {   // one more unit of |T| is refused

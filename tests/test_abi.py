@@ -375,3 +375,18 @@ def test_outer_reduction_arguments():
     assert e.value.status == -2
     with pytest.raises(TypeError):
         q.reduce_outer(Q.astype(np.float32), 2, 0)
+
+
+@pytest.mark.parametrize("kind,seed", [("int", 1), ("int", 2), ("fp32", 3)])
+def test_int32_walk_shift_is_least_chunk_energy(kind, seed):
+    """The int32 walk adds c = -(least chunk energy of its split) to every
+    chunk energy, so they start at 0; c from the brute-force range over all
+    2^17 states (the float32 case on its fixed-point image)."""
+    n = 17
+    Q = inputs.uniform_int(n, -5000, 5000, 640 + seed) if kind == "int" \
+        else inputs.normal_fp32(n, 640 + seed)
+    info = q.plan_info(Q, tier=2)
+    assert info["tier"] == 2
+    lo, hi = _chunk_range_brute(info["T"], info["A"])
+    assert info["pack_shift"] == -lo
+    assert info["sum_abs_t"] + abs(lo) <= 2 ** 30 - 1
