@@ -99,10 +99,10 @@ typedef struct {
  * Tier 4 (packed) holds two 16-bit chunk energies in each 32-bit word, so one
  * int32 add moves two states.  It is exact whenever the chunk energies
  * E_sd(s, x_p) of the split, over every prefix x_p and suffix column s, span
- * at most 65536 consecutive values (they are then shifted by a constant c
- * into the signed 16-bit range; the planner proves it from the sum of |T_ij|
- * over the suffix columns j >= A, at most 32767, or from the exact extremes),
- * and sum |T| + |c| <= 2^30 - 1.  It needs int32 input given in host memory,
+ * at most 65536 consecutive values (the planner computes their exact
+ * extremes and shifts them by a constant c into the signed 16-bit range),
+ * and sum |T| + |c| <= 2^30 - 1.  (The int32 walk shifts its chunk energies
+ * too, to start at 0: c is reported in qubo_plan_info_t::pack_shift.)  It needs int32 input given in host memory,
  * n - B >= 6 and B - 7 = log2 of a built words-per-lane count (4, 8 or 16);
  * with k > 1 the packed plan runs the top-k walk as tier 5.
  * The default plan (no override) takes it wherever that holds, one suffix

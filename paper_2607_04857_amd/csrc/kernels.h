@@ -63,9 +63,9 @@ constexpr int kMaxPrefixRows = 60 - 6;   // A = n - B <= 60 - 6
 // 32-bit add of a row word adds m_lo and m_hi to the two halves however the
 // intermediate carries fall, and a word decodes exactly whenever both biased
 // halves lie in [0, 2^16).  The planner proves every chunk energy E_sd + c
-// (c = Inst::pack_shift, a constant per instance) a signed 16-bit value:
-// from the sum of |T_ij| over the suffix columns (at most kPackSumLimit,
-// c = 0) or from the exact extremes of E_sd over all prefixes and columns.
+// (c = Inst::pack_shift, a constant per instance) a signed 16-bit value from
+// the exact extremes of E_sd over all prefixes and columns, and picks c so
+// that the least biased half is 0.
 constexpr int32_t kPackBias = 1 << 15;
 constexpr int64_t kPackSumLimit = (int64_t(1) << 15) - 1;
 

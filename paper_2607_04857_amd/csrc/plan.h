@@ -94,9 +94,8 @@ int64_t suffix_sum_abs(const Plan &P, int A);
 // E_sd of the split at A (P.T set).
 void chunk_energy_range(const Plan &P, int A, int64_t *lo, int64_t *hi);
 
-// Whether the split at A can run the packed tier, and the shift c that
-// centres its chunk energies: every E_sd + c must be a signed 16-bit value
-// (shift 0 when the suffix-column sum is at most kPackSumLimit, else from the
+// Whether the split at A can run the packed tier, and its shift c: every
+// E_sd + c must be a signed 16-bit value, the least one -2^15 (from the
 // exact range), and P.sum_abs + |c| must stay within kIntSumLimit (the
 // prefix energies move by -c).
 bool packed_shift(const Plan &P, int A, int32_t *shift);

@@ -85,13 +85,15 @@ def test_packed_tier_eligibility():
 
 @pytest.mark.parametrize("sign", [1, -1, 0])
 def test_packed_tier_suffix_sum_bound(sign):
-    """Suffix-column sum 32767 plans tier 4 with no shift, whatever the
-    signs (every chunk energy lies in [-32767, 32767])."""
+    """Suffix-column sum 32767 plans tier 4 whatever the signs (every chunk
+    energy lies in [-32767, 32767]); the shift puts the least at -32768."""
     n, B = 22, 11
     Q = inputs.suffix_edge_int(n, n - B, 32767, sign, 30 + sign)
     info = q.plan_info(Q, tier=4)
-    assert (info["tier"], info["A"], info["pack_shift"]) == (4, n - B, 0)
+    assert (info["tier"], info["A"]) == (4, n - B)
     assert _suffix_sum(info["T"], n - B) == 32767
+    if sign == 1:                        # all suffix entries positive: least 0
+        assert info["pack_shift"] == -32768
 
 
 def _suffix_diagonal(n, A, d, seed):
@@ -164,11 +166,8 @@ def test_packed_tier_matches_brute_force_range(R, seed):
         info = q.plan_info(Q, tier=4)
         assert info["A"] == A
         c = info["pack_shift"]
-        if _suffix_sum(T, A) <= 32767:
-            assert c == 0
-        else:
-            assert c == -32768 - lo
-        assert -32768 <= lo + c and hi + c <= 32767
+        assert c == -32768 - lo
+        assert lo + c == -32768 and hi + c <= 32767
     else:
         with pytest.raises(q.QuboError):
             q.plan_info(Q, tier=4)

@@ -92,7 +92,7 @@ def test_packed_shifted_range_edge(q, orc, signs):
 @pytest.mark.parametrize("n,R,seed", [(17, 3000, 601), (24, 1000, 5), (28, 1500, 6)])
 def test_packed_shifted_random(q, orc, n, R, seed):
     """Entries too large for the suffix-sum bound whose exact chunk-energy
-    range still fits 16 bits: packed with a nonzero shift."""
+    range still fits 16 bits (the suffix-column sum does not)."""
     Q = inputs.uniform_int(n, -R, R, seed)
     info = q.plan_info(Q, tier=4)
     assert info["pack_shift"] != 0
@@ -140,7 +140,7 @@ def test_packed_stored_oracle_results(q, name):
     """The stored oracle answers of the U[-100, 100] and U[-1000, 1000]
     instances (the n = 24 one is the small single-instance workload, the
     n = 36 one the mid-size one) in the default plan, which packs them (the
-    U[-1000, 1000] ones with a shift), and in forced tier 4."""
+    U[-1000, 1000] ones through the exact range), and in forced tier 4."""
     e = _golden()[name]
     Q = getattr(inputs, e["generator"])(**e["kwargs"])
     for kw in ({}, {"tier": 4}):
@@ -235,8 +235,9 @@ def test_packed_in_batch(q, orc):
 
 
 def test_packed_in_server(q, orc):
-    """Served requests with entries to 100 (packed, no shift), to 1000
-    (packed with a shift) and to 10^4 (int32 walk), submitted together:
+    """Served requests with entries to 100 (packed by the suffix-column sum),
+    to 1000 (packed through the exact range) and to 10^4 (int32 walk),
+    submitted together:
     each result equals its lone solve and, for n <= 24, the oracle."""
     Qs, lims = [], []
     for i, n in enumerate([17, 20, 22, 24, 26, 28, 30, 21, 23]):
@@ -258,14 +259,15 @@ def test_packed_in_server(q, orc):
             assert r.tier != 4
         tiers.append((lim, r.tier))
     srv.close()
-    assert (1000, 4) in tiers            # a request packed with a shift
+    assert (1000, 4) in tiers            # packed through the exact range
 
 
 @pytest.mark.parametrize("n,k,R", [(17, 2, 100), (18, 64, 100), (20, 1024, 100), (22, 300, 1000),
                                    (24, 1024, 1000), (26, 512, 100)])
 def test_packed_topk(q, orc, n, k, R):
     """Top-k on the packed layout (tier 5): the whole list equals the
-    oracle's k smallest (E, index) pairs; R = 1000 packs with a shift."""
+    oracle's k smallest (E, index) pairs; R = 1000 packs through the exact
+    range."""
     Q = inputs.uniform_int(n, -R, R, 1500 + n)
     res, pairs = q.solve(Q, k=k)
     ref = orc.solve(Q, k=k)
