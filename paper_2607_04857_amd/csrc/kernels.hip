@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void tables_kernel(const Inst *__restrict__ in
 // finite, S = sum |T| in float64 accumulated i ascending then j ascending
 // (the host's order, so the same S), p = the largest exponent with
 // S 2^p <= 2^29, T~ = round-half-even(T 2^p).
-constexpr int kPrepThreads = 256;
+constexpr int kPrepThreads = 1024;
 
 __device__ __forceinline__ int prep_scale_exponent(double S)
 {
@@ -251,6 +251,7 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(const void *__res
 {
     __shared__ double sTd[kMaxVars * kMaxVars];   // folded float32 input in float64
     __shared__ int32_t sTi[kMaxVars * kMaxVars];  // the int32 T written to T
+    __shared__ int32_t sPart[kMaxPrefixRows][64]; // M_int partial sums (see below)
     __shared__ long long sLo;
     __shared__ unsigned long long sSum;
     __shared__ int sNnz, sBad;
@@ -337,6 +338,22 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(const void *__res
     const bool walked = !inst->direct && status == 0;
     if (tid == 0) sLo = LLONG_MAX;
     __syncthreads();
+    // M[v][s] as the table build forms it: the partial sums over the five
+    // lowest bits of s and over the others (B <= 10 here: 32 + 32 entries)
+    if (walked)
+        for (int e = tid; e < A * 64; e += kPrepThreads) {
+            const int v = e / 64, x = e % 64;
+            int32_t acc = 0;
+            if (x < 32) {
+                for (int u = 0; u < 5 && u < B; u++)
+                    if ((x >> u) & 1) acc += sTi[v * n + A + B - 1 - u];
+            } else {
+                for (int u = 0; u < B - 5; u++)
+                    if (((x - 32) >> u) & 1) acc += sTi[v * n + A + B - 6 - u];
+            }
+            sPart[v][x] = acc;
+        }
+    __syncthreads();
     if (walked) {
         long long lo = LLONG_MAX;
         for (uint32_t c = uint32_t(tid); c < (1u << B); c += kPrepThreads) {
@@ -347,9 +364,7 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(const void *__res
                     if ((c >> (B - 1 - u)) & 1u) e += sTi[(A + t) * n + A + u];
             }
             for (int v = 0; v < A; v++) {
-                int64_t m = 0;
-                for (int t = 0; t < B; t++)
-                    if ((c >> (B - 1 - t)) & 1u) m += sTi[v * n + A + t];
+                const int32_t m = sPart[v][c & 31u] + sPart[v][32u + (c >> 5)];
                 if (m < 0) e += m;
             }
             lo = e < lo ? e : lo;
