@@ -200,7 +200,7 @@ def test_unknown_scope_in_cache_rejected(q, tmp_path):
 
 
 def test_shipped_cache_loads_whole(q):
-    """The tuning cache shipped with the package is valid for this build: every
+    """The tuning cache shipped with the package is valid for this library: every
     entry passes the planner's checks (a stale entry would make the library
     reject the whole file and fall back to the built-in plans), both scopes
     and both dtypes are present, and an entry drives the plan it names."""
