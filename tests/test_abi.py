@@ -389,3 +389,15 @@ def test_int32_walk_shift_is_least_chunk_energy(kind, seed):
     lo, hi = _chunk_range_brute(info["T"], info["A"])
     assert info["pack_shift"] == -lo
     assert info["sum_abs_t"] + abs(lo) <= 2 ** 30 - 1
+
+
+def test_int32_walk_shift_respects_the_exactness_bound():
+    """At sum |T| = 2^30 - 1 no shift fits the int32 bound: c = 0.  Well
+    inside it, c = -(least chunk energy), within the bound."""
+    n = 17
+    edge = q.plan_info(inputs.edge_int(n, 2 ** 30 - 1, 5), tier=2)
+    assert edge["sum_abs_t"] == 2 ** 30 - 1 and edge["pack_shift"] == 0
+    half = q.plan_info(inputs.edge_int(n, 2 ** 28, 5), tier=2)
+    lo, _ = _chunk_range_brute(half["T"], half["A"])
+    assert lo < 0 and half["pack_shift"] == -lo
+    assert half["sum_abs_t"] - lo <= 2 ** 30 - 1
