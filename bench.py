@@ -311,6 +311,9 @@ def main():
     ap.add_argument("--no-packed", action="store_true")
     ap.add_argument("--only-packed", action="store_true",
                     help="only the packed n=44 lone solves (profiling the packed walk alone)")
+    ap.add_argument("--only-topk", action="store_true",
+                    help="only the n=40 top-k instance: two k=1024 solves, then two k=1 solves "
+                         "(profiling the top-k walk against the k=1 walk)")
     ap.add_argument("--skip-single", action="store_true",
                     help="skip the n=44 solves (profiling the batched or served kernels alone)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -355,6 +358,15 @@ def main():
 
     if args.only_packed:
         print(json.dumps({"single_packed": single_packed(q)}), flush=True)
+        return
+    if args.only_topk:
+        T = inputs.uniform_int(40, -10000, 10000, 3)
+        out = []
+        for k in (1024, 1024, 1, 1):
+            r = q.solve(T, k=k)
+            r = r[0] if k > 1 else r
+            out.append({"k": k, "tier": r.tier, "walk_ms": r.kernel_ms})
+        print(json.dumps({"topk_profile": out}), flush=True)
         return
     if args.skip_single:
         out = {}
